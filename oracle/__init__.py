@@ -1,0 +1,170 @@
+"""FP64 CPU oracle for the exact LOO log-likelihood, its bandwidth gradient
+and density queries of the double-kernel conditional density estimator.
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the
+benchmark's CPU-baseline leg are the only callers.  The product library
+(``paper_1206_5278_amd``) never imports this package, and this package never
+imports the product library.
+
+The arithmetic lives in ``cde_oracle.c`` (plain C, double precision, no
+blocking or factorisation); this module only marshals numpy arrays.
+Definitions followed (Holmes, Gray & Isbell): Section 2 (scaled kernel,
+eq. 1), Section 3 eq. (3) and the A_i expansion of Section 3.2.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cde_oracle.c")
+_LIB = os.path.join(_HERE, "libcde_oracle.so")
+
+COND = 0
+JOINT = 1
+_CRIT = {"cond": COND, "conditional": COND, "joint": JOINT, COND: COND, JOINT: JOINT}
+
+_lib = None
+
+
+def build(src: str = _SRC, out: str = _LIB) -> str:
+    """Compile the oracle with gcc (IEEE double arithmetic, no contraction)."""
+    tmp = out + ".tmp"
+    subprocess.run(
+        ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+         "-shared", "-pthread", src, "-o", tmp, "-lm"],
+        check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def load_library(path: str):
+    """Open a compiled oracle library and declare its C signatures."""
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lp = ctypes.POINTER(ctypes.c_long)
+    lib.oracle_loo.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, dp,
+                               ctypes.c_int, lp, ctypes.c_long, dp, dp, ctypes.c_int]
+    lib.oracle_loo.restype = ctypes.c_int
+    lib.oracle_loo_grid.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, ctypes.c_int,
+                                    dp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
+                                    lp, ctypes.c_long, dp, ctypes.c_int]
+    lib.oracle_loo_grid.restype = ctypes.c_int
+    lib.oracle_sum.argtypes = [dp, ctypes.c_long]
+    lib.oracle_sum.restype = ctypes.c_double
+    lib.oracle_density.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, dp,
+                                   dp, ctypes.c_long, dp, ctypes.c_long, dp, ctypes.c_int]
+    lib.oracle_density.restype = ctypes.c_int
+    return lib
+
+
+def _load(lib=None):
+    global _lib
+    if lib is not None:
+        return lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = load_library(_LIB)
+    return _lib
+
+
+def _f64(a, ndim=2):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if ndim == 2 and a.ndim == 1:
+        a = a.reshape(-1, 1)
+    return a
+
+
+def _ptr(a, t=ctypes.c_double):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def _bw(h, dx, dy):
+    h = np.asarray(h, dtype=np.float64).ravel()
+    if h.size == 2 and dx + dy != 2:
+        h = np.concatenate([np.full(dx, h[0]), np.full(dy, h[1])])
+    if h.size != dx + dy:
+        raise ValueError(f"bandwidth vector must have dx+dy={dx + dy} entries")
+    return np.ascontiguousarray(h)
+
+
+def _idx(idx, n):
+    if idx is None:
+        return None, n
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).ravel())
+    return idx, idx.size
+
+
+def loo(x, y, h, criterion="cond", idx=None, grad=False, nthreads=1, lib=None):
+    """Per-point LOO log-likelihood l_i for one diagonal bandwidth setting.
+
+    x: [n, dx], y: [n, dy] (promoted exactly to float64); h: [dx+dy]
+    (hx..., hy...) or a pair (hx, hy) broadcast over dimensions.
+    idx: optional points i to evaluate (each against all j != i).
+    Returns ell [m] and, if grad, dell [m, dx+dy] = d l_i / d h."""
+    lib = _load(lib)
+    x, y = _f64(x), _f64(y)
+    n, dx = x.shape
+    dy = y.shape[1]
+    h = _bw(h, dx, dy)
+    idx_a, m = _idx(idx, n)
+    ell = np.empty(m)
+    dell = np.empty((m, dx + dy)) if grad else None
+    s = lib.oracle_loo(_ptr(x), _ptr(y), n, dx, dy, _ptr(h), _CRIT[criterion],
+                       None if idx_a is None else _ptr(idx_a, ctypes.c_long), m,
+                       _ptr(ell), None if dell is None else _ptr(dell), int(nthreads))
+    if s:
+        raise ValueError(f"oracle_loo failed with status {s}")
+    return (ell, dell) if grad else ell
+
+
+def loo_grid(x, y, hx, hy, criterion="cond", idx=None, nthreads=1, lib=None):
+    """Scalar-bandwidth grid, hx-major: returns ell [len(hx)*len(hy), m]."""
+    lib = _load(lib)
+    x, y = _f64(x), _f64(y)
+    n, dx = x.shape
+    dy = y.shape[1]
+    hx = np.ascontiguousarray(np.asarray(hx, dtype=np.float64).ravel())
+    hy = np.ascontiguousarray(np.asarray(hy, dtype=np.float64).ravel())
+    idx_a, m = _idx(idx, n)
+    ell = np.empty((hx.size * hy.size, m))
+    s = lib.oracle_loo_grid(_ptr(x), _ptr(y), n, dx, dy, _ptr(hx), hx.size, _ptr(hy),
+                            hy.size, _CRIT[criterion],
+                            None if idx_a is None else _ptr(idx_a, ctypes.c_long), m,
+                            _ptr(ell), int(nthreads))
+    if s:
+        raise ValueError(f"oracle_loo_grid failed with status {s}")
+    return ell
+
+
+def total(v) -> float:
+    """Index-order Neumaier-compensated sum of a 1-D float64 array."""
+    v = np.ascontiguousarray(np.asarray(v, dtype=np.float64).ravel())
+    return float(_load().oracle_sum(_ptr(v), v.size))
+
+
+def totals(ell2d):
+    """Row-wise ``total`` of a [G, m] array."""
+    return np.array([total(r) for r in np.asarray(ell2d)])
+
+
+def density(x, y, h, xq, yg, nthreads=1, lib=None):
+    """f(yg[g] | xq[q]) over all training points (eq. 1): returns [q, k]."""
+    lib = _load(lib)
+    x, y = _f64(x), _f64(y)
+    n, dx = x.shape
+    dy = y.shape[1]
+    h = _bw(h, dx, dy)
+    xq = _f64(xq).reshape(-1, dx)
+    yg = _f64(yg).reshape(-1, dy)
+    q, k = xq.shape[0], yg.shape[0]
+    f = np.empty((q, k))
+    s = lib.oracle_density(_ptr(x), _ptr(y), n, dx, dy, _ptr(h), _ptr(xq), q, _ptr(yg), k,
+                           _ptr(f), int(nthreads))
+    if s:
+        raise ValueError(f"oracle_density failed with status {s}")
+    return f

@@ -1,0 +1,373 @@
+/*
+ * cde_oracle.c -- plain FP64 CPU oracle for the exact leave-one-out (LOO)
+ * cross-validated log-likelihood of the double-kernel (Nadaraya-Watson)
+ * conditional density estimator, its bandwidth gradient, and density queries.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the HIP library and is never a product path.
+ *
+ * Source: Holmes, Gray & Isbell, "Fast Nonparametric Conditional Density
+ * Estimation".
+ *   - Section 2: the scaled kernel K_h(t) = h^{-d} K(t/h); K here is the
+ *     Gaussian, applied as a product over dimensions with one bandwidth per
+ *     dimension (a scalar bandwidth is the same value in every dimension).
+ *   - Section 2, eq. (1): f(y|x) = sum_i K_hy(y-y_i) K_hx(x-x_i) /
+ *     sum_i K_hx(x-x_i).  (The paper's h1 is the y-bandwidth and h2 the
+ *     x-bandwidth; this file writes hx and hy.)
+ *   - Section 3, eq. (3) and its expansion in Section 3.2: for each point i,
+ *     num_i = sum_{j!=i} K_hx(x_i-x_j) K_hy(y_i-y_j)  (the paper's A_i) and
+ *     den_i = sum_{j!=i} K_hx(x_i-x_j).
+ *       CONDITIONAL: l_i = log(num_i / den_i)  = log f^{-i}(y_i|x_i)
+ *       JOINT      : l_i = log(num_i / (n-1)) = log f^{-i}(y_i|x_i) f^{-i}(x_i)
+ *     and L = (1/n) sum_i l_i for JOINT is eq. (3).
+ *
+ * Evaluation (plain definition, no blocking, no factorisation): for each i,
+ * in index order, form the Gaussian exponents a_j = -1/2 sum_k (dx_k/hx_k)^2
+ * and b_j = -1/2 sum_l (dy_l/hy_l)^2 for every j != i, take the maxima
+ * Mx = max_j a_j and Mxy = max_j (a_j + b_j), and sum the shifted
+ * exponentials D = sum_j exp(a_j - Mx), U = sum_j exp(a_j + b_j - Mxy) in j
+ * order (log-sum-exp: the common factor cancels in each ratio, so the value
+ * is the plain definition without overflow or underflow).  Then
+ *   CONDITIONAL: l_i = log c_y + (Mxy + log U) - (Mx + log D)
+ *   JOINT      : l_i = log c_x + log c_y + Mxy + log U - log(n-1)
+ * with log c_x = -sum_k (log hx_k + log(2 pi)/2) and likewise log c_y.
+ *
+ * Gradient with respect to the per-dimension bandwidths (differentiating
+ * the Gaussian kernels of Section 2 under the ratio of eq. (1)):
+ *   d l_i / d hx_k = (Mv_k/U - Mw_k/D) / hx_k^3           (CONDITIONAL)
+ *                  = (Mv_k/U) / hx_k^3 - 1/hx_k           (JOINT)
+ *   d l_i / d hy_l = (Mvy_l/U) / hy_l^3 - 1/hy_l          (both)
+ * where Mw_k = sum_j exp(a_j-Mx) dx_k^2, Mv_k = sum_j exp(a_j+b_j-Mxy) dx_k^2
+ * and Mvy_l = sum_j exp(a_j+b_j-Mxy) dy_l^2.
+ *
+ * Threads: points i are split into contiguous ranges, one per thread; each
+ * l_i is computed by exactly the same code whatever the split, so results are
+ * bitwise independent of the thread count.  Totals are formed by the caller
+ * with oracle_sum (index order, Neumaier-compensated).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_COND 0
+#define ORACLE_JOINT 1
+
+static const double HALF_LOG_2PI = 0.91893853320467274178032973640562;
+
+typedef struct {
+    const double* x;     /* [n][dx] */
+    const double* y;     /* [n][dy] */
+    long n;
+    int dx, dy;
+    const double* h;     /* [dx+dy]: hx..., hy... */
+    int criterion;
+    const long* idx;     /* points to evaluate, or NULL for 0..m-1 */
+    long m;
+    double* ell;         /* [m] */
+    double* dell;        /* [m][dx+dy] or NULL */
+    long lo, hi;         /* this worker's range of [0, m) */
+    int status;
+} loo_job;
+
+static double log_norm(const double* h, int d)
+{
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) s -= log(h[k]) + HALF_LOG_2PI;
+    return s;
+}
+
+/* One point i: fills *ell and, if grad != NULL, grad[0..dx+dy). */
+static int loo_point(const loo_job* J, long i, double* a, double* ab,
+                     double* ell, double* grad)
+{
+    const long n = J->n;
+    const int dx = J->dx, dy = J->dy;
+    const double* hx = J->h;
+    const double* hy = J->h + dx;
+    const double* xi = J->x + (size_t)i * dx;
+    const double* yi = J->y + (size_t)i * dy;
+    double Mx = -INFINITY, Mxy = -INFINITY;
+
+    for (long j = 0; j < n; ++j) {
+        if (j == i) continue;           /* leave point i out (eq. 3) */
+        const double* xj = J->x + (size_t)j * dx;
+        const double* yj = J->y + (size_t)j * dy;
+        double sx = 0.0, sy = 0.0;
+        for (int k = 0; k < dx; ++k) {
+            double t = (xi[k] - xj[k]) / hx[k];
+            sx += t * t;
+        }
+        for (int l = 0; l < dy; ++l) {
+            double t = (yi[l] - yj[l]) / hy[l];
+            sy += t * t;
+        }
+        a[j] = -0.5 * sx;
+        ab[j] = -0.5 * sx - 0.5 * sy;
+        if (a[j] > Mx) Mx = a[j];
+        if (ab[j] > Mxy) Mxy = ab[j];
+    }
+
+    /* a[j] and ab[j] now become the shifted weights exp(a_j - Mx) and
+     * exp(a_j + b_j - Mxy); D and U are their sums in j order. */
+    double D = 0.0, U = 0.0;
+    for (long j = 0; j < n; ++j) {
+        if (j == i) continue;
+        a[j] = exp(a[j] - Mx);
+        ab[j] = exp(ab[j] - Mxy);
+        D += a[j];
+        U += ab[j];
+    }
+
+    const double lcx = log_norm(hx, dx);
+    const double lcy = log_norm(hy, dy);
+    if (J->criterion == ORACLE_JOINT)
+        *ell = lcx + lcy + Mxy + log(U) - log((double)(n - 1));
+    else
+        *ell = lcy + (Mxy + log(U)) - (Mx + log(D));
+
+    if (grad) {
+        for (int k = 0; k < dx; ++k) {
+            double mw = 0.0, mv = 0.0;
+            for (long j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double d = xi[k] - J->x[(size_t)j * dx + k];
+                mw += a[j] * d * d;
+                mv += ab[j] * d * d;
+            }
+            double h3 = hx[k] * hx[k] * hx[k];
+            if (J->criterion == ORACLE_JOINT)
+                grad[k] = (mv / U) / h3 - 1.0 / hx[k];
+            else
+                grad[k] = (mv / U - mw / D) / h3;
+        }
+        for (int l = 0; l < dy; ++l) {
+            double mvy = 0.0;
+            for (long j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double d = yi[l] - J->y[(size_t)j * dy + l];
+                mvy += ab[j] * d * d;
+            }
+            double h3 = hy[l] * hy[l] * hy[l];
+            grad[dx + l] = (mvy / U) / h3 - 1.0 / hy[l];
+        }
+    }
+    return 0;
+}
+
+static void* loo_worker(void* arg)
+{
+    loo_job* J = (loo_job*)arg;
+    double* a = (double*)malloc(sizeof(double) * (size_t)J->n);
+    double* ab = (double*)malloc(sizeof(double) * (size_t)J->n);
+    if (!a || !ab) {
+        free(a);
+        free(ab);
+        J->status = 2;
+        return NULL;
+    }
+    const int p = J->dx + J->dy;
+    for (long t = J->lo; t < J->hi; ++t) {
+        long i = J->idx ? J->idx[t] : t;
+        loo_point(J, i, a, ab, &J->ell[t], J->dell ? J->dell + (size_t)t * p : NULL);
+    }
+    free(a);
+    free(ab);
+    J->status = 0;
+    return NULL;
+}
+
+static int check_args(const double* x, const double* y, long n, int dx, int dy,
+                      const double* h)
+{
+    if (!x || !y || !h || n < 2 || dx < 1 || dy < 1) return 1;
+    for (int k = 0; k < dx + dy; ++k)
+        if (!(h[k] > 0.0) || !isfinite(h[k])) return 1;
+    return 0;
+}
+
+static int run_jobs(loo_job* base, long m, int nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > m) nthreads = (int)(m > 0 ? m : 1);
+    loo_job* jobs = (loo_job*)calloc((size_t)nthreads, sizeof(loo_job));
+    pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!jobs || !th) {
+        free(jobs);
+        free(th);
+        return 2;
+    }
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = *base;
+        jobs[t].lo = m * t / nthreads;
+        jobs[t].hi = m * (t + 1) / nthreads;
+        jobs[t].status = 0;
+    }
+    int status = 0;
+    if (nthreads == 1) {
+        loo_worker(&jobs[0]);
+        status = jobs[0].status;
+    } else {
+        for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, loo_worker, &jobs[t]);
+        for (int t = 0; t < nthreads; ++t) {
+            pthread_join(th[t], NULL);
+            if (jobs[t].status) status = jobs[t].status;
+        }
+    }
+    free(jobs);
+    free(th);
+    return status;
+}
+
+/* Per-point LOO log-likelihood (and optionally its bandwidth gradient) for
+ * one diagonal bandwidth setting h[dx+dy].  idx selects the points i that are
+ * evaluated (each against all j != i); idx == NULL means i = 0..m-1 (m == n).
+ * Returns 0 on success, 1 on invalid arguments, 2 on allocation failure. */
+int oracle_loo(const double* x, const double* y, long n, int dx, int dy,
+               const double* h, int criterion, const long* idx, long m,
+               double* ell, double* dell, int nthreads)
+{
+    if (check_args(x, y, n, dx, dy, h) || !ell || m < 0) return 1;
+    if (!idx && m != n) return 1;
+    if (idx)
+        for (long t = 0; t < m; ++t)
+            if (idx[t] < 0 || idx[t] >= n) return 1;
+    loo_job J;
+    memset(&J, 0, sizeof J);
+    J.x = x; J.y = y; J.n = n; J.dx = dx; J.dy = dy; J.h = h;
+    J.criterion = criterion; J.idx = idx; J.m = m; J.ell = ell; J.dell = dell;
+    return run_jobs(&J, m, nthreads);
+}
+
+/* Scalar bandwidth grid, evaluated directly setting by setting: for every
+ * (a, b) the exponent of each pair is formed from hx[a] and hy[b] and
+ * exponentiated as a whole (no factorisation of the two kernels).  Output is
+ * hx-major: ell[(a*nhy + b)*m + t]. */
+int oracle_loo_grid(const double* x, const double* y, long n, int dx, int dy,
+                    const double* hx, int nhx, const double* hy, int nhy,
+                    int criterion, const long* idx, long m, double* ell,
+                    int nthreads)
+{
+    if (!hx || !hy || nhx < 1 || nhy < 1 || dx + dy > 256) return 1;
+    double h[256];
+    for (int a = 0; a < nhx; ++a) {
+        for (int b = 0; b < nhy; ++b) {
+            for (int k = 0; k < dx; ++k) h[k] = hx[a];
+            for (int l = 0; l < dy; ++l) h[dx + l] = hy[b];
+            int s = oracle_loo(x, y, n, dx, dy, h, criterion, idx, m,
+                               ell + ((size_t)a * nhy + b) * (size_t)m, NULL, nthreads);
+            if (s) return s;
+        }
+    }
+    return 0;
+}
+
+/* Sum in index order with Neumaier's compensation. */
+double oracle_sum(const double* v, long m)
+{
+    double s = 0.0, c = 0.0;
+    for (long t = 0; t < m; ++t) {
+        double u = s + v[t];
+        if (fabs(s) >= fabs(v[t]))
+            c += (s - u) + v[t];
+        else
+            c += (v[t] - u) + s;
+        s = u;
+    }
+    return s + c;
+}
+
+typedef struct {
+    const double *x, *y, *h, *xq, *yg;
+    long n, q, k;
+    int dx, dy;
+    double* f;
+    long lo, hi;
+    int status;
+} dens_job;
+
+static void* dens_worker(void* arg)
+{
+    dens_job* J = (dens_job*)arg;
+    const long n = J->n;
+    const int dx = J->dx, dy = J->dy;
+    const double* hx = J->h;
+    const double* hy = J->h + dx;
+    double* a = (double*)malloc(sizeof(double) * (size_t)n);
+    double* ab = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!a || !ab) {
+        free(a);
+        free(ab);
+        J->status = 2;
+        return NULL;
+    }
+    const double lcy = log_norm(hy, dy);
+    for (long qq = J->lo; qq < J->hi; ++qq) {
+        const double* xq = J->xq + (size_t)qq * dx;
+        double Mx = -INFINITY;
+        for (long i = 0; i < n; ++i) {
+            double sx = 0.0;
+            for (int k = 0; k < dx; ++k) {
+                double t = (xq[k] - J->x[(size_t)i * dx + k]) / hx[k];
+                sx += t * t;
+            }
+            a[i] = -0.5 * sx;
+            if (a[i] > Mx) Mx = a[i];
+        }
+        double D = 0.0;
+        for (long i = 0; i < n; ++i) D += exp(a[i] - Mx);
+        for (long g = 0; g < J->k; ++g) {
+            const double* yg = J->yg + (size_t)g * dy;
+            double Mxy = -INFINITY;
+            for (long i = 0; i < n; ++i) {
+                double sy = 0.0;
+                for (int l = 0; l < dy; ++l) {
+                    double t = (yg[l] - J->y[(size_t)i * dy + l]) / hy[l];
+                    sy += t * t;
+                }
+                ab[i] = a[i] - 0.5 * sy;
+                if (ab[i] > Mxy) Mxy = ab[i];
+            }
+            double U = 0.0;
+            for (long i = 0; i < n; ++i) U += exp(ab[i] - Mxy);
+            J->f[(size_t)qq * J->k + g] = exp(lcy + (Mxy + log(U)) - (Mx + log(D)));
+        }
+    }
+    free(a);
+    free(ab);
+    J->status = 0;
+    return NULL;
+}
+
+/* Density queries, eq. (1) over all n training points (no point left out):
+ * f[qq][g] = f(yg[g] | xq[qq]) for q query x's and k y values. */
+int oracle_density(const double* x, const double* y, long n, int dx, int dy,
+                   const double* h, const double* xq, long q, const double* yg,
+                   long k, double* f, int nthreads)
+{
+    if (check_args(x, y, n, dx, dy, h) || !xq || !yg || !f || q < 0 || k < 0) return 1;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > q) nthreads = (int)(q > 0 ? q : 1);
+    dens_job* jobs = (dens_job*)calloc((size_t)nthreads, sizeof(dens_job));
+    pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!jobs || !th) {
+        free(jobs);
+        free(th);
+        return 2;
+    }
+    for (int t = 0; t < nthreads; ++t) {
+        dens_job J = {x, y, h, xq, yg, n, q, k, dx, dy, f, q * t / nthreads,
+                      q * (t + 1) / nthreads, 0};
+        jobs[t] = J;
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, dens_worker, &jobs[t]);
+    int status = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        pthread_join(th[t], NULL);
+        if (jobs[t].status) status = jobs[t].status;
+    }
+    free(jobs);
+    free(th);
+    return status;
+}

@@ -1,0 +1,97 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake (a dropped term, a wrong sign, index or stride,
+a missing constant) in a temporary copy of the oracle's C source, builds it,
+and checks that the compact battery of independent pins below rejects it.
+Everything runs on the CPU; the committed oracle is never modified.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.stats import norm
+
+import oracle
+from tests import brute
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "cde_oracle.c")
+
+MUTATIONS = {
+    "self_pair_included": ("if (j == i) continue;", ""),
+    "wrong_sign_y_exponent": ("ab[j] = -0.5 * sx - 0.5 * sy;", "ab[j] = -0.5 * sx + 0.5 * sy;"),
+    "missing_2pi_constant": ("s -= log(h[k]) + HALF_LOG_2PI;", "s -= log(h[k]);"),
+    "y_scaled_by_hx": ("double t = (yi[l] - yj[l]) / hy[l];", "double t = (yi[l] - yj[l]) / hx[l];"),
+    "wrong_x_stride": ("const double* xj = J->x + (size_t)j * dx;",
+                       "const double* xj = J->x + (size_t)j * dy;"),
+    "grad_sign": ("grad[k] = (mv / U - mw / D) / h3;", "grad[k] = (mv / U + mw / D) / h3;"),
+    "grad_missing_norm_term": ("grad[dx + l] = (mvy / U) / h3 - 1.0 / hy[l];",
+                               "grad[dx + l] = (mvy / U) / h3;"),
+    "joint_wrong_count": ("- log((double)(n - 1));", "- log((double)n);"),
+    "density_missing_cy": ("exp(lcy + (Mxy + log(U)) - (Mx + log(D)))",
+                           "exp((Mxy + log(U)) - (Mx + log(D)))"),
+    "density_den_shift_dropped": ("J->f[(size_t)qq * J->k + g] = exp(lcy + (Mxy + log(U)) - (Mx + log(D)));",
+                                  "J->f[(size_t)qq * J->k + g] = exp(lcy + (Mxy + log(U)) - log(D));"),
+}
+
+
+def battery(lib) -> list:
+    """Independent checks; returns the names of those that fail."""
+    failed = []
+    rng = np.random.default_rng(5)
+    n, dx, dy = 7, 2, 1
+    x = rng.normal(0, 2, size=(n, dx))
+    y = rng.normal(0, 1, size=(n, dy))
+    hx, hy = np.array([0.7, 1.2]), np.array([0.5])
+    h = np.concatenate([hx, hy])
+    for crit in ("cond", "joint"):
+        got = oracle.loo(x, y, h, crit, lib=lib)
+        ref = np.array([float(v) for v in brute.ell(x, y, hx, hy, crit)])
+        if not np.allclose(got, ref, rtol=1e-12, atol=1e-12):
+            failed.append(f"brute_{crit}")
+    # gradient: central differences of the 50-digit brute force
+    _, dell = oracle.loo(x, y, h, "cond", grad=True, lib=lib)
+    g = dell.sum(axis=0)
+    for k in range(3):
+        hp, hm = h.copy(), h.copy()
+        d = 1e-6 * h[k]
+        hp[k] += d
+        hm[k] -= d
+        fd = (sum(float(v) for v in brute.ell(x, y, hp[:2], hp[2:])) -
+              sum(float(v) for v in brute.ell(x, y, hm[:2], hm[2:]))) / (hp[k] - hm[k])
+        if abs(g[k] - fd) > 1e-6 * max(1.0, abs(fd)):
+            failed.append(f"grad_{k}")
+            break
+    # density: integral over y is 1 and matches the brute force
+    xq = rng.normal(0, 1, size=(2, dx))
+    yg = np.linspace(y.min() - 8 * hy[0], y.max() + 8 * hy[0], 2001)
+    f = oracle.density(x, y, h, xq, yg, lib=lib)
+    integ = np.trapezoid(f, yg, axis=1)
+    if not np.allclose(integ, 1.0, atol=1e-6):
+        failed.append("density_integral")
+    ref = float(brute.density(x, y, hx, hy, xq[0], [yg[1000]]))
+    if abs(f[0, 1000] - ref) > 1e-12 * ref:
+        failed.append("density_brute")
+    # hx -> infinity limit (LOO marginal KDE of y)
+    got = oracle.loo(x, y, [1e8, 1e8, hy[0]], lib=lib)
+    ref = [math.log(np.mean(norm.pdf(y[i, 0], loc=np.delete(y[:, 0], i), scale=hy[0])))
+           for i in range(n)]
+    if not np.allclose(got, ref, rtol=1e-12):
+        failed.append("limit_hx_inf")
+    return failed
+
+
+def test_unmutated_oracle_passes_battery():
+    assert battery(None) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert old in src, f"mutation anchor not found: {old!r}"
+    mutated = tmp_path / "mut.c"
+    mutated.write_text(src.replace(old, new))
+    so = oracle.build(str(mutated), str(tmp_path / "libmut.so"))
+    lib = oracle.load_library(so)
+    assert battery(lib), f"mutation {name} was not detected by any pin"
