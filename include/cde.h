@@ -1,0 +1,139 @@
+/*
+ * cde.h -- C ABI of the MI355X (gfx950) library for the exact leave-one-out
+ * (LOO) cross-validated log-likelihood of the double-kernel (Nadaraya-Watson)
+ * conditional density estimator, its bandwidth gradient, and density queries.
+ *
+ * Method: Holmes, Gray & Isbell, "Fast Nonparametric Conditional Density
+ * Estimation".
+ *   - Kernel (Section 2): K_h(t) = h^{-d} K(t/h) with K the Gaussian, used
+ *     here as a product over dimensions with one bandwidth per dimension.
+ *   - Estimator (Section 2, eq. 1): f(y|x) = sum_i K_hy(y-y_i) K_hx(x-x_i) /
+ *     sum_i K_hx(x-x_i).  The paper calls the y-bandwidth h1 and the
+ *     x-bandwidth h2; this header writes hx and hy.
+ *   - Criterion (Section 3, eq. 3 and the A_i expansion of Section 3.2):
+ *     num_i = sum_{j!=i} K_hx(x_i-x_j) K_hy(y_i-y_j), den_i = sum_{j!=i}
+ *     K_hx(x_i-x_j);
+ *       CDE_COND : S = sum_i log(num_i / den_i)      (log f^{-i}(y_i|x_i))
+ *       CDE_JOINT: S = sum_i log(num_i / (n - 1))    (n * L of eq. 3)
+ *     The exact O(n^2) sum is evaluated (the paper's "naive" evaluation in
+ *     Section 3); no pruning or sampling approximation is applied.
+ *
+ * Conventions for every call:
+ *   - Device pointers are HIP device memory (e.g. torch tensors' data_ptr).
+ *     Host pointers (bandwidth arrays) are read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls only enqueue work on `stream`; outputs are valid once the stream
+ *     has passed the call.  A model may be used from several streams only for
+ *     calls whose outputs do not overlap; calls on one stream are ordered.
+ *   - Outputs are caller-owned device buffers.
+ *   - Errors are reported by status code only; no exception crosses the ABI.
+ *     After a non-OK status, cde_last_error() returns a message (per thread).
+ *   - Results are deterministic: fixed reduction orders, no float atomics on
+ *     result paths, so repeated calls give identical bits.
+ */
+#ifndef CDE_H
+#define CDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CDE_ABI_VERSION 1
+
+typedef struct cde_model cde_model; /* opaque handle */
+
+typedef enum {
+    CDE_OK = 0,
+    CDE_EINVAL = 1,       /* bad argument: null pointer, n < 2, h <= 0 or non-finite, ... */
+    CDE_ENOMEM = 2,       /* device allocation failed */
+    CDE_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed */
+    CDE_EUNSUPPORTED = 4  /* valid but outside this build: dx > 64, dy > 4, ... */
+} cde_status;
+
+typedef enum {
+    CDE_F32 = 0, /* FP32 data and kernel values, compensated tile sums, FP64 log and reduce */
+    CDE_F64 = 1  /* FP64 throughout */
+} cde_precision;
+
+typedef enum {
+    CDE_COND = 0, /* sum_i log(num_i / den_i): the conditional LOO log-likelihood */
+    CDE_JOINT = 1 /* sum_i log(num_i / (n-1)): eq. (3) times n */
+} cde_criterion;
+
+typedef enum {
+    CDE_XTERM_AUTO = 0,       /* library choice (VALU differences) */
+    CDE_XTERM_VALU = 1,       /* squared distances from coordinate differences on the VALU */
+    CDE_XTERM_MFMA_BF16X3 = 2 /* dx >= 16: |x_i|^2 + |x_j|^2 - 2 x_i.x_j with the cross term
+                                 from a split-bf16 x3 MFMA product, FP32 accumulate */
+} cde_xterm;
+
+/* ABI version of the loaded library (CDE_ABI_VERSION at build time). */
+int cde_abi_version(void);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char* cde_last_error(void);
+
+/* Create a model from a training set {(x_i, y_i)}, i < n (Section 2 data).
+ *   x_dev: [n][dx] row-major, y_dev: [n][dy] row-major, device memory, of
+ *          float (CDE_F32) or double (CDE_F64).  The values handed in ARE the
+ *          dataset: nothing is re-rounded or re-centred.
+ *   The model copies the data into its own device memory (structure-of-arrays,
+ *   padded to a whole number of 256-point tiles) on `stream`; the caller may
+ *   free x_dev / y_dev once the stream has passed this call.
+ *   Limits: n >= 2, 1 <= dx <= 64, 1 <= dy <= 4, n < 2^31.
+ *   The model owns its device memory until cde_destroy.  */
+cde_status cde_create(cde_model** out, const void* x_dev, const void* y_dev, int64_t n,
+                      int32_t dx, int32_t dy, cde_precision precision, void* stream);
+
+/* Release the model and its device memory (synchronises the device first). */
+cde_status cde_destroy(cde_model* m);
+
+/* Device bytes held by the model (packed data, per-point shifts, scratch). */
+size_t cde_model_device_bytes(const cde_model* m);
+
+/* Exact LOO log-likelihood over a grid of scalar bandwidths (one hx for all
+ * x-dimensions, one hy for all y-dimensions), Section 3 eq. (3).
+ *   hx[n_hx], hy[n_hy]: host arrays, every value finite and > 0.
+ *   totals_dev: [n_hx*n_hy] doubles, hx-major (index a*n_hy + b): S(hx[a], hy[b]).
+ *   per_point_dev: optional [n_hx*n_hy][n] doubles (l_i per setting) or NULL.
+ *   n_nonfinite_dev: optional [1] int64: number of non-finite l_i (0 for
+ *   finite data; a non-finite l_i makes its total non-finite), or NULL.
+ *   xterm: CDE_XTERM_MFMA_BF16X3 is accepted for dx >= 16 only.
+ *   Limits: n_hx, n_hy in [1, 64]. */
+cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const double* hy,
+                          int32_t n_hy, cde_criterion criterion, cde_xterm xterm,
+                          double* totals_dev, double* per_point_dev,
+                          int64_t* n_nonfinite_dev, void* stream);
+
+/* Exact LOO log-likelihood for a list of g diagonal bandwidth settings.
+ *   h: host [g][dx+dy] (hx_1..hx_dx, hy_1..hy_dy per setting).
+ *   totals_dev: [g] doubles; per_point_dev: optional [g][n] doubles or NULL.
+ *   Limits: 1 <= g <= 4096. */
+cde_status cde_loo_loglik_list(cde_model* m, const double* h, int32_t g,
+                               cde_criterion criterion, double* totals_dev,
+                               double* per_point_dev, void* stream);
+
+/* Value and bandwidth gradient for one diagonal setting (adjoint of eq. 3).
+ *   h: host [dx+dy].  total_dev: [1] double S(h).  grad_dev: [dx+dy] doubles,
+ *   dS/dh_k (with respect to the bandwidths themselves, not their logs).
+ *   per_point_dev: optional [n] doubles (l_i) or NULL. */
+cde_status cde_loo_grad(cde_model* m, const double* h, cde_criterion criterion,
+                        double* total_dev, double* grad_dev, double* per_point_dev,
+                        void* stream);
+
+/* Conditional density queries, eq. (1) over all n training points (no point
+ * left out): f_dev[qq][g] = f(ygrid[g] | xq[qq]).
+ *   xq_dev: [q][dx], ygrid_dev: [k][dy], device memory of the model's
+ *   precision type.  h: host [dx+dy].  f_dev: [q][k] doubles.
+ *   Limits: q >= 0, 0 <= k <= 4096. */
+cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const void* ygrid_dev,
+                             int64_t k, const double* h, double* f_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDE_H */

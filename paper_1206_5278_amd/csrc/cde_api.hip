@@ -1,0 +1,316 @@
+// cde_api.hip -- host side of the C ABI declared in include/cde.h: argument
+// validation, per-setting coefficient preparation in FP64, device memory of
+// the model, and stream-ordered kernel launches.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cde_common.h"
+#include "cde_kernels.h"
+
+using namespace cde;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+cde_status fail(cde_status s, const std::string& msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+cde_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(e == hipErrorOutOfMemory ? CDE_ENOMEM : CDE_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool supported_dims(int dx, int dy)
+{
+    return (dy == 1 || dy == 2) && ((dx >= 1 && dx <= 8) || dx == 16);
+}
+
+bool valid_bandwidths(const double* h, int k)
+{
+    if (!h) return false;
+    for (int q = 0; q < k; ++q)
+        if (!(h[q] > 0.0) || !std::isfinite(h[q])) return false;
+    return true;
+}
+
+// Gaussian coefficients of one diagonal setting (Section 2: K_h(t) =
+// h^{-d} K(t/h), K the standard normal density).
+template <typename T>
+void fill_set(DiagSet<T>& s, const double* h, int dx, int dy)
+{
+    std::memset(&s, 0, sizeof s);
+    double lcx = 0.0, lcy = 0.0;
+    for (int k = 0; k < dx + dy; ++k) {
+        s.c[k] = (T)(LOG2E / (2.0 * h[k] * h[k]));
+        s.inv_h[k] = 1.0 / h[k];
+        s.inv_h3[k] = 1.0 / (h[k] * h[k] * h[k]);
+        if (k < dx) lcx -= std::log(h[k]) + HALF_LOG_2PI;
+        else lcy -= std::log(h[k]) + HALF_LOG_2PI;
+    }
+    s.log_cx = lcx;
+    s.log_cy = lcy;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+cde_status ensure_scratch(cde_model* m, size_t bytes)
+{
+    if (m->scratch_bytes >= bytes) return CDE_OK;
+    if (m->scratch) {
+        hipError_t e = hipFree(m->scratch);  // device-synchronising: no call still uses it
+        m->scratch = nullptr;
+        m->bytes -= m->scratch_bytes;
+        m->scratch_bytes = 0;
+        if (e != hipSuccess) return hip_fail(e, "hipFree(scratch)");
+    }
+    bytes = (bytes + 4095) & ~size_t(4095);
+    hipError_t e = hipMalloc(&m->scratch, bytes);
+    if (e != hipSuccess) {
+        m->scratch = nullptr;
+        return hip_fail(e, "hipMalloc(scratch)");
+    }
+    m->scratch_bytes = bytes;
+    m->bytes += bytes;
+    return CDE_OK;
+}
+
+// Value (and gradient) for a list of diagonal settings, reduced into
+// totals[g] (and grad[g][dx+dy]); per-setting non-finite counts are summed
+// into *nonfinite when given.
+template <typename T>
+cde_status run_diag_list(cde_model* m, const double* h, int g, int crit, bool grad, double* totals,
+                         double* grad_out, double* per_point, int64_t* nonfinite,
+                         hipStream_t stream)
+{
+    const int p = m->dx + m->dy;
+    const int nblocks = (int)(m->npad / TILE);
+    const int nv = grad ? p + 2 : 2;
+    const size_t part_bytes = sizeof(double) * (size_t)g * nblocks * nv;
+    const size_t cnt_bytes = sizeof(double) * (size_t)g;
+    cde_status st = ensure_scratch(m, part_bytes + cnt_bytes + 256);
+    if (st != CDE_OK) return st;
+    double* part = (double*)m->scratch;
+    for (int s0 = 0; s0 < g; s0 += MAX_SETS_PER_LAUNCH) {
+        const int cnt = std::min(MAX_SETS_PER_LAUNCH, g - s0);
+        DiagSets<T> sets;
+        std::memset(&sets, 0, sizeof sets);
+        for (int s = 0; s < cnt; ++s) fill_set(sets.s[s], h + (size_t)(s0 + s) * p, m->dx, m->dy);
+        hipError_t e = launch_diag<T>(m, sets, cnt, crit, grad,
+                                      per_point ? per_point + (size_t)s0 * m->n : nullptr,
+                                      part + (size_t)s0 * nblocks * nv, stream);
+        if (e != hipSuccess) return hip_fail(e, "launch k_loo_diag");
+    }
+    double* counts = part + (size_t)g * nblocks * nv;
+    hipError_t e = launch_reduce_parts(part, g, nblocks, nv, totals, grad ? grad_out : nullptr,
+                                       counts, nonfinite, stream);
+    if (e != hipSuccess) return hip_fail(e, "launch k_reduce_parts");
+    return CDE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cde_abi_version(void) { return CDE_ABI_VERSION; }
+
+const char* cde_last_error(void) { return g_last_error.c_str(); }
+
+cde_status cde_create(cde_model** out, const void* x_dev, const void* y_dev, int64_t n, int32_t dx,
+                      int32_t dy, cde_precision precision, void* stream)
+{
+    try {
+        if (!out) return fail(CDE_EINVAL, "cde_create: out is NULL");
+        *out = nullptr;
+        if (!x_dev || !y_dev) return fail(CDE_EINVAL, "cde_create: x_dev or y_dev is NULL");
+        if (n < 2) return fail(CDE_EINVAL, "cde_create: n must be >= 2");
+        if (n >= (int64_t(1) << 31) - TILE) return fail(CDE_EUNSUPPORTED, "cde_create: n >= 2^31");
+        if (dx < 1 || dy < 1) return fail(CDE_EINVAL, "cde_create: dx and dy must be >= 1");
+        if (!supported_dims(dx, dy))
+            return fail(CDE_EUNSUPPORTED, "cde_create: supported shapes are dx in {1..8, 16}, dy in {1, 2}");
+        if (precision != CDE_F32 && precision != CDE_F64)
+            return fail(CDE_EINVAL, "cde_create: unknown precision");
+        cde_model* m = new (std::nothrow) cde_model;
+        if (!m) return fail(CDE_ENOMEM, "cde_create: host allocation failed");
+        m->n = n;
+        m->npad = (n + TILE - 1) / TILE * TILE;
+        m->dx = dx;
+        m->dy = dy;
+        m->stride = row_stride(dx, dy);
+        m->prec = precision;
+        hipError_t e = hipGetDevice(&m->device);
+        if (e != hipSuccess) { delete m; return hip_fail(e, "hipGetDevice"); }
+        const size_t elt = precision == CDE_F64 ? sizeof(double) : sizeof(float);
+        const size_t pts_bytes = (size_t)m->npad * m->stride * elt;
+        e = hipMalloc(&m->pts, pts_bytes);
+        if (e != hipSuccess) { delete m; return hip_fail(e, "hipMalloc(points)"); }
+        m->bytes = pts_bytes;
+        hipStream_t s = (hipStream_t)stream;
+        e = precision == CDE_F64 ? launch_pack<double>(m, (const double*)x_dev, (const double*)y_dev, s)
+                                 : launch_pack<float>(m, (const float*)x_dev, (const float*)y_dev, s);
+        if (e != hipSuccess) {
+            (void)hipFree(m->pts);
+            delete m;
+            return hip_fail(e, "launch k_pack");
+        }
+        *out = m;
+        return CDE_OK;
+    } catch (...) {
+        return fail(CDE_EDEVICE, "cde_create: unexpected exception");
+    }
+}
+
+cde_status cde_destroy(cde_model* m)
+{
+    if (!m) return CDE_OK;
+    DeviceGuard guard(m->device);
+    cde_status st = CDE_OK;
+    for (void* p : {m->pts, m->nn, m->scratch}) {
+        if (!p) continue;
+        hipError_t e = hipFree(p);
+        if (e != hipSuccess && st == CDE_OK) st = hip_fail(e, "hipFree");
+    }
+    delete m;
+    return st;
+}
+
+size_t cde_model_device_bytes(const cde_model* m) { return m ? m->bytes : 0; }
+
+cde_status cde_loo_loglik_list(cde_model* m, const double* h, int32_t g, cde_criterion criterion,
+                               double* totals_dev, double* per_point_dev, void* stream)
+{
+    try {
+        if (!m) return fail(CDE_EINVAL, "cde_loo_loglik_list: model is NULL");
+        if (!totals_dev) return fail(CDE_EINVAL, "cde_loo_loglik_list: totals_dev is NULL");
+        if (g < 1 || g > 4096) return fail(CDE_EINVAL, "cde_loo_loglik_list: g must be in [1, 4096]");
+        if (criterion != CDE_COND && criterion != CDE_JOINT)
+            return fail(CDE_EINVAL, "cde_loo_loglik_list: unknown criterion");
+        if (!valid_bandwidths(h, g * (m->dx + m->dy)))
+            return fail(CDE_EINVAL, "cde_loo_loglik_list: bandwidths must be finite and > 0");
+        DeviceGuard guard(m->device);
+        hipStream_t s = (hipStream_t)stream;
+        return m->prec == CDE_F64
+                   ? run_diag_list<double>(m, h, g, criterion, false, totals_dev, nullptr,
+                                           per_point_dev, nullptr, s)
+                   : run_diag_list<float>(m, h, g, criterion, false, totals_dev, nullptr,
+                                          per_point_dev, nullptr, s);
+    } catch (...) {
+        return fail(CDE_EDEVICE, "cde_loo_loglik_list: unexpected exception");
+    }
+}
+
+cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const double* hy,
+                          int32_t n_hy, cde_criterion criterion, cde_xterm xterm,
+                          double* totals_dev, double* per_point_dev, int64_t* n_nonfinite_dev,
+                          void* stream)
+{
+    try {
+        if (!m) return fail(CDE_EINVAL, "cde_loo_loglik: model is NULL");
+        if (!totals_dev) return fail(CDE_EINVAL, "cde_loo_loglik: totals_dev is NULL");
+        if (n_hx < 1 || n_hx > 64 || n_hy < 1 || n_hy > 64)
+            return fail(CDE_EINVAL, "cde_loo_loglik: grid sizes must be in [1, 64]");
+        if (!valid_bandwidths(hx, n_hx) || !valid_bandwidths(hy, n_hy))
+            return fail(CDE_EINVAL, "cde_loo_loglik: bandwidths must be finite and > 0");
+        if (criterion != CDE_COND && criterion != CDE_JOINT)
+            return fail(CDE_EINVAL, "cde_loo_loglik: unknown criterion");
+        if (xterm == CDE_XTERM_MFMA_BF16X3)
+            return fail(CDE_EUNSUPPORTED, "cde_loo_loglik: the MFMA cross-term path is not built");
+        if (xterm != CDE_XTERM_AUTO && xterm != CDE_XTERM_VALU)
+            return fail(CDE_EINVAL, "cde_loo_loglik: unknown xterm");
+        const int p = m->dx + m->dy;
+        const int g = n_hx * n_hy;
+        std::vector<double> h((size_t)g * p);
+        for (int a = 0; a < n_hx; ++a)
+            for (int b = 0; b < n_hy; ++b)
+                for (int k = 0; k < p; ++k) h[(size_t)(a * n_hy + b) * p + k] = k < m->dx ? hx[a] : hy[b];
+        DeviceGuard guard(m->device);
+        hipStream_t s = (hipStream_t)stream;
+        return m->prec == CDE_F64
+                   ? run_diag_list<double>(m, h.data(), g, criterion, false, totals_dev, nullptr,
+                                           per_point_dev, n_nonfinite_dev, s)
+                   : run_diag_list<float>(m, h.data(), g, criterion, false, totals_dev, nullptr,
+                                          per_point_dev, n_nonfinite_dev, s);
+    } catch (...) {
+        return fail(CDE_EDEVICE, "cde_loo_loglik: unexpected exception");
+    }
+}
+
+cde_status cde_loo_grad(cde_model* m, const double* h, cde_criterion criterion, double* total_dev,
+                        double* grad_dev, double* per_point_dev, void* stream)
+{
+    try {
+        if (!m) return fail(CDE_EINVAL, "cde_loo_grad: model is NULL");
+        if (!total_dev || !grad_dev) return fail(CDE_EINVAL, "cde_loo_grad: output pointer is NULL");
+        if (criterion != CDE_COND && criterion != CDE_JOINT)
+            return fail(CDE_EINVAL, "cde_loo_grad: unknown criterion");
+        if (!valid_bandwidths(h, m->dx + m->dy))
+            return fail(CDE_EINVAL, "cde_loo_grad: bandwidths must be finite and > 0");
+        DeviceGuard guard(m->device);
+        hipStream_t s = (hipStream_t)stream;
+        return m->prec == CDE_F64
+                   ? run_diag_list<double>(m, h, 1, criterion, true, total_dev, grad_dev,
+                                           per_point_dev, nullptr, s)
+                   : run_diag_list<float>(m, h, 1, criterion, true, total_dev, grad_dev,
+                                          per_point_dev, nullptr, s);
+    } catch (...) {
+        return fail(CDE_EDEVICE, "cde_loo_grad: unexpected exception");
+    }
+}
+
+cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const void* ygrid_dev,
+                             int64_t k, const double* h, double* f_dev, void* stream)
+{
+    try {
+        if (!m) return fail(CDE_EINVAL, "cde_density_query: model is NULL");
+        if (q < 0 || k < 0 || k > 4096) return fail(CDE_EINVAL, "cde_density_query: need q >= 0, 0 <= k <= 4096");
+        if (q > 0 && k > 0 && (!xq_dev || !ygrid_dev || !f_dev))
+            return fail(CDE_EINVAL, "cde_density_query: NULL device pointer");
+        if (!valid_bandwidths(h, m->dx + m->dy))
+            return fail(CDE_EINVAL, "cde_density_query: bandwidths must be finite and > 0");
+        if (q == 0 || k == 0) return CDE_OK;
+        if (q * k >= (int64_t(1) << 40)) return fail(CDE_EUNSUPPORTED, "cde_density_query: q*k too large");
+        DeviceGuard guard(m->device);
+        hipStream_t s = (hipStream_t)stream;
+        hipError_t e;
+        if (m->prec == CDE_F64) {
+            DiagSets<double> sets;
+            std::memset(&sets, 0, sizeof sets);
+            fill_set(sets.s[0], h, m->dx, m->dy);
+            e = launch_query<double>(m, (const double*)xq_dev, q, (const double*)ygrid_dev, k, sets,
+                                     f_dev, s);
+        } else {
+            DiagSets<float> sets;
+            std::memset(&sets, 0, sizeof sets);
+            fill_set(sets.s[0], h, m->dx, m->dy);
+            e = launch_query<float>(m, (const float*)xq_dev, q, (const float*)ygrid_dev, k, sets,
+                                    f_dev, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "launch k_query");
+        return CDE_OK;
+    } catch (...) {
+        return fail(CDE_EDEVICE, "cde_density_query: unexpected exception");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// cde_device.h -- small device helpers shared by the gfx950 kernels.
+#pragma once
+
+#include "cde_common.h"
+
+namespace cde {
+
+template <typename T>
+__device__ __forceinline__ T exp2_(T x);
+
+// v_exp_f32: base-2 exponential on the transcendental unit (about 1 ulp).
+template <>
+__device__ __forceinline__ float exp2_<float>(float x) { return __builtin_amdgcn_exp2f(x); }
+
+template <>
+__device__ __forceinline__ double exp2_<double>(double x) { return exp2(x); }
+
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float min_(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double min_(double a, double b) { return __builtin_fmin(a, b); }
+
+template <typename T>
+__device__ __forceinline__ T inf_();
+template <>
+__device__ __forceinline__ float inf_<float>() { return __builtin_inff(); }
+template <>
+__device__ __forceinline__ double inf_<double>() { return __builtin_inf(); }
+
+// Compensated (Kahan) accumulator: `s - c` carries the running sum with the
+// rounding error of each addition fed back into the next one.
+template <typename T>
+struct Kahan {
+    T s, c;
+    __device__ __forceinline__ void zero() { s = T(0); c = T(0); }
+    __device__ __forceinline__ void add(T x)
+    {
+        T y = x - c;
+        T t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ void scale(T f) { s *= f; c *= f; }
+    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+};
+
+// Load one point row of S values (S a multiple of 4) with 16-byte loads.
+template <int S>
+__device__ __forceinline__ void load_row(float (&dst)[S], const float* src)
+{
+    static_assert(S % 4 == 0, "row stride must be a multiple of 4");
+#pragma unroll
+    for (int q = 0; q < S; q += 4) {
+        float4 v = *reinterpret_cast<const float4*>(src + q);
+        dst[q] = v.x; dst[q + 1] = v.y; dst[q + 2] = v.z; dst[q + 3] = v.w;
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void load_row(double (&dst)[S], const double* src)
+{
+    static_assert(S % 2 == 0, "row stride must be even");
+#pragma unroll
+    for (int q = 0; q < S; q += 2) {
+        double2 v = *reinterpret_cast<const double2*>(src + q);
+        dst[q] = v.x; dst[q + 1] = v.y;
+    }
+}
+
+template <int S, typename T>
+__device__ __forceinline__ void store_row(T* dst, const T (&src)[S])
+{
+#pragma unroll
+    for (int q = 0; q < S; ++q) dst[q] = src[q];
+}
+
+// Deterministic block sum of NV doubles per thread over a 256-thread block:
+// fixed butterfly inside each 64-lane wave, then waves 0..3 in order.
+// The result is valid in thread 0 only.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* [4][NV] LDS */)
+{
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[wave * NV + q] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] = ((red[q] + red[NV + q]) + red[2 * NV + q]) + red[3 * NV + q];
+    }
+}
+
+}  // namespace cde

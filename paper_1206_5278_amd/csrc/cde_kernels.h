@@ -1,0 +1,31 @@
+// cde_kernels.h -- launch functions of the gfx950 kernels (library-internal).
+#pragma once
+
+#include "cde_common.h"
+
+namespace cde {
+
+// Pack row-major x [n][dx] and y [n][dy] into the model's [npad][stride] rows.
+template <typename T>
+hipError_t launch_pack(cde_model* m, const T* x, const T* y, hipStream_t stream);
+
+// Diagonal-bandwidth LOO pass (value, optionally gradient) for `nsets`
+// settings; writes one partial row per (setting, 256-point block) to `part`.
+template <typename T>
+hipError_t launch_diag(const cde_model* m, const DiagSets<T>& sets, int nsets, int crit, bool grad,
+                       double* per_point, double* part, hipStream_t stream);
+
+// Density queries f(yg[g] | xq[q]) over all training points -> f [q][k].
+template <typename T>
+hipError_t launch_query(const cde_model* m, const T* xq, int64_t q, const T* yg, int64_t k,
+                        const DiagSets<T>& sets, double* f, hipStream_t stream);
+
+// Fixed-order FP64 sum of the per-block partial rows of `nsets` settings:
+// part [nsets][nblocks][nv] -> totals [nsets] (column 0), grad [nsets][nv-2]
+// (columns 1..nv-2, if grad != NULL); if nonfinite != NULL, the per-setting
+// non-finite counts (last column) go to counts [nsets] (scratch) and their
+// sum is written to *nonfinite.
+hipError_t launch_reduce_parts(const double* part, int nsets, int nblocks, int nv, double* totals,
+                               double* grad, double* counts, int64_t* nonfinite, hipStream_t stream);
+
+}  // namespace cde

@@ -1,0 +1,75 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, and rejects bad arguments with status codes before touching
+a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cde.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cde_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1206_5278_amd import _binding
+    return _binding.load()
+
+
+def test_header_declares_expected_calls():
+    names = declared_functions()
+    for n in ("cde_create", "cde_destroy", "cde_loo_loglik", "cde_loo_grad", "cde_density_query",
+              "cde_loo_loglik_list", "cde_last_error", "cde_abi_version"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1206_5278_amd import _binding
+    out = subprocess.run(["nm", "-D", "--defined-only", _binding.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (cde_\w+)", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    # and the binding declares a signature for each of them
+    assert set(declared_functions()) <= set(_binding.SIGNATURES)
+
+
+def test_abi_version(lib):
+    assert lib.cde_abi_version() == 1
+
+
+def test_invalid_arguments_return_status(lib):
+    from paper_1206_5278_amd import _binding as B
+    h = ctypes.c_void_p()
+    assert lib.cde_create(None, 1, 1, 10, 1, 1, 0, None) == B.CDE_EINVAL
+    assert lib.cde_create(ctypes.byref(h), None, None, 10, 1, 1, 0, None) == B.CDE_EINVAL
+    assert lib.cde_create(ctypes.byref(h), 8, 8, 1, 1, 1, 0, None) == B.CDE_EINVAL  # n < 2
+    assert lib.cde_create(ctypes.byref(h), 8, 8, 10, 0, 1, 0, None) == B.CDE_EINVAL
+    assert lib.cde_create(ctypes.byref(h), 8, 8, 10, 65, 1, 0, None) == B.CDE_EUNSUPPORTED
+    assert lib.cde_create(ctypes.byref(h), 8, 8, 10, 1, 1, 7, None) == B.CDE_EINVAL
+    assert b"precision" in lib.cde_last_error()
+    hv = B.doubles([1.0, 1.0])
+    assert lib.cde_loo_grad(None, hv, 0, 8, 8, None, None) == B.CDE_EINVAL
+    assert lib.cde_loo_loglik(None, hv, 1, hv, 1, 0, 0, 8, None, None, None) == B.CDE_EINVAL
+    assert lib.cde_loo_loglik_list(None, hv, 1, 0, 8, None, None) == B.CDE_EINVAL
+    assert lib.cde_density_query(None, 8, 1, 8, 1, hv, 8, None) == B.CDE_EINVAL
+    assert lib.cde_destroy(None) == B.CDE_OK
+    assert lib.cde_model_device_bytes(None) == 0
+
+
+def test_product_path_does_not_reference_oracle():
+    pkg = os.path.join(ROOT, "paper_1206_5278_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "cde_oracle" not in text and "oracle_loo" not in text, f
