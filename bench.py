@@ -35,6 +35,11 @@ EXP_SLOTS = 2.0
 # for the product-kernel exponent, 2 kernel-sum adds and 11 moment FMAs
 # (F = 30), plus two exponentials (E = 2).
 PAIR_F, PAIR_E = 30.0, 2.0
+# Scaled HBM bytes of one k_loo_diag<float,5,1,grad> launch at N=500k, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE runs, each scaled by the same counter's
+# reading for a 256 MiB copy (profiles/k_loo_diag_f32_5x1_grad_photoz500k.md).
+# Set to None whenever that kernel changes, until the counters are re-taken.
+DIAG_TRAFFIC_BYTES = 976_613_000
 
 
 def parse():
@@ -46,6 +51,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (a known-size kernel "
+                         "for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -94,6 +102,13 @@ def main():
     model = cde.Model(torch.from_numpy(x32).to(dev), torch.from_numpy(y32).to(dev))
     h0 = cde.normal_reference_bandwidths(x32.astype(np.float64), y32.astype(np.float64))
 
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     theta = torch.log(h0.clone()).requires_grad_(True)
     opt = torch.optim.Adam([theta], lr=0.05, betas=(0.9, 0.999))
     stream = torch.cuda.current_stream()
@@ -133,7 +148,8 @@ def main():
     achieved = slots / (kern_ms * 1e-3) / 1e12
     peak = VALU_PEAK_SLOTS / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak,
+                "traffic": DIAG_TRAFFIC_BYTES if n == 500_000 else None,
                 "kernel": "k_loo_diag<float,5,1,grad>", "kernel_ms": kern_ms,
                 "work_per_pair": f"F={PAIR_F:g} VALU ops + E={PAIR_E:g} v_exp_f32 x {EXP_SLOTS:g} slots"}
 

@@ -1,0 +1,126 @@
+"""Parity at the benchmark sizes, in the launch configuration the benchmark
+times: sampled per-point values against the oracle computed point by point
+(each sampled i against all N-1 points j), plus properties that hold at any
+size.  Also the gradient workload's 5k-point subsample checks (oracle
+gradient, finite differences) and the exactness of ascent checkpoints."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+NT = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def cde():
+    import paper_1206_5278_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def photoz_full():
+    x, y = workloads.photoz(500_000, seed=0)
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    return xo, yo, cde().Model(xd, yd)
+
+
+def test_photoz_500k_sampled_points_value_and_grad_call(photoz_full):
+    print("case: photoz n=500000 value+grad, 96 sampled points", flush=True)
+    xo, yo, m = photoz_full
+    h0 = cde().normal_reference_bandwidths(xo, yo).tolist()
+    for h in (h0, [0.03, 0.025, 0.03, 0.035, 0.04, 0.012]):
+        total, grad, pp = m.loo_grad(h, per_point=True)
+        pp = pp.cpu().numpy()
+        assert np.all(np.isfinite(pp))
+        idx = np.sort(np.random.default_rng(7).choice(500_000, 96, replace=False))
+        # include the points with the largest and smallest l_i: the outliers
+        idx = np.unique(np.concatenate([idx, [int(np.argmin(pp)), int(np.argmax(pp))]]))
+        ref = oracle.loo(xo, yo, h, idx=idx, nthreads=NT)
+        P.assert_points(pp[idx], ref)
+        # the total is the fixed-order sum of the per-point values
+        assert abs(float(total.item()) - float(np.sum(pp))) <= 1e-10 * abs(float(total.item()))
+        assert np.all(np.isfinite(grad.cpu().numpy()))
+
+
+def test_photoz_5k_subsample_gradient_vs_oracle_and_fd():
+    print("case: photoz 5k subsample gradient", flush=True)
+    x, y = workloads.photoz(500_000, seed=0)
+    xs, ys = workloads.subsample(x, y, 5000, seed=1)
+    xo, yo, xd, yd = P.f32_pair(xs, ys)
+    m = cde().Model(xd, yd)
+    h = cde().normal_reference_bandwidths(xo, yo).numpy()
+    total, grad, pp = m.loo_grad(h.tolist(), per_point=True)
+    ell, dell = oracle.loo(xo, yo, h, grad=True, nthreads=NT)
+    P.assert_points(pp.cpu().numpy(), ell)
+    P.assert_total(float(total.item()), oracle.total(ell), ell)
+    g = grad.cpu().numpy()
+    rg = dell.sum(axis=0)
+    P.assert_grad(g, rg)
+    # Central differences, step 1e-4 relative, of the FP64 oracle (its own
+    # truncation error is ~1e-8 relative) agree with the GPU adjoint.
+    fd = np.empty(6)
+    for k in range(6):
+        d = 1e-4 * h[k]
+        hp, hm = h.copy(), h.copy()
+        hp[k] += d
+        hm[k] -= d
+        fd[k] = (oracle.total(oracle.loo(xo, yo, hp, nthreads=NT)) -
+                 oracle.total(oracle.loo(xo, yo, hm, nthreads=NT))) / (2 * d)
+    P.assert_grad(g, fd)
+    # The same 12 finite-difference points evaluated on the GPU in one list
+    # call: a loose sanity check (FP32 noise / 2e-4 dominates).
+    hs = []
+    for k in range(6):
+        for sgn in (1, -1):
+            hh = h.copy()
+            hh[k] += sgn * 1e-4 * h[k]
+            hs.append(hh.tolist())
+    tl, _ = m.loo_list(hs)
+    tl = tl.cpu().numpy()
+    gfd = np.array([(tl[2 * k] - tl[2 * k + 1]) / (2e-4 * h[k]) for k in range(6)])
+    assert np.all(np.abs(gfd - g) <= 2e-2 * np.max(np.abs(g)))
+
+
+def test_gmm_50k_32x32_grid_sampled_points():
+    print("case: gmm n=50000 32x32 grid, 8 sampled points", flush=True)
+    cfg = workloads.WORKLOADS["gmm"]
+    x, y = workloads.gmm()
+    hx, hy = cfg["grid"]
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    tot, pp, nonfin = m.loo_grid(hx, hy, per_point=True)
+    assert int(nonfin.item()) == 0
+    pp = pp.cpu().numpy()
+    idx = np.sort(np.random.default_rng(3).choice(50_000, 8, replace=False))
+    ref = oracle.loo_grid(xo, yo, hx, hy, idx=idx, nthreads=NT)
+    P.assert_points(pp[:, idx], ref)
+    t = tot.cpu().numpy()
+    np.testing.assert_allclose(t, pp.sum(axis=1), rtol=1e-10)
+
+
+def test_ascend_checkpoint_resume_is_exact(tmp_path):
+    print("case: ascend checkpoint/resume", flush=True)
+    x, y = workloads.photoz(3000, seed=9)
+    _, _, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    h0 = cde().normal_reference_bandwidths(x.astype(np.float32), y.astype(np.float32))
+    full = cde().ascend(m, h0, steps=6)
+    ck = str(tmp_path / "ck.json")
+    cde().ascend(m, h0, steps=3, checkpoint=ck)
+    import json
+    resumed = cde().ascend(m, h0, steps=6, resume=json.load(open(ck)))
+    assert resumed["trace"] == full["trace"]
+    assert resumed["theta"] == full["theta"]
+    # ascent increases the criterion from the normal-reference start
+    assert full["trace"][-1] > full["trace"][0]
