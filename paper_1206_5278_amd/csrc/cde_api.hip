@@ -238,19 +238,41 @@ cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const do
             return fail(CDE_EUNSUPPORTED, "cde_loo_loglik: the MFMA cross-term path is not built");
         if (xterm != CDE_XTERM_AUTO && xterm != CDE_XTERM_VALU)
             return fail(CDE_EINVAL, "cde_loo_loglik: unknown xterm");
-        const int p = m->dx + m->dy;
-        const int g = n_hx * n_hy;
-        std::vector<double> h((size_t)g * p);
-        for (int a = 0; a < n_hx; ++a)
-            for (int b = 0; b < n_hy; ++b)
-                for (int k = 0; k < p; ++k) h[(size_t)(a * n_hy + b) * p + k] = k < m->dx ? hx[a] : hy[b];
         DeviceGuard guard(m->device);
         hipStream_t s = (hipStream_t)stream;
-        return m->prec == CDE_F64
-                   ? run_diag_list<double>(m, h.data(), g, criterion, false, totals_dev, nullptr,
-                                           per_point_dev, n_nonfinite_dev, s)
-                   : run_diag_list<float>(m, h.data(), g, criterion, false, totals_dev, nullptr,
-                                          per_point_dev, n_nonfinite_dev, s);
+        const int g = n_hx * n_hy;
+        if (m->prec == CDE_F64) {
+            // FP64 models: every setting as a diagonal setting (FP64 throughout).
+            const int p = m->dx + m->dy;
+            std::vector<double> h((size_t)g * p);
+            for (int a = 0; a < n_hx; ++a)
+                for (int b = 0; b < n_hy; ++b)
+                    for (int k = 0; k < p; ++k)
+                        h[(size_t)(a * n_hy + b) * p + k] = k < m->dx ? hx[a] : hy[b];
+            return run_diag_list<double>(m, h.data(), g, criterion, false, totals_dev, nullptr,
+                                         per_point_dev, n_nonfinite_dev, s);
+        }
+        if (!m->nn) {
+            hipError_t e = hipMalloc(&m->nn, sizeof(double) * 2 * (size_t)m->npad);
+            if (e != hipSuccess) {
+                m->nn = nullptr;
+                return hip_fail(e, "hipMalloc(neighbour shifts)");
+            }
+            m->bytes += sizeof(double) * 2 * (size_t)m->npad;
+        }
+        const size_t wb = grid_work_bytes(m, n_hx, n_hy);
+        cde_status st = ensure_scratch(m, wb + sizeof(double) * (size_t)g + 256);
+        if (st != CDE_OK) return st;
+        double* counts = (double*)((char*)m->scratch + wb);
+        hipError_t e = launch_grid(m, hx, n_hx, hy, n_hy, criterion, totals_dev, per_point_dev,
+                                   m->scratch, wb, counts, s);
+        if (e != hipSuccess) return hip_fail(e, "launch grid kernels");
+        m->nn_ready = true;
+        if (n_nonfinite_dev) {
+            e = launch_sum_counts(counts, g, n_nonfinite_dev, s);
+            if (e != hipSuccess) return hip_fail(e, "launch k_sum_counts");
+        }
+        return CDE_OK;
     } catch (...) {
         return fail(CDE_EDEVICE, "cde_loo_loglik: unexpected exception");
     }

@@ -51,7 +51,7 @@ struct cde_model {
     void* pts = nullptr;     // [npad][stride] of float or double
     // per-point nearest-neighbour squared distances (unscaled), min over j != i,
     // in x and in y separately; computed once, used as the grid kernel's shifts
-    void* nn = nullptr;      // [2][npad] of float or double
+    void* nn = nullptr;      // [2][npad] doubles (FP32 models, grid path)
     bool nn_ready = false;
     void* scratch = nullptr; // block partials and flags
     size_t scratch_bytes = 0;

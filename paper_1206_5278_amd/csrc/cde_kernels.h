@@ -20,6 +20,15 @@ template <typename T>
 hipError_t launch_query(const cde_model* m, const T* xq, int64_t q, const T* yg, int64_t k,
                         const DiagSets<T>& sets, double* f, hipStream_t stream);
 
+// Scalar-bandwidth grid on FP32 models: per-point neighbour shifts (first
+// call only), the MFMA grid pass, FP64 finalisation, exact fixup of extreme
+// entries and the fixed-order row sums.  `work` must hold grid_work_bytes();
+// `counts` receives the per-setting non-finite counts [n_hx * n_hy].
+hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* hy, int n_hy, int crit,
+                       double* totals, double* per_point, void* work, size_t work_bytes,
+                       double* counts, hipStream_t stream);
+size_t grid_work_bytes(const cde_model* m, int n_hx, int n_hy);
+
 // Fixed-order FP64 sum of the per-block partial rows of `nsets` settings:
 // part [nsets][nblocks][nv] -> totals [nsets] (column 0), grad [nsets][nv-2]
 // (columns 1..nv-2, if grad != NULL); if nonfinite != NULL, the per-setting
@@ -27,5 +36,8 @@ hipError_t launch_query(const cde_model* m, const T* xq, int64_t q, const T* yg,
 // sum is written to *nonfinite.
 hipError_t launch_reduce_parts(const double* part, int nsets, int nblocks, int nv, double* totals,
                                double* grad, double* counts, int64_t* nonfinite, hipStream_t stream);
+
+// *out = sum of counts[0..nsets) in order (one thread).
+hipError_t launch_sum_counts(const double* counts, int nsets, int64_t* out, hipStream_t stream);
 
 }  // namespace cde

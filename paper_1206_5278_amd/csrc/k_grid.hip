@@ -1,0 +1,481 @@
+// k_grid.hip -- exact LOO log-likelihood over a grid of scalar bandwidths
+// (one hx for all x-dimensions, one hy for all y-dimensions), FP32 data.
+//
+// Definitions (Holmes, Gray & Isbell): Section 2 (scaled Gaussian kernel,
+// eq. 1) and eq. (3) expanded as in Section 3.2.  For point i and grid cell
+// (a, b) the sums are
+//     den_i[a]    = sum_{j!=i} K_hx[a](x_i - x_j)
+//     num_i[a][b] = sum_{j!=i} K_hx[a](x_i - x_j) K_hy[b](y_i - y_j).
+// With scalar bandwidths both kernels are exponentials of the squared
+// distances d2x_ij, d2y_ij times per-bandwidth coefficients, so
+//     num_i[a][b] = sum_j ex_a(i,j) * ey_b(i,j)
+// is, for each i, a dense contraction over j of an [Gx x J] matrix with a
+// [J x Gy] matrix: it runs on the matrix cores (v_mfma_f64_16x16x4f64),
+// while the VALU forms the distances and only Gx + Gy kernel values per pair
+// (not Gx * Gy).
+//
+// Range and precision: every exponent is taken relative to the point's
+// nearest x-neighbour distance m_i and nearest y-neighbour distance my_i
+// (over j != i, computed once per model by k_nn with the same FP32 formula):
+//     ex_a = 2^-((d2x - m_i) c_a),  ey_b = 2^-((d2y - my_i) c'_b),
+// so ex <= 1 with ex = 1 at the x-neighbour (den' >= 1) and ey <= 1.  Over a
+// whole grid the largest term of a cell can still be hundreds of binary
+// orders below 1 (small hx with small hy), which FP32 cannot hold; so each
+// kernel value is formed as v_exp_f32 of the fractional part of its exponent
+// (FP32 accuracy) scaled exactly by a power of two in FP64, and the products
+// and sums over j run in FP64 on the matrix cores.  The shifts cancel in the
+// ratio and are restored in FP64 by the finalisation.  An entry whose
+// shifted num' is below 2^-1000 is recomputed exactly by k_grid_fixup with a
+// per-entry shift.
+//
+// Work decomposition: a 256-lane block owns 32 points (8 per wave) and one
+// 16 x 16 tile of the (padded) grid (blockIdx.y); j streams through LDS in
+// 256-point tiles.  Lane l of a wave forms the distance of point i0 + l%8 to
+// tile row 4*((l%16)/8) + l/16 of the current 8-row group; a DPP row
+// broadcast (row_newbcast) then hands each MFMA operand lane the pair it
+// needs, so every distance is computed once per tile of the grid.
+#include <type_traits>
+
+#include "cde_device.h"
+#include "cde_kernels.h"
+
+namespace cde {
+
+// Compile-time loop: f(integral_constant<int, 0>) ... f(integral_constant<int, K-1>).
+template <int K>
+struct Unroll {
+    template <class F>
+    __device__ __forceinline__ static void run(F&& f)
+    {
+        Unroll<K - 1>::run(f);
+        f(std::integral_constant<int, K - 1>{});
+    }
+};
+template <>
+struct Unroll<0> {
+    template <class F>
+    __device__ __forceinline__ static void run(F&&) {}
+};
+
+// Value of lane `L` of this lane's 16-lane row (DPP row_newbcast).
+template <int L>
+__device__ __forceinline__ float row_bcast(int v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x150 + L, 0xF, 0xF, false));
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// 2^-t in FP64 for finite t >= 0: v_exp_f32 of the fractional part, an exact
+// power-of-two scaling for the integer part (which saturates, giving 0, for
+// the huge sentinel used for excluded pairs).
+__device__ __forceinline__ double exp2_neg_wide(float t)
+{
+#pragma clang fp contract(off)
+    const float fl = floorf(t);
+    const float fr = t - fl;  // in [0, 1)
+    return ldexp((double)__builtin_amdgcn_exp2f(-fr), (int)(-fl));
+}
+
+// Exponent argument of an excluded pair (j == i, or j past the end): finite,
+// so that sentinel * c stays finite for any c < 3e18 (h > 5e-10), and its
+// kernel value is exactly 0.
+constexpr float EXCLUDED = 1e20f;
+
+// Squared distances in x and in y, in FP64: the differences of FP32
+// coordinates are exact in FP64, so the only roundings are those of the
+// squares and sums (about 1e-16 relative).
+template <int DX, int DY>
+__device__ __forceinline__ void dist2(const double* a, const float* b, double& dxs, double& dys)
+{
+    double e = 0.0;
+#pragma unroll
+    for (int k = 0; k < DX; ++k) {
+        double d = a[k] - (double)b[k];
+        e = fma_(d, d, e);
+    }
+    double f = 0.0;
+#pragma unroll
+    for (int l = 0; l < DY; ++l) {
+        double d = a[DX + l] - (double)b[DX + l];
+        f = fma_(d, d, f);
+    }
+    dxs = e;
+    dys = f;
+}
+
+template <int S>
+__device__ __forceinline__ void own_f64(double (&dst)[S], const float* src)
+{
+    float t[S];
+    load_row<S>(t, src);
+#pragma unroll
+    for (int q = 0; q < S; ++q) dst[q] = (double)t[q];
+}
+
+// Per point: nearest-neighbour squared distances in x and in y, j != i.
+template <int DX, int DY>
+__global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int n,
+                                             double* __restrict__ nn, int npad)
+{
+    constexpr int S = row_stride(DX, DY);
+    __shared__ float tile[TILE * S];
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x * TILE + tid;
+    double own[S];
+    own_f64<S>(own, pts + (size_t)i * S);
+    double mx = inf_<double>(), my = inf_<double>();
+    const int ntiles = (n + TILE - 1) / TILE;
+    for (int t = 0; t < ntiles; ++t) {
+        __syncthreads();
+        float pre[S];
+        load_row<S>(pre, pts + ((size_t)t * TILE + tid) * S);
+        store_row<S>(tile + tid * S, pre);
+        __syncthreads();
+        const int cnt = min(TILE, n - t * TILE);
+        const int self = (t == (int)blockIdx.x) ? tid : -1;
+        for (int q = 0; q < cnt; ++q) {
+            float pj[S];
+            load_row<S>(pj, tile + q * S);
+            double a, b;
+            dist2<DX, DY>(own, pj, a, b);
+            if (q == self) continue;
+            mx = min_(mx, a);
+            my = min_(my, b);
+        }
+    }
+    nn[i] = mx;
+    nn[npad + i] = my;
+}
+
+// Grid coefficients (base 2), padded to a multiple of 16 with copies of the
+// last value; only the first gx x gy cells are reported.
+struct GridArgs {
+    float cx[64];
+    float cy[64];
+    int gx, gy;    // real grid sizes
+    int gxp, gyp;  // padded to multiples of 16
+};
+
+template <int DX, int DY>
+__global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts,
+                                                   const double* __restrict__ nn, int n, int npad,
+                                                   GridArgs ga, double* __restrict__ numbuf,
+                                                   double* __restrict__ denbuf)
+{
+    constexpr int S = row_stride(DX, DY);
+    __shared__ float tile[TILE * S];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int i0 = blockIdx.x * 32 + wave * 8;  // this wave's 8 points
+    const int tb = ga.gyp / 16;                 // b-tiles per row of tiles
+    const int ab = blockIdx.y / tb, bb = blockIdx.y % tb;
+    const bool do_den = (bb == 0);
+
+    // distance role: point i0 + lane%8 against tile row group*8 + jo
+    const int di = i0 + (lane & 7);
+    const int jo = 4 * ((lane & 15) >> 3) + (lane >> 4);
+    double own[S];
+    own_f64<S>(own, pts + (size_t)di * S);
+    const double m_i = nn[di], my_i = nn[npad + di];
+    // MFMA role: row a = ab*16 + lane%16 of A, column b = bb*16 + lane%16 of B
+    const float ca = ga.cx[ab * 16 + (lane & 15)];
+    const float cb = ga.cy[bb * 16 + (lane & 15)];
+
+    v4d acc[8];
+    double dsum[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+        dsum[t] = 0.0;
+    }
+
+    const int ntiles = (n + TILE - 1) / TILE;
+    float pre[S];
+    load_row<S>(pre, pts + (size_t)tid * S);
+    for (int t = 0; t < ntiles; ++t) {
+        __syncthreads();
+        store_row<S>(tile + tid * S, pre);
+        __syncthreads();
+        if (t + 1 < ntiles) load_row<S>(pre, pts + ((size_t)(t + 1) * TILE + tid) * S);
+        const int base = t * TILE;
+        const int cnt = min(TILE, n - base);
+        const int ngroups = (cnt + 7) >> 3;
+        for (int g = 0; g < ngroups; ++g) {
+            const int jj = g * 8 + jo;
+            float pj[S];
+            load_row<S>(pj, tile + jj * S);  // rows >= cnt hold packed padding (in bounds)
+            double d2x, d2y;
+            dist2<DX, DY>(own, pj, d2x, d2y);
+            // shifted distances, rounded to FP32 only after the subtraction
+            float xa = (float)(d2x - m_i), ya = (float)(d2y - my_i);
+            if (jj >= cnt || base + jj == di) {
+                xa = EXCLUDED;
+                ya = EXCLUDED;
+            }
+            const int xai = __float_as_int(xa), yai = __float_as_int(ya);
+            // step idx = 8 s + q: point i0 + q against rows 4 s + k (k = lane/16)
+            Unroll<16>::run([&](auto c) {
+                constexpr int idx = decltype(c)::value;
+                constexpr int q = idx & 7;
+                const double ex = exp2_neg_wide(row_bcast<idx>(xai) * ca);
+                const double ey = exp2_neg_wide(row_bcast<idx>(yai) * cb);
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, ey, acc[q], 0, 0, 0);
+                dsum[q] += ex;  // used by the b-tile-0 blocks only
+            });
+        }
+    }
+
+    // num' for (i0+q, a, b): the f64 16x16x4 result puts row (lane/16) + 4r,
+    // column lane%16 in register r of each lane.
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int i = i0 + q;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int a = ab * 16 + (lane >> 4) + 4 * r;
+            const int b = bb * 16 + (lane & 15);
+            if (a < ga.gx && b < ga.gy) numbuf[((size_t)a * ga.gy + b) * npad + i] = acc[q][r];
+        }
+    }
+    if (do_den) {
+        // den' partials: lane (a = lane%16, k = lane/16) summed its k-rows;
+        // combine the four k-rows in a fixed order.
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            double v = dsum[q];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            const int a = ab * 16 + (lane & 15);
+            if (lane < 16 && a < ga.gx) denbuf[(size_t)a * npad + i0 + q] = v;
+        }
+    }
+}
+
+struct GridFin {
+    double cxa[64];   // c_a in FP64 (the same FP32 values the kernel used)
+    double cyb[64];
+    double log_cx[64];
+    double log_cy[64];
+    int gx, gy;
+};
+
+// Per (setting, point) finalisation in FP64; entries whose shifted num' is
+// too small for FP32 to have carried it are queued for the exact fixup.
+__global__ void k_grid_finalize(const double* __restrict__ numbuf, const double* __restrict__ denbuf,
+                                const double* __restrict__ nn, int n, int npad, GridFin gf, int crit,
+                                double* __restrict__ ell, int* __restrict__ fix_count,
+                                int2* __restrict__ fix_list, int fix_cap)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    if (i >= n) return;
+    const int a = g / gf.gy, b = g - a * gf.gy;
+    const double num = numbuf[(size_t)g * npad + i];
+    const double den = denbuf[(size_t)a * npad + i];
+    const double m = nn[i], my = nn[npad + i];
+    double v;
+    if (crit == CDE_COND)
+        v = gf.log_cy[b] + log(num / den) - my * gf.cyb[b] * LN2;
+    else
+        v = gf.log_cx[a] + gf.log_cy[b] + log(num) - (m * gf.cxa[a] + my * gf.cyb[b]) * LN2 -
+            log((double)(n - 1));
+    ell[(size_t)g * npad + i] = v;
+    if (!(num >= 0x1p-1000)) {
+        const int slot = atomicAdd(fix_count, 1);
+        if (slot < fix_cap) fix_list[slot] = make_int2(g, i);
+    }
+}
+
+// Exact recomputation of queued (setting, point) entries: one wave per entry,
+// lanes split j; pass 1 finds the entry's largest term, pass 2 sums all terms
+// relative to it (Kahan per lane, FP64 across lanes).
+template <int DX, int DY>
+__global__ __launch_bounds__(TILE) void k_grid_fixup(const float* __restrict__ pts,
+                                                     const double* __restrict__ nn, int n, int npad,
+                                                     GridArgs ga, GridFin gf, int crit,
+                                                     const double* __restrict__ denbuf,
+                                                     double* __restrict__ ell,
+                                                     const int* __restrict__ fix_count,
+                                                     const int2* __restrict__ fix_list, int fix_cap)
+{
+    constexpr int S = row_stride(DX, DY);
+    const int lane = threadIdx.x & 63;
+    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nw = (gridDim.x * blockDim.x) >> 6;
+    const int count = min(*fix_count, fix_cap);
+    for (int e = wid; e < count; e += nw) {
+        const int2 gi = fix_list[e];
+        const int g = gi.x, i = gi.y;
+        const int a = g / ga.gy, b = g - a * ga.gy;
+        const float ca = ga.cx[a], cb = ga.cy[b];
+        double own[S];
+        own_f64<S>(own, pts + (size_t)i * S);
+        const double m_i = nn[i], my_i = nn[npad + i];
+        // E_j = (d2x - m) c_a + (d2y - my) c_b, shifted distances rounded to
+        // FP32 after the FP64 subtraction exactly as in k_loo_grid
+        float emin = inf_<float>();
+        for (int j = lane; j < n; j += 64) {
+            if (j == i) continue;
+            float pj[S];
+            load_row<S>(pj, pts + (size_t)j * S);
+            double d2x, d2y;
+            dist2<DX, DY>(own, pj, d2x, d2y);
+            emin = min_(emin, (float)(d2x - m_i) * ca + (float)(d2y - my_i) * cb);
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) emin = min_(emin, __shfl_xor(emin, off, 64));
+        Kahan<float> s;
+        s.zero();
+        for (int j = lane; j < n; j += 64) {
+            if (j == i) continue;
+            float pj[S];
+            load_row<S>(pj, pts + (size_t)j * S);
+            double d2x, d2y;
+            dist2<DX, DY>(own, pj, d2x, d2y);
+            s.add(exp2_<float>(-((float)(d2x - m_i) * ca + (float)(d2y - my_i) * cb - emin)));
+        }
+        double v = s.value();
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) {
+            const double den = denbuf[(size_t)a * npad + i];
+            const double m = m_i, my = my_i;
+            // sum_j 2^{-E_j} = 2^{-emin} * v, with E_j the shifted exponents
+            double r;
+            if (crit == CDE_COND)
+                r = gf.log_cy[b] + log(v / den) - (double)emin * LN2 - my * gf.cyb[b] * LN2;
+            else
+                r = gf.log_cx[a] + gf.log_cy[b] + log(v) - (double)emin * LN2 -
+                    (m * gf.cxa[a] + my * gf.cyb[b]) * LN2 - log((double)(n - 1));
+            ell[(size_t)g * npad + i] = r;
+        }
+    }
+}
+
+// Fixed-order sum of each setting's row of per-point values; optional copy
+// of the rows to a caller buffer with row stride n; non-finite counts.
+__global__ __launch_bounds__(256) void k_grid_rows(const double* __restrict__ ell, int n, int npad,
+                                                   double* __restrict__ totals,
+                                                   double* __restrict__ per_point,
+                                                   double* __restrict__ counts)
+{
+    __shared__ double red[8];
+    const int g = blockIdx.x;
+    double v[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double x = ell[(size_t)g * npad + i];
+        v[0] += x;
+        v[1] += isfinite(x) ? 0.0 : 1.0;
+        if (per_point) per_point[(size_t)g * n + i] = x;
+    }
+    block_sum<2>(v, red);
+    if (threadIdx.x == 0) {
+        totals[g] = v[0];
+        counts[g] = v[1];
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <int DX, int DY>
+static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& gf, int crit,
+                         double* numbuf, double* denbuf, double* ell, int* fix_count, int2* fix_list,
+                         int fix_cap, double* totals, double* per_point, double* counts,
+                         hipStream_t stream)
+{
+    const int nb = (int)(m->npad / TILE);
+    const float* pts = (const float*)m->pts;
+    const double* nn = (const double*)m->nn;
+    hipError_t e;
+    if (!m->nn_ready) {
+        hipLaunchKernelGGL((k_nn<DX, DY>), dim3(nb), dim3(TILE), 0, stream, pts, (int)m->n,
+                           (double*)m->nn, (int)m->npad);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const int tiles = (ga.gxp / 16) * (ga.gyp / 16);
+    hipLaunchKernelGGL((k_loo_grid<DX, DY>), dim3((unsigned)(m->npad / 32), (unsigned)tiles),
+                       dim3(TILE), 0, stream, pts, nn, (int)m->n, (int)m->npad, ga, numbuf, denbuf);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int G = ga.gx * ga.gy;
+    hipLaunchKernelGGL(k_grid_finalize, dim3((unsigned)((m->n + 255) / 256), (unsigned)G), dim3(256),
+                       0, stream, (const double*)numbuf, (const double*)denbuf, nn, (int)m->n,
+                       (int)m->npad, gf, crit, ell, fix_count, fix_list, fix_cap);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_grid_fixup<DX, DY>), dim3(1024), dim3(TILE), 0, stream, pts, nn, (int)m->n,
+                       (int)m->npad, ga, gf, crit, (const double*)denbuf, ell,
+                       (const int*)fix_count, (const int2*)fix_list, fix_cap);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grid_rows, dim3((unsigned)G), dim3(256), 0, stream, (const double*)ell,
+                       (int)m->n, (int)m->npad, totals, per_point, counts);
+    return hipGetLastError();
+}
+
+#define CDE_GRID_CASE(DX_, DY_)                                                                 \
+    case (DX_) * 8 + (DY_):                                                                     \
+        return grid_t<DX_, DY_>(m, ga, gf, crit, numbuf, denbuf, ell, fix_count, fix_list, fix_cap, \
+                                totals, per_point, counts, stream);
+
+// Zero a small int buffer with a kernel (no memset node, so a caller may
+// capture the sequence in a graph).
+__global__ void k_zero_int(int* p, int cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) p[i] = 0;
+}
+
+hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* hy, int n_hy, int crit,
+                       double* totals, double* per_point, void* work, size_t work_bytes,
+                       double* counts, hipStream_t stream)
+{
+    GridArgs ga;
+    GridFin gf;
+    ga.gx = gf.gx = n_hx;
+    ga.gy = gf.gy = n_hy;
+    ga.gxp = (n_hx + 15) / 16 * 16;
+    ga.gyp = (n_hy + 15) / 16 * 16;
+    for (int a = 0; a < 64; ++a) {
+        const double h = hx[a < n_hx ? a : n_hx - 1];
+        ga.cx[a] = (float)(LOG2E / (2.0 * h * h));
+        gf.cxa[a] = (double)ga.cx[a];
+        gf.log_cx[a] = -m->dx * (log(h) + HALF_LOG_2PI);
+    }
+    for (int b = 0; b < 64; ++b) {
+        const double h = hy[b < n_hy ? b : n_hy - 1];
+        ga.cy[b] = (float)(LOG2E / (2.0 * h * h));
+        gf.cyb[b] = (double)ga.cy[b];
+        gf.log_cy[b] = -m->dy * (log(h) + HALF_LOG_2PI);
+    }
+    const size_t G = (size_t)n_hx * n_hy;
+    // work layout: numbuf [G][npad] | denbuf [gx][npad] | ell [G][npad] | fix_count | fix_list
+    double* numbuf = (double*)work;
+    double* denbuf = numbuf + G * m->npad;
+    double* ell = denbuf + (size_t)n_hx * m->npad;
+    int* fix_count = (int*)(ell + G * m->npad);
+    int2* fix_list = (int2*)(fix_count + 64);
+    const size_t used = (size_t)((char*)fix_list - (char*)work);
+    if (used >= work_bytes) return hipErrorInvalidValue;
+    const int fix_cap = (int)std::min<size_t>((work_bytes - used) / sizeof(int2), size_t(1) << 30);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, fix_count, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (m->dx * 8 + m->dy) {
+        CDE_GRID_CASE(1, 1) CDE_GRID_CASE(1, 2) CDE_GRID_CASE(2, 1) CDE_GRID_CASE(2, 2)
+        CDE_GRID_CASE(3, 1) CDE_GRID_CASE(3, 2) CDE_GRID_CASE(4, 1) CDE_GRID_CASE(4, 2)
+        CDE_GRID_CASE(5, 1) CDE_GRID_CASE(5, 2) CDE_GRID_CASE(6, 1) CDE_GRID_CASE(6, 2)
+        CDE_GRID_CASE(7, 1) CDE_GRID_CASE(7, 2) CDE_GRID_CASE(8, 1) CDE_GRID_CASE(8, 2)
+        CDE_GRID_CASE(16, 1) CDE_GRID_CASE(16, 2)
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t grid_work_bytes(const cde_model* m, int n_hx, int n_hy)
+{
+    const size_t G = (size_t)n_hx * n_hy;
+    const size_t fix_cap = std::max<size_t>(G * m->npad / 8, 1 << 20);  // 1/8 of all entries
+    return sizeof(double) * (2 * G + n_hx) * m->npad + 64 * sizeof(int) + fix_cap * sizeof(int2);
+}
+
+}  // namespace cde

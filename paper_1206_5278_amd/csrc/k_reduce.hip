@@ -88,4 +88,10 @@ hipError_t launch_reduce_parts(const double* part, int nsets, int nblocks, int n
     return hipGetLastError();
 }
 
+hipError_t launch_sum_counts(const double* counts, int nsets, int64_t* out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1), 0, stream, counts, nsets, out);
+    return hipGetLastError();
+}
+
 }  // namespace cde

@@ -1,0 +1,113 @@
+"""GPU parity of the scalar-bandwidth grid path (MFMA kernel on FP32 models)
+against the FP64 oracle evaluated setting by setting, through the C ABI."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+NT = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def cde():
+    import paper_1206_5278_amd as m
+    return m
+
+
+def run_grid(x, y, hx, hy, crit="cond"):
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    tot, pp, nonfin = m.loo_grid(hx, hy, crit, per_point=True)
+    ref = oracle.loo_grid(xo, yo, hx, hy, crit, nthreads=NT)
+    return m, tot.cpu().numpy(), pp.cpu().numpy(), int(nonfin.item()), ref
+
+
+def check(tot, pp, ref):
+    P.assert_points(pp, ref)
+    for s in range(ref.shape[0]):
+        P.assert_total(float(tot[s]), oracle.total(ref[s]), ref[s])
+
+
+SHAPES = [(dx, dy) for dx in (1, 2, 3, 4, 5, 6, 7, 8, 16) for dy in (1, 2)]
+
+
+@pytest.mark.parametrize("dx,dy", SHAPES)
+def test_grid_all_shapes_padded_grid(dx, dy):
+    print(f"case: grid shape dx={dx} dy={dy} n=300 grid 5x7", flush=True)
+    v = workloads.gmm_general(300, dx + dy, seed=100 + dx * 10 + dy)
+    hx = workloads.geomspace(0.2, 3.0, 5)
+    hy = workloads.geomspace(0.1, 2.0, 7)
+    _, tot, pp, nonfin, ref = run_grid(v[:, :dx], v[:, dx:], hx, hy)
+    assert nonfin == 0
+    check(tot, pp, ref)
+
+
+@pytest.mark.parametrize("crit", ["cond", "joint"])
+def test_grid_ragged_16x16(crit):
+    print(f"case: grid ragged n=700 16x16 {crit}", flush=True)
+    x, y = workloads.gmm(700, seed=21)
+    hx = hy = workloads.geomspace(0.05, 5.0, 16)
+    _, tot, pp, nonfin, ref = run_grid(x, y, hx, hy, crit)
+    assert nonfin == 0
+    check(tot, pp, ref)
+
+
+def test_grid_32x32_small_n():
+    print("case: grid n=1100 32x32", flush=True)
+    x, y = workloads.gmm(1100, seed=22)
+    hx = hy = workloads.geomspace(0.05, 5.0, 32)
+    _, tot, pp, nonfin, ref = run_grid(x, y, hx, hy)
+    assert nonfin == 0
+    check(tot, pp, ref)
+
+
+def test_grid_tiny_bandwidths_wide_range_and_fixup():
+    # Largest terms hundreds to thousands of binary orders below the
+    # neighbour shifts: exercises the wide-range kernel values and the exact
+    # per-entry recomputation.
+    print("case: grid tiny bandwidths", flush=True)
+    x, y = workloads.gmm(500, seed=23, dx=2)
+    hx = [1e-3, 3e-3, 1e-2, 0.05]
+    hy = [1e-3, 4e-3, 0.02]
+    _, tot, pp, nonfin, ref = run_grid(x, y, hx, hy)
+    assert nonfin == 0
+    assert np.min(ref) < -1000.0  # the regime is really extreme
+    check(tot, pp, ref)
+
+
+def test_grid_deterministic_and_reused_shifts():
+    print("case: grid determinism", flush=True)
+    x, y = workloads.gmm(2000, seed=24, dx=3)
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    hx = hy = workloads.geomspace(0.1, 3.0, 12)
+    a = m.loo_grid(hx, hy, per_point=True)
+    b = m.loo_grid(hx, hy, per_point=True)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    # a second, different grid on the same model reuses the neighbour shifts
+    hx2 = workloads.geomspace(0.3, 1.0, 3)
+    t2, pp2, _ = m.loo_grid(hx2, [0.2, 0.4], per_point=True)
+    ref = oracle.loo_grid(xo, yo, hx2, [0.2, 0.4], nthreads=NT)
+    P.assert_points(pp2.cpu().numpy(), ref)
+
+
+def test_grid_highdim_subset_16x16():
+    print("case: highdim subset n=3000 16x16 grid (dx=16, dy=2)", flush=True)
+    x, y = workloads.highdim(3000, seed=5)
+    hx, hy = workloads.WORKLOADS["highdim"]["grid"]
+    _, tot, pp, nonfin, ref = run_grid(x, y, hx, hy)
+    assert nonfin == 0
+    check(tot, pp, ref)
+    # grid argmax agrees with the oracle's
+    assert int(np.argmax(tot)) == int(np.argmax(oracle.totals(ref)))
