@@ -1,0 +1,123 @@
+"""Serving benchmark: continuous batching vs one request per launch.
+
+Open-loop Poisson arrivals (default 200 req/s): 70% conditional-density
+queries (1..4096 query points, 256-point y grid) against 8 resident training
+sets, 30% bandwidth-selection jobs (N log-uniform in [1k, 200k], dx in 1..8,
+dy = 1, 16 x 16 grid) on their own data.  Both servers receive the same
+seeded request list; the script reports throughput, p50/p99 latency (of the
+completed requests and per kind) and whether every result is bit-identical
+between the two (each result alone vs in the mix).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import copy
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def build_requests(stream, sets, seed=0, n_cap=None):
+    """Materialise workloads.serve_stream descriptors: job data drawn like the
+    10-component mixture workload; query points are resident training points
+    plus small noise."""
+    import numpy as np
+
+    import workloads
+    from paper_1206_5278_amd.serve import ServeRequest
+    rng = np.random.default_rng(seed)
+    g = tuple(workloads.geomspace(0.05, 5.0, 16))
+    out = []
+    for d in stream:
+        if d.kind == "job":
+            n = d.n if n_cap is None else min(d.n, n_cap)
+            x, y = workloads.gmm(n, seed=d.seed, dx=d.dx)
+            out.append(ServeRequest(d.rid, "job", d.t_arrive, x=x.astype(np.float32),
+                                    y=y.astype(np.float32), hx=g, hy=g))
+        else:
+            xs = sets[d.set_id][0]
+            idx = rng.integers(0, xs.shape[0], size=d.q)
+            xq = xs[idx] + 0.05 * rng.standard_normal((d.q, xs.shape[1]))
+            out.append(ServeRequest(d.rid, "query", d.t_arrive, set_id=d.set_id,
+                                    xq=xq.astype(np.float32)))
+    return out
+
+
+def job_pairs(r):
+    n = r.x.shape[0]
+    return float(n) * (n - 1) * len(r.hx) * len(r.hy)
+
+
+def run_mode(executor, reqs, batched, budget, deadline):
+    from paper_1206_5278_amd.serve import Scheduler
+    s = Scheduler(executor, hbm_budget=budget, max_active=64, batched=batched)
+    s.submit_all(reqs)
+    t0 = time.perf_counter()
+    s.run(deadline=deadline)
+    wall = time.perf_counter() - t0
+    rep = s.report(wall)
+    done = [r for r in s.completed if r.error is None]
+    rep["job_pair_evals_per_s"] = sum(job_pairs(r) for r in done if r.kind == "job") / max(
+        rep["makespan_s"], 1e-9)
+    rep["wall_s"] = wall
+    return rep, {r.rid: r.result for r in done}
+
+
+def same(a, b):
+    import numpy as np
+    if isinstance(a, dict):
+        return np.array_equal(a["totals"], b["totals"]) and a["argmax"] == b["argmax"]
+    return np.array_equal(a, b)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--duration", type=float, default=10.0)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--n-cap", type=int, default=None, help="cap job sizes (smoke runs)")
+    ap.add_argument("--budget-gb", type=float, default=96.0)
+    ap.add_argument("--deadline", type=float, default=600.0)
+    args = ap.parse_args()
+
+    import workloads
+    from paper_1206_5278_amd.serve import GpuExecutor
+
+    sets = workloads.resident_sets(8, seed=args.seed)
+    stream = workloads.serve_stream(rate=args.rate, duration=args.duration, seed=args.seed)
+    reqs = build_requests(stream, sets, seed=args.seed, n_cap=args.n_cap)
+    ex = GpuExecutor(sets)
+    budget = int(args.budget_gb * (1 << 30))
+    # warm-up: one small job and one query through every code path
+    run_mode(ex, copy.deepcopy(reqs[:4]), True, budget, 60.0)
+
+    res = {}
+    results = {}
+    for mode, batched in (("plain", False), ("batched", True)):
+        rep, out = run_mode(ex, copy.deepcopy(reqs), batched, budget, args.deadline)
+        res[mode] = rep
+        results[mode] = out
+        print(f"{mode}: {json.dumps(rep)}", file=sys.stderr, flush=True)
+    common = set(results["plain"]) & set(results["batched"])
+    identical = all(same(results["plain"][k], results["batched"][k]) for k in common)
+    n_jobs = sum(1 for r in reqs if r.kind == "job")
+    offered = sum(job_pairs(r) for r in reqs if r.kind == "job") / args.duration
+    out = {
+        "metric": "serving throughput and p50/p99 latency, continuous batching vs one request per launch",
+        "rate_req_s": args.rate, "duration_s": args.duration, "requests": len(reqs), "jobs": n_jobs,
+        "queries": len(reqs) - n_jobs, "offered_job_pair_evals_per_s": offered,
+        "plain": res["plain"], "batched": res["batched"],
+        "throughput_ratio": res["batched"]["throughput_req_s"] / max(res["plain"]["throughput_req_s"], 1e-9),
+        "results_identical_alone_vs_mixed": identical, "compared": len(common),
+        "data": "synthetic", "dtype": "f32 kernel values, f64 accumulation",
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

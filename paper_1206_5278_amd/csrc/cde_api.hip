@@ -322,11 +322,11 @@ cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const 
             e = launch_query<double>(m, (const double*)xq_dev, q, (const double*)ygrid_dev, k, sets,
                                      f_dev, s);
         } else {
-            DiagSets<float> sets;
-            std::memset(&sets, 0, sizeof sets);
-            fill_set(sets.s[0], h, m->dx, m->dy);
-            e = launch_query<float>(m, (const float*)xq_dev, q, (const float*)ygrid_dev, k, sets,
-                                    f_dev, s);
+            if (q >= (int64_t(1) << 31) - 64) return fail(CDE_EUNSUPPORTED, "cde_density_query: q >= 2^31");
+            cde_status st = ensure_scratch(m, sizeof(double) * (size_t)(q + k) + 256);
+            if (st != CDE_OK) return st;
+            e = launch_query_mfma(m, (const float*)xq_dev, (int)q, (const float*)ygrid_dev, (int)k, h,
+                                  f_dev, (double*)m->scratch, s);
         }
         if (e != hipSuccess) return hip_fail(e, "launch k_query");
         return CDE_OK;

@@ -20,6 +20,11 @@ template <typename T>
 hipError_t launch_query(const cde_model* m, const T* xq, int64_t q, const T* yg, int64_t k,
                         const DiagSets<T>& sets, double* f, hipStream_t stream);
 
+// Density queries on FP32 models, on the matrix cores: f [q][k]; `work`
+// holds q + k doubles (per-query and per-grid-point shifts).
+hipError_t launch_query_mfma(const cde_model* m, const float* xq, int q, const float* yg, int k,
+                             const double* h, double* f, double* work, hipStream_t stream);
+
 // Scalar-bandwidth grid on FP32 models: per-point neighbour shifts (first
 // call only), the MFMA grid pass, FP64 finalisation, exact fixup of extreme
 // entries and the fixed-order row sums.  `work` must hold grid_work_bytes();

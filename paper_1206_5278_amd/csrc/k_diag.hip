@@ -272,9 +272,10 @@ __global__ __launch_bounds__(TILE) void k_loo_diag(const T* __restrict__ pts, in
     }
 }
 
-// Conditional density queries, eq. (1) over all n training points (no point
-// left out): lane e of the flattened [q][k] output evaluates f(yg | xq) with
-// the same shifted sums as the LOO pass, so den' >= 1 and num' >= 1 hold.
+// Conditional density queries on FP64 models, eq. (1) over all n training
+// points (no point left out): lane e of the flattened [q][k] output evaluates
+// f(yg | xq) with the same shifted sums as the LOO pass, so den' >= 1 and
+// num' >= 1 hold.  (FP32 models use the matrix-core kernel of k_query.hip.)
 template <typename T, int DX, int DY>
 __global__ __launch_bounds__(TILE) void k_query(const T* __restrict__ pts, int n,
                                                 const T* __restrict__ xq,

@@ -205,3 +205,34 @@ def test_query_parity_and_normalisation():
     # the estimate integrates to ~1 over a grid wide enough to hold the mass
     integ = np.trapezoid(f, yg, axis=1)
     assert np.all(np.abs(integ - 1) < 2e-3)
+
+
+@pytest.mark.parametrize("dx,dy", DIMS)
+def test_query_all_shapes(dx, dy):
+    # FP32 models: matrix-core query kernel; k = 150 spans two 128-point chunks
+    # and q = 70 two 64-query blocks with ragged tails.
+    say(f"case: query shape dx={dx} dy={dy}")
+    v = workloads.gmm_general(400, dx + dy, seed=200 + dx * 10 + dy)
+    x, y = v[:, :dx], v[:, dx:]
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    h = list(np.linspace(0.7, 1.2, dx)) + list(np.linspace(0.3, 0.5, dy))
+    rng = np.random.default_rng(dx * 7 + dy)
+    xq = (xo[rng.choice(400, 70)] + 0.1 * rng.normal(size=(70, dx))).astype(np.float32).astype(np.float64)
+    yg = (yo[rng.choice(400, 150)] + 0.2 * rng.normal(size=(150, dy))).astype(np.float32).astype(np.float64)
+    f = m.query(P.to_dev(xq), P.to_dev(yg), h).cpu().numpy()
+    ref = oracle.density(xo, yo, h, xq, yg, nthreads=NT)
+    peak = ref.max(axis=1, keepdims=True)
+    err = np.abs(f - ref)
+    assert np.all(err <= 1e-5 * ref + 1e-7 * peak), float(np.max(err / (1e-5 * ref + 1e-7 * peak)))
+
+
+def test_query_fp64_model():
+    say("case: query fp64 model")
+    x, y = workloads.tiny(500, seed=4)
+    m = cde().Model(P.to_dev(x, torch.float64), P.to_dev(y, torch.float64))
+    xq = np.linspace(0, 100, 9).reshape(-1, 1)
+    yg = np.linspace(0, 100, 41).reshape(-1, 1)
+    f = m.query(P.to_dev(xq, torch.float64), P.to_dev(yg, torch.float64), [4.0, 5.0]).cpu().numpy()
+    ref = oracle.density(x, y, [4.0, 5.0], xq, yg, nthreads=NT)
+    np.testing.assert_allclose(f, ref, rtol=1e-10, atol=1e-300)
