@@ -186,7 +186,7 @@ cde_status cde_destroy(cde_model* m)
     if (!m) return CDE_OK;
     DeviceGuard guard(m->device);
     cde_status st = CDE_OK;
-    for (void* p : {m->pts, m->nn, m->scratch}) {
+    for (void* p : {m->pts, m->nn, m->xmean, m->scratch}) {
         if (!p) continue;
         hipError_t e = hipFree(p);
         if (e != hipSuccess && st == CDE_OK) st = hip_fail(e, "hipFree");
@@ -234,10 +234,11 @@ cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const do
             return fail(CDE_EINVAL, "cde_loo_loglik: bandwidths must be finite and > 0");
         if (criterion != CDE_COND && criterion != CDE_JOINT)
             return fail(CDE_EINVAL, "cde_loo_loglik: unknown criterion");
-        if (xterm == CDE_XTERM_MFMA_BF16X3)
-            return fail(CDE_EUNSUPPORTED, "cde_loo_loglik: the MFMA cross-term path is not built");
-        if (xterm != CDE_XTERM_AUTO && xterm != CDE_XTERM_VALU)
+        if (xterm != CDE_XTERM_AUTO && xterm != CDE_XTERM_VALU && xterm != CDE_XTERM_MFMA_BF16X3)
             return fail(CDE_EINVAL, "cde_loo_loglik: unknown xterm");
+        const bool xt = xterm == CDE_XTERM_MFMA_BF16X3;
+        if (xt && (m->dx < 16 || m->prec != CDE_F32))
+            return fail(CDE_EUNSUPPORTED, "cde_loo_loglik: the MFMA cross term needs dx >= 16 and FP32 data");
         DeviceGuard guard(m->device);
         hipStream_t s = (hipStream_t)stream;
         const int g = n_hx * n_hy;
@@ -260,11 +261,19 @@ cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const do
             }
             m->bytes += sizeof(double) * 2 * (size_t)m->npad;
         }
+        if (xt && !m->xmean) {
+            hipError_t e = hipMalloc(&m->xmean, 16 * sizeof(float));
+            if (e != hipSuccess) {
+                m->xmean = nullptr;
+                return hip_fail(e, "hipMalloc(column means)");
+            }
+            m->bytes += 16 * sizeof(float);
+        }
         const size_t wb = grid_work_bytes(m, n_hx, n_hy);
         cde_status st = ensure_scratch(m, wb + sizeof(double) * (size_t)g + 256);
         if (st != CDE_OK) return st;
         double* counts = (double*)((char*)m->scratch + wb);
-        hipError_t e = launch_grid(m, hx, n_hx, hy, n_hy, criterion, totals_dev, per_point_dev,
+        hipError_t e = launch_grid(m, hx, n_hx, hy, n_hy, criterion, xt, totals_dev, per_point_dev,
                                    m->scratch, wb, counts, s);
         if (e != hipSuccess) return hip_fail(e, "launch grid kernels");
         m->nn_ready = true;

@@ -53,6 +53,8 @@ struct cde_model {
     // in x and in y separately; computed once, used as the grid kernel's shifts
     void* nn = nullptr;      // [2][npad] doubles (FP32 models, grid path)
     bool nn_ready = false;
+    void* xmean = nullptr;   // [16] floats: column means of x (cross-term option)
+    bool xmean_ready = false;
     void* scratch = nullptr; // block partials and flags
     size_t scratch_bytes = 0;
     size_t bytes = 0;

@@ -30,7 +30,7 @@ hipError_t launch_query_mfma(const cde_model* m, const float* xq, int q, const f
 // entries and the fixed-order row sums.  `work` must hold grid_work_bytes();
 // `counts` receives the per-setting non-finite counts [n_hx * n_hy].
 hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* hy, int n_hy, int crit,
-                       double* totals, double* per_point, void* work, size_t work_bytes,
+                       bool xt, double* totals, double* per_point, void* work, size_t work_bytes,
                        double* counts, hipStream_t stream);
 size_t grid_work_bytes(const cde_model* m, int n_hx, int n_hy);
 

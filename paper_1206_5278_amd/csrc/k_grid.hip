@@ -28,6 +28,15 @@
 // shifted num' is below 2^-1000 is recomputed exactly by k_grid_fixup with a
 // per-entry shift.
 //
+// Cross-term option (dx = 16, CDE_XTERM_MFMA_BF16X3): the x-distances are
+// formed as |u_i|^2 + |u_j|^2 - 2 u_i.u_j on coordinates centred by the data
+// mean, with the cross term u_i.u_j of each wave's 8 points against a whole
+// 256-point j-tile computed on the matrix cores as a split-bf16 product
+// (u = hi + lo in bf16; hi.hi + hi.lo + lo.hi accumulated in FP32 by
+// v_mfma_f32_16x16x16_bf16) and staged in LDS.  This trades the 16 FP64
+// differences per pair for an approximation whose error grows with |u|^2 /
+// h^2; it is reported against the oracle, not gated.
+//
 // Work decomposition: a 256-lane block owns 32 points (8 per wave) and one
 // 16 x 16 tile of the (padded) grid (blockIdx.y); j streams through LDS in
 // 256-point tiles.  Lane l of a wave forms the distance of point i0 + l%8 to
@@ -157,14 +166,38 @@ struct GridArgs {
     int gxp, gyp;  // padded to multiples of 16
 };
 
-template <int DX, int DY>
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float v)
+{
+    return __builtin_bit_cast(short, (__bf16)v);
+}
+
+// Split-bf16 operand halves of four consecutive centred coordinates.
+__device__ __forceinline__ void split4(const float* x, const float* mean, v4s& hi, v4s& lo)
+{
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float u = x[e] - mean[e];
+        const __bf16 h = (__bf16)u;
+        hi[e] = __builtin_bit_cast(short, h);
+        lo[e] = bf16_bits(u - (float)h);
+    }
+}
+
+template <int DX, int DY, bool XT>
 __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts,
                                                    const double* __restrict__ nn, int n, int npad,
-                                                   GridArgs ga, double* __restrict__ numbuf,
+                                                   GridArgs ga, const float* __restrict__ xmean,
+                                                   double* __restrict__ numbuf,
                                                    double* __restrict__ denbuf)
 {
     constexpr int S = row_stride(DX, DY);
+    static_assert(!XT || DX == 16, "the MFMA cross term is built for dx = 16");
     __shared__ float tile[TILE * S];
+    __shared__ float jnorm[XT ? TILE : 1];
+    __shared__ float xcross[XT ? 4 * 8 * TILE : 1];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -180,6 +213,23 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
     double own[S];
     own_f64<S>(own, pts + (size_t)di * S);
     const double m_i = nn[di], my_i = nn[npad + di];
+    // cross-term operands of this wave's points (B of the bf16 MFMA: point
+    // i0 + (lane%16)%8, dimensions 4*(lane/16) .. +3) and the own norm
+    float mean[XT ? DX : 1];
+    v4s bhi, blo;
+    float inorm = 0.f;
+    if constexpr (XT) {
+#pragma unroll
+        for (int k = 0; k < DX; ++k) mean[k] = xmean[k];
+        float xb[S];
+        load_row<S>(xb, pts + (size_t)(i0 + (lane & 7)) * S);
+        split4(xb + 4 * (lane >> 4), mean + 4 * (lane >> 4), bhi, blo);
+#pragma unroll
+        for (int k = 0; k < DX; ++k) {
+            const float u = (float)own[k] - mean[k];
+            inorm = fma_(u, u, inorm);
+        }
+    }
     // MFMA role: row a = ab*16 + lane%16 of A, column b = bb*16 + lane%16 of B
     const float ca = ga.cx[ab * 16 + (lane & 15)];
     const float cb = ga.cy[bb * 16 + (lane & 15)];
@@ -203,12 +253,52 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
         const int base = t * TILE;
         const int cnt = min(TILE, n - base);
         const int ngroups = (cnt + 7) >> 3;
+        if constexpr (XT) {
+            // norms of the tile's centred points (one per thread)
+            float nj = 0.f;
+#pragma unroll
+            for (int k = 0; k < DX; ++k) {
+                const float u = tile[tid * S + k] - mean[k];
+                nj = fma_(u, u, nj);
+            }
+            jnorm[tid] = nj;
+            // cross terms of this wave's 8 points against the 256 tile rows:
+            // A = tile rows jb*16 + lane%16 (dims 4*(lane/16)..), B = own points
+            float* xc = xcross + wave * 8 * TILE;
+            for (int jb = 0; jb < TILE / 16; ++jb) {
+                v4s ahi, alo;
+                split4(tile + (jb * 16 + (lane & 15)) * S + 4 * (lane >> 4), mean + 4 * (lane >> 4),
+                       ahi, alo);
+                v4f c = {0.f, 0.f, 0.f, 0.f};
+                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, c, 0, 0, 0);
+                // c[r]: row jb*16 + 4*(lane/16) + r, point column lane%16
+                if ((lane & 15) < 8) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) xc[(lane & 7) * TILE + jb * 16 + 4 * (lane >> 4) + r] = c[r];
+                }
+            }
+            __syncthreads();
+        }
         for (int g = 0; g < ngroups; ++g) {
             const int jj = g * 8 + jo;
             float pj[S];
             load_row<S>(pj, tile + jj * S);  // rows >= cnt hold packed padding (in bounds)
             double d2x, d2y;
-            dist2<DX, DY>(own, pj, d2x, d2y);
+            if constexpr (XT) {
+                const float cr = xcross[wave * 8 * TILE + (lane & 7) * TILE + jj];
+                d2x = (double)((inorm + jnorm[jj]) - 2.f * cr);
+                double f = 0.0;
+#pragma unroll
+                for (int l = 0; l < DY; ++l) {
+                    const double d = own[DX + l] - (double)pj[DX + l];
+                    f = fma_(d, d, f);
+                }
+                d2y = f;
+            } else {
+                dist2<DX, DY>(own, pj, d2x, d2y);
+            }
             // shifted distances, rounded to FP32 only after the subtraction
             float xa = (float)(d2x - m_i), ya = (float)(d2y - my_i);
             if (jj >= cnt || base + jj == di) {
@@ -382,9 +472,9 @@ __global__ __launch_bounds__(256) void k_grid_rows(const double* __restrict__ el
 
 template <int DX, int DY>
 static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& gf, int crit,
-                         double* numbuf, double* denbuf, double* ell, int* fix_count, int2* fix_list,
-                         int fix_cap, double* totals, double* per_point, double* counts,
-                         hipStream_t stream)
+                         bool xt, double* numbuf, double* denbuf, double* ell, int* fix_count,
+                         int2* fix_list, int fix_cap, double* totals, double* per_point,
+                         double* counts, hipStream_t stream)
 {
     const int nb = (int)(m->npad / TILE);
     const float* pts = (const float*)m->pts;
@@ -396,8 +486,20 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const int tiles = (ga.gxp / 16) * (ga.gyp / 16);
-    hipLaunchKernelGGL((k_loo_grid<DX, DY>), dim3((unsigned)(m->npad / 32), (unsigned)tiles),
-                       dim3(TILE), 0, stream, pts, nn, (int)m->n, (int)m->npad, ga, numbuf, denbuf);
+    const dim3 grid((unsigned)(m->npad / 32), (unsigned)tiles);
+    const float* xmean = (const float*)m->xmean;
+    if constexpr (DX == 16) {
+        if (xt)
+            hipLaunchKernelGGL((k_loo_grid<DX, DY, true>), grid, dim3(TILE), 0, stream, pts, nn,
+                               (int)m->n, (int)m->npad, ga, xmean, numbuf, denbuf);
+        else
+            hipLaunchKernelGGL((k_loo_grid<DX, DY, false>), grid, dim3(TILE), 0, stream, pts, nn,
+                               (int)m->n, (int)m->npad, ga, xmean, numbuf, denbuf);
+    } else {
+        if (xt) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_loo_grid<DX, DY, false>), grid, dim3(TILE), 0, stream, pts, nn,
+                           (int)m->n, (int)m->npad, ga, xmean, numbuf, denbuf);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int G = ga.gx * ga.gy;
     hipLaunchKernelGGL(k_grid_finalize, dim3((unsigned)((m->n + 255) / 256), (unsigned)G), dim3(256),
@@ -415,8 +517,8 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
 
 #define CDE_GRID_CASE(DX_, DY_)                                                                 \
     case (DX_) * 8 + (DY_):                                                                     \
-        return grid_t<DX_, DY_>(m, ga, gf, crit, numbuf, denbuf, ell, fix_count, fix_list, fix_cap, \
-                                totals, per_point, counts, stream);
+        return grid_t<DX_, DY_>(m, ga, gf, crit, xt, numbuf, denbuf, ell, fix_count, fix_list,   \
+                                fix_cap, totals, per_point, counts, stream);
 
 // Zero a small int buffer with a kernel (no memset node, so a caller may
 // capture the sequence in a graph).
@@ -426,10 +528,29 @@ __global__ void k_zero_int(int* p, int cnt)
     if (i < cnt) p[i] = 0;
 }
 
+// Column means of x (FP64 accumulation in a fixed order, one thread per
+// dimension), stored as FP32: the centring of the cross-term option.
+__global__ void k_colmean(const float* __restrict__ pts, int n, int dx, int stride,
+                          float* __restrict__ mean)
+{
+    const int k = threadIdx.x;
+    if (k >= dx) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += (double)pts[(size_t)i * stride + k];
+    mean[k] = (float)(s / n);
+}
+
 hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* hy, int n_hy, int crit,
-                       double* totals, double* per_point, void* work, size_t work_bytes,
+                       bool xt, double* totals, double* per_point, void* work, size_t work_bytes,
                        double* counts, hipStream_t stream)
 {
+    if (xt && !m->xmean_ready) {
+        hipLaunchKernelGGL(k_colmean, dim3(1), dim3(64), 0, stream, (const float*)m->pts, (int)m->n,
+                           m->dx, m->stride, (float*)m->xmean);
+        hipError_t e0 = hipGetLastError();
+        if (e0 != hipSuccess) return e0;
+        m->xmean_ready = true;
+    }
     GridArgs ga;
     GridFin gf;
     ga.gx = gf.gx = n_hx;

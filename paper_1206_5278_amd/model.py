@@ -91,7 +91,7 @@ class Model:
 
     # ------------------------------------------------------------- the calls
     def loo_grid(self, hx, hy, criterion: str = "cond", per_point: bool = False,
-                 stream=None, out=None):
+                 stream=None, out=None, xterm: int = B.CDE_XTERM_AUTO):
         """Exact LOO log-likelihood totals over the scalar grid hx x hy.
 
         Returns (totals [len(hx)*len(hy)] float64 on the device, hx-major;
@@ -103,7 +103,7 @@ class Model:
         pp = torch.empty((g, self.n), dtype=torch.float64, device=self.device) if per_point else None
         nonfin = torch.empty(1, dtype=torch.int64, device=self.device)
         st = self._lib.cde_loo_loglik(self._h, B.doubles(hx), len(hx), B.doubles(hy), len(hy),
-                                      CRITERIA[criterion], B.CDE_XTERM_AUTO, totals.data_ptr(),
+                                      CRITERIA[criterion], int(xterm), totals.data_ptr(),
                                       pp.data_ptr() if pp is not None else None, nonfin.data_ptr(),
                                       _stream_ptr(stream))
         B.check(st, "cde_loo_loglik")

@@ -111,3 +111,30 @@ def test_grid_highdim_subset_16x16():
     check(tot, pp, ref)
     # grid argmax agrees with the oracle's
     assert int(np.argmax(tot)) == int(np.argmax(oracle.totals(ref)))
+
+
+def test_grid_mfma_bf16x3_cross_term_reported():
+    # dx = 16 cross term on the matrix cores (split-bf16 x3): an approximation
+    # whose error is reported; the check here is a sanity bound plus the
+    # exact VALU path on the same model.
+    print("case: highdim subset n=2000 16x16 grid, bf16x3 cross term", flush=True)
+    x, y = workloads.highdim(2000, seed=6)
+    hx, hy = workloads.WORKLOADS["highdim"]["grid"]
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    from paper_1206_5278_amd import _binding as B
+    tot_x, pp_x, nf = m.loo_grid(hx, hy, per_point=True, xterm=B.CDE_XTERM_MFMA_BF16X3)
+    tot_v, pp_v, _ = m.loo_grid(hx, hy, per_point=True)
+    ref = oracle.loo_grid(xo, yo, hx, hy, nthreads=NT)
+    P.assert_points(pp_v.cpu().numpy(), ref)  # exact path unchanged
+    assert int(nf.item()) == 0
+    ex = pp_x.cpu().numpy()
+    err = np.abs(ex - ref) / np.maximum(1.0, np.abs(ref))
+    rt = oracle.totals(ref)
+    terr = np.abs(tot_x.cpu().numpy() - rt) / np.abs(rt)
+    print(f"bf16x3 cross term: per-point rel err max {err.max():.3e} median {np.median(err):.3e}; "
+          f"total rel err max {terr.max():.3e} (largest hx: {terr.reshape(16, 16)[-1].max():.3e})",
+          flush=True)
+    assert np.all(np.isfinite(ex))
+    # at the widest bandwidth the approximation is tight
+    assert terr.reshape(16, 16)[-1, -1] < 1e-3
