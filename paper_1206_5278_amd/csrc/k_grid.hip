@@ -191,7 +191,9 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
                                                    const double* __restrict__ nn, int n, int npad,
                                                    GridArgs ga, const float* __restrict__ xmean,
                                                    double* __restrict__ numbuf,
-                                                   double* __restrict__ denbuf)
+                                                   double* __restrict__ denbuf,
+                                                   const int* __restrict__ plist,
+                                                   const int* __restrict__ pcount)
 {
     constexpr int S = row_stride(DX, DY);
     static_assert(!XT || DX == 16, "the MFMA cross term is built for dx = 16");
@@ -202,13 +204,24 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int i0 = blockIdx.x * 32 + wave * 8;  // this wave's 8 points
+    // this wave's 8 points: i0 .. i0+7, or list entries i0 .. i0+7 of plist
+    const int i0 = blockIdx.x * 32 + wave * 8;
+    int cnt_list = 0;
+    if (plist) {
+        cnt_list = *pcount;
+        if ((int)blockIdx.x * 32 >= cnt_list) return;  // whole block past the list (uniform)
+    }
+    auto point = [&](int q) -> int {
+        if (!plist) return i0 + q;
+        return plist[min(i0 + q, cnt_list - 1)];  // repeat the last entry in a ragged tail
+    };
+    auto point_valid = [&](int q) -> bool { return !plist || i0 + q < cnt_list; };
     const int tb = ga.gyp / 16;                 // b-tiles per row of tiles
     const int ab = blockIdx.y / tb, bb = blockIdx.y % tb;
     const bool do_den = (bb == 0);
 
     // distance role: point i0 + lane%8 against tile row group*8 + jo
-    const int di = i0 + (lane & 7);
+    const int di = point(lane & 7);
     const int jo = 4 * ((lane & 15) >> 3) + (lane >> 4);
     double own[S];
     own_f64<S>(own, pts + (size_t)di * S);
@@ -222,7 +235,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
 #pragma unroll
         for (int k = 0; k < DX; ++k) mean[k] = xmean[k];
         float xb[S];
-        load_row<S>(xb, pts + (size_t)(i0 + (lane & 7)) * S);
+        load_row<S>(xb, pts + (size_t)point(lane & 7) * S);
         split4(xb + 4 * (lane >> 4), mean + 4 * (lane >> 4), bhi, blo);
 #pragma unroll
         for (int k = 0; k < DX; ++k) {
@@ -322,12 +335,13 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
     // column lane%16 in register r of each lane.
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        const int i = i0 + q;
+        const int i = point(q);
+        const bool ok = point_valid(q);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int a = ab * 16 + (lane >> 4) + 4 * r;
             const int b = bb * 16 + (lane & 15);
-            if (a < ga.gx && b < ga.gy) numbuf[((size_t)a * ga.gy + b) * npad + i] = acc[q][r];
+            if (ok && a < ga.gx && b < ga.gy) numbuf[((size_t)a * ga.gy + b) * npad + i] = acc[q][r];
         }
     }
     if (do_den) {
@@ -336,6 +350,107 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             double v = dsum[q];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            const int a = ab * 16 + (lane & 15);
+            if (lane < 16 && a < ga.gx && point_valid(q)) denbuf[(size_t)a * npad + point(q)] = v;
+        }
+    }
+}
+
+// FP32 fast pass: the same decomposition with FP32 kernel values (plain
+// v_exp_f32), v_mfma_f32_16x16x4f32 products and sums, partial sums over a
+// 256-point j-tile folded into Kahan-compensated FP32 totals.  FP32 cannot
+// carry a cell whose shifted num' falls far below 1; k_grid_finalize flags
+// the points that have such a cell (num' < 2^-80) and those points are
+// recomputed by the FP64 kernel above.
+template <int DX, int DY>
+__global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ pts,
+                                                     const double* __restrict__ nn, int n, int npad,
+                                                     GridArgs ga, double* __restrict__ numbuf,
+                                                     double* __restrict__ denbuf)
+{
+    constexpr int S = row_stride(DX, DY);
+    __shared__ float tile[TILE * S];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i0 = blockIdx.x * 32 + wave * 8;
+    const int tb = ga.gyp / 16;
+    const int ab = blockIdx.y / tb, bb = blockIdx.y % tb;
+    const bool do_den = (bb == 0);
+    const int di = i0 + (lane & 7);
+    const int jo = 4 * ((lane & 15) >> 3) + (lane >> 4);
+    double own[S];
+    own_f64<S>(own, pts + (size_t)di * S);
+    const double m_i = nn[di], my_i = nn[npad + di];
+    const float ca = ga.cx[ab * 16 + (lane & 15)];
+    const float cb = ga.cy[bb * 16 + (lane & 15)];
+
+    v4f acc[8];
+    Kahan<float> tot[8][4], dtot[8];
+    float dpart[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+        dpart[q] = 0.f;
+        dtot[q].zero();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tot[q][r].zero();
+    }
+    const int ntiles = (n + TILE - 1) / TILE;
+    float pre[S];
+    load_row<S>(pre, pts + (size_t)tid * S);
+    for (int t = 0; t < ntiles; ++t) {
+        __syncthreads();
+        store_row<S>(tile + tid * S, pre);
+        __syncthreads();
+        if (t + 1 < ntiles) load_row<S>(pre, pts + ((size_t)(t + 1) * TILE + tid) * S);
+        const int base = t * TILE;
+        const int cnt = min(TILE, n - base);
+        const int ngroups = (cnt + 7) >> 3;
+        for (int g = 0; g < ngroups; ++g) {
+            const int jj = g * 8 + jo;
+            float pj[S];
+            load_row<S>(pj, tile + jj * S);
+            double d2x, d2y;
+            dist2<DX, DY>(own, pj, d2x, d2y);
+            float xa = (float)(d2x - m_i), ya = (float)(d2y - my_i);
+            if (jj >= cnt || base + jj == di) {
+                xa = EXCLUDED;
+                ya = EXCLUDED;
+            }
+            const int xai = __float_as_int(xa), yai = __float_as_int(ya);
+            Unroll<16>::run([&](auto c) {
+                constexpr int idx = decltype(c)::value;
+                constexpr int q = idx & 7;
+                const float ex = exp2_<float>(-(row_bcast<idx>(xai) * ca));
+                const float ey = exp2_<float>(-(row_bcast<idx>(yai) * cb));
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ex, ey, acc[q], 0, 0, 0);
+                dpart[q] += ex;
+            });
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tot[q][r].add(acc[q][r]);
+            acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+            dtot[q].add(dpart[q]);
+            dpart[q] = 0.f;
+        }
+    }
+    // f32 16x16x4 result layout: register r holds row 4*(lane/16) + r
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int a = ab * 16 + 4 * (lane >> 4) + r;
+            const int b = bb * 16 + (lane & 15);
+            if (a < ga.gx && b < ga.gy) numbuf[((size_t)a * ga.gy + b) * npad + i0 + q] = tot[q][r].value();
+        }
+    }
+    if (do_den) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            double v = dtot[q].value();
             v += __shfl_xor(v, 16, 64);
             v += __shfl_xor(v, 32, 64);
             const int a = ab * 16 + (lane & 15);
@@ -354,10 +469,13 @@ struct GridFin {
 
 // Per (setting, point) finalisation in FP64; entries whose shifted num' is
 // too small for FP32 to have carried it are queued for the exact fixup.
+// flag_points != NULL (after the FP32 pass): mark points with a cell below
+// 2^-80; otherwise queue entries below 2^-1000 for the per-entry fixup.
 __global__ void k_grid_finalize(const double* __restrict__ numbuf, const double* __restrict__ denbuf,
                                 const double* __restrict__ nn, int n, int npad, GridFin gf, int crit,
                                 double* __restrict__ ell, int* __restrict__ fix_count,
-                                int2* __restrict__ fix_list, int fix_cap)
+                                int2* __restrict__ fix_list, int fix_cap,
+                                int* __restrict__ flag_points)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int g = blockIdx.y;
@@ -373,10 +491,20 @@ __global__ void k_grid_finalize(const double* __restrict__ numbuf, const double*
         v = gf.log_cx[a] + gf.log_cy[b] + log(num) - (m * gf.cxa[a] + my * gf.cyb[b]) * LN2 -
             log((double)(n - 1));
     ell[(size_t)g * npad + i] = v;
-    if (!(num >= 0x1p-1000)) {
+    if (flag_points) {
+        if (!(num >= 0x1p-80)) flag_points[i] = 1;
+    } else if (!(num >= 0x1p-1000)) {
         const int slot = atomicAdd(fix_count, 1);
         if (slot < fix_cap) fix_list[slot] = make_int2(g, i);
     }
+}
+
+// List of flagged points (order of the list does not affect any result).
+__global__ void k_compact_points(const int* __restrict__ flag, int n, int* __restrict__ count,
+                                 int* __restrict__ list)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flag[i]) list[atomicAdd(count, 1)] = i;
 }
 
 // Exact recomputation of queued (setting, point) entries: one wave per entry,
@@ -470,56 +598,6 @@ __global__ __launch_bounds__(256) void k_grid_rows(const double* __restrict__ el
 
 // ---------------------------------------------------------------- launchers
 
-template <int DX, int DY>
-static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& gf, int crit,
-                         bool xt, double* numbuf, double* denbuf, double* ell, int* fix_count,
-                         int2* fix_list, int fix_cap, double* totals, double* per_point,
-                         double* counts, hipStream_t stream)
-{
-    const int nb = (int)(m->npad / TILE);
-    const float* pts = (const float*)m->pts;
-    const double* nn = (const double*)m->nn;
-    hipError_t e;
-    if (!m->nn_ready) {
-        hipLaunchKernelGGL((k_nn<DX, DY>), dim3(nb), dim3(TILE), 0, stream, pts, (int)m->n,
-                           (double*)m->nn, (int)m->npad);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    const int tiles = (ga.gxp / 16) * (ga.gyp / 16);
-    const dim3 grid((unsigned)(m->npad / 32), (unsigned)tiles);
-    const float* xmean = (const float*)m->xmean;
-    if constexpr (DX == 16) {
-        if (xt)
-            hipLaunchKernelGGL((k_loo_grid<DX, DY, true>), grid, dim3(TILE), 0, stream, pts, nn,
-                               (int)m->n, (int)m->npad, ga, xmean, numbuf, denbuf);
-        else
-            hipLaunchKernelGGL((k_loo_grid<DX, DY, false>), grid, dim3(TILE), 0, stream, pts, nn,
-                               (int)m->n, (int)m->npad, ga, xmean, numbuf, denbuf);
-    } else {
-        if (xt) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_loo_grid<DX, DY, false>), grid, dim3(TILE), 0, stream, pts, nn,
-                           (int)m->n, (int)m->npad, ga, xmean, numbuf, denbuf);
-    }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int G = ga.gx * ga.gy;
-    hipLaunchKernelGGL(k_grid_finalize, dim3((unsigned)((m->n + 255) / 256), (unsigned)G), dim3(256),
-                       0, stream, (const double*)numbuf, (const double*)denbuf, nn, (int)m->n,
-                       (int)m->npad, gf, crit, ell, fix_count, fix_list, fix_cap);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_grid_fixup<DX, DY>), dim3(1024), dim3(TILE), 0, stream, pts, nn, (int)m->n,
-                       (int)m->npad, ga, gf, crit, (const double*)denbuf, ell,
-                       (const int*)fix_count, (const int2*)fix_list, fix_cap);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_grid_rows, dim3((unsigned)G), dim3(256), 0, stream, (const double*)ell,
-                       (int)m->n, (int)m->npad, totals, per_point, counts);
-    return hipGetLastError();
-}
-
-#define CDE_GRID_CASE(DX_, DY_)                                                                 \
-    case (DX_) * 8 + (DY_):                                                                     \
-        return grid_t<DX_, DY_>(m, ga, gf, crit, xt, numbuf, denbuf, ell, fix_count, fix_list,   \
-                                fix_cap, totals, per_point, counts, stream);
-
 // Zero a small int buffer with a kernel (no memset node, so a caller may
 // capture the sequence in a graph).
 __global__ void k_zero_int(int* p, int cnt)
@@ -527,6 +605,83 @@ __global__ void k_zero_int(int* p, int cnt)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cnt) p[i] = 0;
 }
+
+
+// Work buffers of one grid call (carved from the caller's work area).
+struct GridWork {
+    double* numbuf;  // [G][npad]
+    double* denbuf;  // [gx][npad]
+    double* ell;     // [G][npad]
+    int* fix_count;  // [1]
+    int* flags;      // [npad] points needing the FP64 pass
+    int* plist;      // [npad] list of those points
+    int* pcount;     // [1]
+    int2* fix_list;  // [fix_cap] entries needing the per-entry recomputation
+    int fix_cap;
+};
+
+template <int DX, int DY>
+static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& gf, int crit,
+                         bool xt, const GridWork& w, double* totals, double* per_point,
+                         double* counts, hipStream_t stream)
+{
+    const int nb = (int)(m->npad / TILE);
+    const int n = (int)m->n, npad = (int)m->npad;
+    const float* pts = (const float*)m->pts;
+    const double* nn = (const double*)m->nn;
+    hipError_t e;
+    if (!m->nn_ready) {
+        hipLaunchKernelGGL((k_nn<DX, DY>), dim3(nb), dim3(TILE), 0, stream, pts, n, (double*)m->nn,
+                           npad);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const int tiles = (ga.gxp / 16) * (ga.gyp / 16);
+    const dim3 grid((unsigned)(npad / 32), (unsigned)tiles);
+    const int G = ga.gx * ga.gy;
+    const dim3 fgrid((unsigned)((n + 255) / 256), (unsigned)G);
+    const float* xmean = (const float*)m->xmean;
+    if (xt) {
+        if constexpr (DX == 16) {
+            hipLaunchKernelGGL((k_loo_grid<DX, DY, true>), grid, dim3(TILE), 0, stream, pts, nn, n,
+                               npad, ga, xmean, w.numbuf, w.denbuf, (const int*)nullptr,
+                               (const int*)nullptr);
+        } else {
+            return hipErrorInvalidValue;
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+        // FP32 pass over all points, flag points with a cell FP32 cannot carry,
+        // recompute those points on the FP64 path.
+        hipLaunchKernelGGL(k_zero_int, dim3((npad + 255) / 256), dim3(256), 0, stream, w.flags, npad);
+        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, w.pcount, 1);
+        hipLaunchKernelGGL((k_loo_grid32<DX, DY>), grid, dim3(TILE), 0, stream, pts, nn, n, npad, ga,
+                           w.numbuf, w.denbuf);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_grid_finalize, fgrid, dim3(256), 0, stream, (const double*)w.numbuf,
+                           (const double*)w.denbuf, nn, n, npad, gf, crit, w.ell, w.fix_count,
+                           w.fix_list, w.fix_cap, w.flags);
+        hipLaunchKernelGGL(k_compact_points, dim3((n + 255) / 256), dim3(256), 0, stream,
+                           (const int*)w.flags, n, w.pcount, w.plist);
+        hipLaunchKernelGGL((k_loo_grid<DX, DY, false>), grid, dim3(TILE), 0, stream, pts, nn, n, npad,
+                           ga, xmean, w.numbuf, w.denbuf, (const int*)w.plist, (const int*)w.pcount);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_grid_finalize, fgrid, dim3(256), 0, stream, (const double*)w.numbuf,
+                       (const double*)w.denbuf, nn, n, npad, gf, crit, w.ell, w.fix_count, w.fix_list,
+                       w.fix_cap, (int*)nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_grid_fixup<DX, DY>), dim3(1024), dim3(TILE), 0, stream, pts, nn, n, npad,
+                       ga, gf, crit, (const double*)w.denbuf, w.ell, (const int*)w.fix_count,
+                       (const int2*)w.fix_list, w.fix_cap);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grid_rows, dim3((unsigned)G), dim3(256), 0, stream, (const double*)w.ell, n,
+                       npad, totals, per_point, counts);
+    return hipGetLastError();
+}
+
+#define CDE_GRID_CASE(DX_, DY_)                                                                 \
+    case (DX_) * 8 + (DY_):                                                                     \
+        return grid_t<DX_, DY_>(m, ga, gf, crit, xt, w, totals, per_point, counts, stream);
 
 // Column means of x (FP64 accumulation in a fixed order, one thread per
 // dimension), stored as FP32: the centring of the cross-term option.
@@ -570,16 +725,21 @@ hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* h
         gf.log_cy[b] = -m->dy * (log(h) + HALF_LOG_2PI);
     }
     const size_t G = (size_t)n_hx * n_hy;
-    // work layout: numbuf [G][npad] | denbuf [gx][npad] | ell [G][npad] | fix_count | fix_list
-    double* numbuf = (double*)work;
-    double* denbuf = numbuf + G * m->npad;
-    double* ell = denbuf + (size_t)n_hx * m->npad;
-    int* fix_count = (int*)(ell + G * m->npad);
-    int2* fix_list = (int2*)(fix_count + 64);
-    const size_t used = (size_t)((char*)fix_list - (char*)work);
+    // work layout: numbuf [G][npad] | denbuf [gx][npad] | ell [G][npad] |
+    // fix_count [64] | flags [npad] | plist [npad] | pcount [64] | fix_list
+    GridWork w;
+    w.numbuf = (double*)work;
+    w.denbuf = w.numbuf + G * m->npad;
+    w.ell = w.denbuf + (size_t)n_hx * m->npad;
+    w.fix_count = (int*)(w.ell + G * m->npad);
+    w.flags = w.fix_count + 64;
+    w.plist = w.flags + m->npad;
+    w.pcount = w.plist + m->npad;
+    w.fix_list = (int2*)(w.pcount + 64);
+    const size_t used = (size_t)((char*)w.fix_list - (char*)work);
     if (used >= work_bytes) return hipErrorInvalidValue;
-    const int fix_cap = (int)std::min<size_t>((work_bytes - used) / sizeof(int2), size_t(1) << 30);
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, fix_count, 1);
+    w.fix_cap = (int)std::min<size_t>((work_bytes - used) / sizeof(int2), size_t(1) << 30);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, w.fix_count, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (m->dx * 8 + m->dy) {
@@ -596,7 +756,8 @@ size_t grid_work_bytes(const cde_model* m, int n_hx, int n_hy)
 {
     const size_t G = (size_t)n_hx * n_hy;
     const size_t fix_cap = std::max<size_t>(G * m->npad / 8, 1 << 20);  // 1/8 of all entries
-    return sizeof(double) * (2 * G + n_hx) * m->npad + 64 * sizeof(int) + fix_cap * sizeof(int2);
+    return sizeof(double) * (2 * G + n_hx) * m->npad + (2 * m->npad + 128) * sizeof(int) +
+           fix_cap * sizeof(int2) + 64;
 }
 
 }  // namespace cde
