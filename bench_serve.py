@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--n-cap", type=int, default=None, help="cap job sizes (smoke runs)")
     ap.add_argument("--budget-gb", type=float, default=96.0)
     ap.add_argument("--deadline", type=float, default=600.0)
+    ap.add_argument("--sweep", type=str, default="",
+                    help="comma-separated extra arrival rates, each run for --sweep-duration")
+    ap.add_argument("--sweep-duration", type=float, default=4.0)
     args = ap.parse_args()
 
     import workloads
@@ -116,6 +119,20 @@ def main():
         "results_identical_alone_vs_mixed": identical, "compared": len(common),
         "data": "synthetic", "dtype": "f32 kernel values, f64 accumulation",
     }
+    if args.sweep:
+        sweep = []
+        for rate in [float(v) for v in args.sweep.split(",") if v]:
+            st = workloads.serve_stream(rate=rate, duration=args.sweep_duration, seed=args.seed + 1)
+            rq = build_requests(st, sets, seed=args.seed + 1, n_cap=args.n_cap)
+            row = {"rate_req_s": rate, "requests": len(rq)}
+            for mode, batched in (("plain", False), ("batched", True)):
+                rep, _ = run_mode(ex, copy.deepcopy(rq), batched, budget, args.deadline)
+                row[mode] = {k: rep[k] for k in ("throughput_req_s", "p50_s", "p99_s", "makespan_s")}
+                row[mode]["job_p99_s"] = rep["job"]["p99_s"]
+                row[mode]["query_p99_s"] = rep["query"]["p99_s"]
+            print(json.dumps(row), file=sys.stderr, flush=True)
+            sweep.append(row)
+        out["sweep"] = sweep
     print(json.dumps(out))
 
 
