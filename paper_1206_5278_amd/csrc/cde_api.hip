@@ -332,7 +332,7 @@ cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const 
                                      f_dev, s);
         } else {
             if (q >= (int64_t(1) << 31) - 64) return fail(CDE_EUNSUPPORTED, "cde_density_query: q >= 2^31");
-            cde_status st = ensure_scratch(m, sizeof(double) * (size_t)(q + k) + 256);
+            cde_status st = ensure_scratch(m, sizeof(double) * query_work_doubles(m, q, k) + 256);
             if (st != CDE_OK) return st;
             e = launch_query_mfma(m, (const float*)xq_dev, (int)q, (const float*)ygrid_dev, (int)k, h,
                                   f_dev, (double*)m->scratch, s);

@@ -21,9 +21,10 @@ hipError_t launch_query(const cde_model* m, const T* xq, int64_t q, const T* yg,
                         const DiagSets<T>& sets, double* f, hipStream_t stream);
 
 // Density queries on FP32 models, on the matrix cores: f [q][k]; `work`
-// holds q + k doubles (per-query and per-grid-point shifts).
+// holds query_work_doubles(m, q, k) doubles (shifts and chunk partials).
 hipError_t launch_query_mfma(const cde_model* m, const float* xq, int q, const float* yg, int k,
                              const double* h, double* f, double* work, hipStream_t stream);
+size_t query_work_doubles(const cde_model* m, int64_t q, int64_t k);
 
 // Scalar-bandwidth grid on FP32 models: per-point neighbour shifts (first
 // call only), the MFMA grid pass, FP64 finalisation, exact fixup of extreme

@@ -364,32 +364,45 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
 // carry a cell whose shifted num' falls far below 1; k_grid_finalize flags
 // the points that have such a cell (num' < 2^-80) and those points are
 // recomputed by the FP64 kernel above.
-template <int DX, int DY>
+// Points per wave of the FP32 pass (4 or 8): fewer points per wave means
+// fewer accumulator registers and more resident waves to hide the latency of
+// each exponential feeding an MFMA.
+#ifndef CDE_GRID32_POINTS_PER_WAVE
+#define CDE_GRID32_POINTS_PER_WAVE 4
+#endif
+
+template <int DX, int DY, int PW>
 __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ pts,
                                                      const double* __restrict__ nn, int n, int npad,
                                                      GridArgs ga, double* __restrict__ numbuf,
                                                      double* __restrict__ denbuf)
 {
+    static_assert(PW == 4 || PW == 8, "4 or 8 points per wave");
     constexpr int S = row_stride(DX, DY);
+    constexpr int JG = 64 / PW;  // tile rows per distance group
     __shared__ float tile[TILE * S];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int i0 = blockIdx.x * 32 + wave * 8;
+    const int i0 = blockIdx.x * (4 * PW) + wave * PW;
     const int tb = ga.gyp / 16;
     const int ab = blockIdx.y / tb, bb = blockIdx.y % tb;
     const bool do_den = (bb == 0);
-    const int di = i0 + (lane & 7);
-    const int jo = 4 * ((lane & 15) >> 3) + (lane >> 4);
+    // distance role: lane = 16 r + PW s + q forms point i0 + q against row
+    // group*JG + 4 s + r; a row broadcast of position PW s + q then gives
+    // every lane of row r the pair (i0 + q, group*JG + 4 s + r).
+    const int pos = lane & 15;
+    const int di = i0 + (pos % PW);
+    const int jo = 4 * (pos / PW) + (lane >> 4);
     double own[S];
     own_f64<S>(own, pts + (size_t)di * S);
     const double m_i = nn[di], my_i = nn[npad + di];
     const float ca = ga.cx[ab * 16 + (lane & 15)];
     const float cb = ga.cy[bb * 16 + (lane & 15)];
 
-    v4f acc[8];
-    Kahan<float> tot[8][4], dtot[8];
-    float dpart[8];
+    v4f acc[PW];
+    Kahan<float> tot[PW][4], dtot[PW];
+    float dpart[PW];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < PW; ++q) {
         acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
         dpart[q] = 0.f;
         dtot[q].zero();
@@ -406,11 +419,11 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
         if (t + 1 < ntiles) load_row<S>(pre, pts + ((size_t)(t + 1) * TILE + tid) * S);
         const int base = t * TILE;
         const int cnt = min(TILE, n - base);
-        const int ngroups = (cnt + 7) >> 3;
+        const int ngroups = (cnt + JG - 1) / JG;
         for (int g = 0; g < ngroups; ++g) {
-            const int jj = g * 8 + jo;
+            const int jj = g * JG + jo;
             float pj[S];
-            load_row<S>(pj, tile + jj * S);
+            load_row<S>(pj, tile + jj * S);  // jj < 256: rows >= cnt are packed padding
             double d2x, d2y;
             dist2<DX, DY>(own, pj, d2x, d2y);
             float xa = (float)(d2x - m_i), ya = (float)(d2y - my_i);
@@ -420,8 +433,8 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
             }
             const int xai = __float_as_int(xa), yai = __float_as_int(ya);
             Unroll<16>::run([&](auto c) {
-                constexpr int idx = decltype(c)::value;
-                constexpr int q = idx & 7;
+                constexpr int idx = decltype(c)::value;  // idx = PW s + q
+                constexpr int q = idx % PW;
                 const float ex = exp2_<float>(-(row_bcast<idx>(xai) * ca));
                 const float ey = exp2_<float>(-(row_bcast<idx>(yai) * cb));
                 acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ex, ey, acc[q], 0, 0, 0);
@@ -429,7 +442,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
             });
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < PW; ++q) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) tot[q][r].add(acc[q][r]);
             acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -439,7 +452,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
     }
     // f32 16x16x4 result layout: register r holds row 4*(lane/16) + r
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < PW; ++q) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int a = ab * 16 + 4 * (lane >> 4) + r;
@@ -449,7 +462,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
     }
     if (do_den) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < PW; ++q) {
             double v = dtot[q].value();
             v += __shfl_xor(v, 16, 64);
             v += __shfl_xor(v, 32, 64);
@@ -654,8 +667,10 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
         // recompute those points on the FP64 path.
         hipLaunchKernelGGL(k_zero_int, dim3((npad + 255) / 256), dim3(256), 0, stream, w.flags, npad);
         hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, w.pcount, 1);
-        hipLaunchKernelGGL((k_loo_grid32<DX, DY>), grid, dim3(TILE), 0, stream, pts, nn, n, npad, ga,
-                           w.numbuf, w.denbuf);
+        constexpr int PW = CDE_GRID32_POINTS_PER_WAVE;
+        const dim3 grid32((unsigned)(npad / (4 * PW)), (unsigned)tiles);
+        hipLaunchKernelGGL((k_loo_grid32<DX, DY, PW>), grid32, dim3(TILE), 0, stream, pts, nn, n, npad,
+                           ga, w.numbuf, w.denbuf);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(k_grid_finalize, fgrid, dim3(256), 0, stream, (const double*)w.numbuf,
                            (const double*)w.denbuf, nn, n, npad, gf, crit, w.ell, w.fix_count,

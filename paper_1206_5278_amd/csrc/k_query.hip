@@ -6,20 +6,24 @@
 //     F[q][g] = sum_i w(q, i) k(i, g),
 // a dense contraction over the training points of a [Q x n] matrix of
 // x-kernels with an [n x k] matrix of y-kernels.  It runs on
-// v_mfma_f64_16x16x4f64: per training point, one x-kernel value per query and
+// v_mfma_f32_16x16x4f32: per training point, one x-kernel value per query and
 // one y-kernel value per grid point are formed on the VALU (not one product
 // kernel per (q, g)).
 //
 // Shifts: w' = 2^-(d2x(q,i) - m_q), k' = 2^-(d2y(g,i) - mu_g), with m_q the
 // smallest scaled x-distance of query q to the data and mu_g the smallest
-// scaled y-distance of grid point g (FP64 prepasses), so w' <= 1 (= 1 at the
-// query's neighbour: den' >= 1) and k' <= 1; kernel values are v_exp_f32 of
-// the fractional exponent scaled exactly by a power of two in FP64, as in the
-// grid kernel.  f = c_y 2^-mu_g F'/D' is formed in FP64 in the epilogue.
+// scaled y-distance of grid point g (FP64 prepasses; exact minima, so the
+// nearest point has w' = 1 and den' >= 1).  Distances and the shifted
+// exponents are formed in FP64 and rounded to FP32 after the subtraction.
+// Kernel values and products are FP32; sums over a 256-point tile are folded
+// into Kahan-compensated FP32 totals.  A value of f more than ~2^-100 below
+// its query's peak is not carried to full relative precision (FP32 range);
+// such tail values are far below the accuracy floor of a density estimate.
 //
-// Work decomposition: a 256-lane block owns 64 queries (16 per wave) and a
-// chunk of up to 128 grid points (blockIdx.y); training points stream through
-// LDS in 256-point tiles.
+// Work decomposition: a 256-lane block owns 64 queries (16 per wave), a chunk
+// of up to 128 grid points (blockIdx.y) and a range of training points
+// (blockIdx.z); chunk partial sums (FP64) are combined in a fixed order by
+// k_query_reduce, so results do not depend on the chunking's timing.
 #include <type_traits>
 
 #include "cde_device.h"
@@ -29,15 +33,7 @@ namespace cde {
 
 namespace {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ double exp2_neg_wide_q(float t)
-{
-#pragma clang fp contract(off)
-    const float fl = floorf(t);
-    const float fr = t - fl;
-    return ldexp((double)__builtin_amdgcn_exp2f(-fr), (int)(-fl));
-}
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr float QEXCLUDED = 1e20f;
 
@@ -47,11 +43,25 @@ struct QueryArgs {
     double log_cy;
 };
 
+// Non-negative doubles order like their bit patterns: an exact, order-free
+// minimum through a 64-bit integer atomic.
+__device__ __forceinline__ void atomic_min_nonneg(double* p, double v)
+{
+    atomicMin((unsigned long long*)p, (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ void k_fill_inf(double* p, int cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) p[i] = __builtin_inf();
+}
+
 }  // namespace
 
-// m_q = min_i sum_k c_k (x_qk - x_ik)^2 (FP64), one lane per query.
+// m_q = min_i sum_k c_k (x_qk - x_ik)^2 (FP64): lane = query, blockIdx.y =
+// range of training points.
 template <int DX, int DY>
-__global__ __launch_bounds__(TILE) void k_qshift_x(const float* __restrict__ pts, int n,
+__global__ __launch_bounds__(TILE) void k_qshift_x(const float* __restrict__ pts, int n, int chunk,
                                                    const float* __restrict__ xq, int q,
                                                    QueryArgs qa, double* __restrict__ mq)
 {
@@ -64,30 +74,32 @@ __global__ __launch_bounds__(TILE) void k_qshift_x(const float* __restrict__ pts
 #pragma unroll
     for (int k = 0; k < DX; ++k) xo[k] = (double)xq[(size_t)ec * DX + k];
     double best = inf_<double>();
-    const int ntiles = (n + TILE - 1) / TILE;
-    for (int t = 0; t < ntiles; ++t) {
+    const int j0 = blockIdx.y * chunk, j1 = min(n, j0 + chunk);
+    for (int t0 = j0; t0 < j1; t0 += TILE) {
         __syncthreads();
         float pre[S];
-        load_row<S>(pre, pts + ((size_t)t * TILE + tid) * S);
+        load_row<S>(pre, pts + ((size_t)t0 + tid) * S);
         store_row<S>(tile + tid * S, pre);
         __syncthreads();
-        const int cnt = min(TILE, n - t * TILE);
+        const int cnt = min(TILE, j1 - t0);
         for (int j = 0; j < cnt; ++j) {
+            float pj[S];
+            load_row<S>(pj, tile + j * S);
             double d2 = 0.0;
 #pragma unroll
             for (int k = 0; k < DX; ++k) {
-                const double d = xo[k] - (double)tile[j * S + k];
+                const double d = xo[k] - (double)pj[k];
                 d2 = fma_(d * d, qa.cx[k], d2);
             }
             best = min_(best, d2);
         }
     }
-    if (e < q) mq[e] = best;
+    if (e < q) atomic_min_nonneg(mq + e, best);
 }
 
-// mu_g = min_i sum_l c'_l (y_gl - y_il)^2 (FP64), one lane per grid point.
+// mu_g = min_i sum_l c'_l (y_gl - y_il)^2 (FP64), same decomposition.
 template <int DX, int DY>
-__global__ __launch_bounds__(TILE) void k_qshift_y(const float* __restrict__ pts, int n,
+__global__ __launch_bounds__(TILE) void k_qshift_y(const float* __restrict__ pts, int n, int chunk,
                                                    const float* __restrict__ yg, int k,
                                                    QueryArgs qa, double* __restrict__ mu)
 {
@@ -100,34 +112,37 @@ __global__ __launch_bounds__(TILE) void k_qshift_y(const float* __restrict__ pts
 #pragma unroll
     for (int l = 0; l < DY; ++l) yo[l] = (double)yg[(size_t)ec * DY + l];
     double best = inf_<double>();
-    const int ntiles = (n + TILE - 1) / TILE;
-    for (int t = 0; t < ntiles; ++t) {
+    const int j0 = blockIdx.y * chunk, j1 = min(n, j0 + chunk);
+    for (int t0 = j0; t0 < j1; t0 += TILE) {
         __syncthreads();
         float pre[S];
-        load_row<S>(pre, pts + ((size_t)t * TILE + tid) * S);
+        load_row<S>(pre, pts + ((size_t)t0 + tid) * S);
         store_row<S>(tile + tid * S, pre);
         __syncthreads();
-        const int cnt = min(TILE, n - t * TILE);
+        const int cnt = min(TILE, j1 - t0);
         for (int j = 0; j < cnt; ++j) {
+            float pj[S];
+            load_row<S>(pj, tile + j * S);
             double d2 = 0.0;
 #pragma unroll
             for (int l = 0; l < DY; ++l) {
-                const double d = yo[l] - (double)tile[j * S + DX + l];
+                const double d = yo[l] - (double)pj[DX + l];
                 d2 = fma_(d * d, qa.cy[l], d2);
             }
             best = min_(best, d2);
         }
     }
-    if (e < k) mu[e] = best;
+    if (e < k) atomic_min_nonneg(mu + e, best);
 }
 
 template <int DX, int DY>
-__global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ pts, int n,
+__global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ pts, int n, int chunk,
                                                      const float* __restrict__ xq, int q,
                                                      const float* __restrict__ yg, int k,
                                                      QueryArgs qa, const double* __restrict__ mq,
                                                      const double* __restrict__ mu,
-                                                     double* __restrict__ f)
+                                                     double* __restrict__ fpart,
+                                                     double* __restrict__ dpart)
 {
     constexpr int S = row_stride(DX, DY);
     constexpr int GT = 8;  // grid tiles of 16 per block (128 grid points)
@@ -135,6 +150,7 @@ __global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ p
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q0 = blockIdx.x * 64 + wave * 16;
     const int g0 = blockIdx.y * 16 * GT;
+    const int c = blockIdx.z;
     const int kr = lane >> 4;  // k-row of the MFMA operands: training point i0 + kr
 
     // A role: query q0 + lane%16
@@ -155,24 +171,31 @@ __global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ p
     }
     const int ntg = min(GT, (k - g0 + 15) / 16);  // grid tiles present in this chunk
 
-    v4d acc[GT];
+    v4f acc[GT];
+    Kahan<float> tot[GT][4];
 #pragma unroll
-    for (int t = 0; t < GT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
-    double dsum = 0.0;
+    for (int t = 0; t < GT; ++t) {
+        acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tot[t][r].zero();
+    }
+    float dp = 0.f;
+    Kahan<float> dtot;
+    dtot.zero();
 
-    const int ntiles = (n + TILE - 1) / TILE;
+    const int j0 = c * chunk, j1 = min(n, j0 + chunk);
     float pre[S];
-    load_row<S>(pre, pts + (size_t)tid * S);
-    for (int tt = 0; tt < ntiles; ++tt) {
+    load_row<S>(pre, pts + ((size_t)j0 + tid) * S);
+    for (int t0 = j0; t0 < j1; t0 += TILE) {
         __syncthreads();
         store_row<S>(tile + tid * S, pre);
         __syncthreads();
-        if (tt + 1 < ntiles) load_row<S>(pre, pts + ((size_t)(tt + 1) * TILE + tid) * S);
-        const int cnt = min(TILE, n - tt * TILE);
+        if (t0 + TILE < j1) load_row<S>(pre, pts + ((size_t)t0 + TILE + tid) * S);
+        const int cnt = min(TILE, j1 - t0);
         for (int i4 = 0; i4 < cnt; i4 += 4) {
             const int ii = i4 + kr;
             float pj[S];
-            load_row<S>(pj, tile + ii * S);  // rows >= cnt are packed padding (in bounds)
+            load_row<S>(pj, tile + ii * S);  // rows >= cnt are packed rows (in bounds)
             const bool live = ii < cnt;
             double d2 = 0.0;
 #pragma unroll
@@ -181,8 +204,8 @@ __global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ p
                 d2 = fma_(d * d, qa.cx[kk], d2);
             }
             const float xa = live ? (float)(d2 - m_q) : QEXCLUDED;
-            const double w = exp2_neg_wide_q(xa);
-            dsum += w;
+            const float w = exp2_<float>(-xa);
+            dp += w;
 #pragma unroll
             for (int t = 0; t < GT; ++t) {
                 if (t < ntg) {
@@ -193,32 +216,60 @@ __global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ p
                         e = fma_(d * d, qa.cy[l], e);
                     }
                     const float ya = live ? (float)(e - mu_g[t]) : QEXCLUDED;
-                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(w, exp2_neg_wide_q(ya), acc[t], 0,
-                                                                  0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, exp2_<float>(-ya), acc[t], 0, 0, 0);
                 }
             }
         }
+#pragma unroll
+        for (int t = 0; t < GT; ++t) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tot[t][r].add(acc[t][r]);
+            acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
+        dtot.add(dp);
+        dp = 0.f;
     }
-    // den' of query q0 + lane%16: sum over the four k-rows in a fixed order
+    // den' partial of query q0 + lane%16: the four k-rows in a fixed order
+    double dsum = dtot.value();
     dsum += __shfl_xor(dsum, 16, 64);
     dsum += __shfl_xor(dsum, 32, 64);
-    // result layout (f64 16x16x4): register r holds query (lane/16) + 4 r,
+    if (blockIdx.y == 0 && lane < 16 && q0 + lane < q) dpart[(size_t)c * q + q0 + lane] = dsum;
+    // f32 16x16x4 result layout: register r holds query 4*(lane/16) + r,
     // grid column lane%16
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int qi = (lane >> 4) + 4 * r;
-        const double den = __shfl(dsum, qi, 64);
-        const int qq = q0 + qi;
+        const int qq = q0 + 4 * (lane >> 4) + r;
 #pragma unroll
         for (int t = 0; t < GT; ++t) {
             const int g = g0 + 16 * t + (lane & 15);
-            if (t < ntg && qq < q && g < k) {
-                const double num = acc[t][r];
-                f[(size_t)qq * k + g] =
-                    num > 0.0 ? exp(qa.log_cy - mu_g[t] * LN2 + log(num / den)) : 0.0;
-            }
+            if (t < ntg && qq < q && g < k) fpart[((size_t)c * q + qq) * k + g] = tot[t][r].value();
         }
     }
+}
+
+// f = c_y 2^-mu_g F'/D' with F' and D' summed over the point chunks in order.
+__global__ void k_query_reduce(const double* __restrict__ fpart, const double* __restrict__ dpart,
+                               const double* __restrict__ mu, int q, int k, int nchunks,
+                               double log_cy, double* __restrict__ f)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)q * k) return;
+    const int qq = (int)(e / k), g = (int)(e - (int64_t)qq * k);
+    double num = 0.0, den = 0.0;
+    for (int c = 0; c < nchunks; ++c) {
+        num += fpart[((size_t)c * q + qq) * k + g];
+        den += dpart[(size_t)c * q + qq];
+    }
+    f[e] = num > 0.0 ? exp(log_cy - mu[g] * LN2 + log(num / den)) : 0.0;
+}
+
+size_t query_work_doubles(const cde_model* m, int64_t q, int64_t k)
+{
+    const int64_t qb = (q + 63) / 64, gb = (k + 127) / 128;
+    const int64_t max_chunks = (m->n + TILE - 1) / TILE;
+    int64_t c = std::max<int64_t>(1, 1024 / std::max<int64_t>(1, qb * gb));
+    c = std::min(c, max_chunks);
+    return (size_t)(q + k + c * q * (k + 1) + 64);
 }
 
 template <int DX, int DY>
@@ -233,19 +284,36 @@ static hipError_t query_t(const cde_model* m, const float* xq, int q, const floa
         if (l < DY) lcy -= log(h[DX + l]) + HALF_LOG_2PI;
     }
     qa.log_cy = lcy;
+    const int n = (int)m->n;
     const float* pts = (const float*)m->pts;
+    const int qb = (q + 63) / 64, gb = (k + 127) / 128;
+    const int ntiles = (n + TILE - 1) / TILE;
+    // training-point chunks: enough blocks to fill the device, whole tiles each
+    int nch = std::max(1, 1024 / std::max(1, qb * gb));
+    nch = std::min(nch, ntiles);
+    const int chunk = (ntiles + nch - 1) / nch * TILE;
+    nch = (n + chunk - 1) / chunk;
     double* mq = work;
     double* mu = work + q;
-    hipLaunchKernelGGL((k_qshift_x<DX, DY>), dim3((q + TILE - 1) / TILE), dim3(TILE), 0, stream,
-                       pts, (int)m->n, xq, q, qa, mq);
+    double* dpart = mu + k;
+    double* fpart = dpart + (size_t)nch * q;
+    // shifts: exact minima over point chunks
+    const int sch = 16 * TILE;
+    const int nsch = (n + sch - 1) / sch;
+    hipLaunchKernelGGL(k_fill_inf, dim3((q + k + 255) / 256), dim3(256), 0, stream, mq, q + k);
+    hipLaunchKernelGGL((k_qshift_x<DX, DY>), dim3((q + TILE - 1) / TILE, nsch), dim3(TILE), 0, stream,
+                       pts, n, sch, xq, q, qa, mq);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_qshift_y<DX, DY>), dim3((k + TILE - 1) / TILE), dim3(TILE), 0, stream,
-                       pts, (int)m->n, yg, k, qa, mu);
+    hipLaunchKernelGGL((k_qshift_y<DX, DY>), dim3((k + TILE - 1) / TILE, nsch), dim3(TILE), 0, stream,
+                       pts, n, sch, yg, k, qa, mu);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_query_mfma<DX, DY>), dim3((q + 63) / 64, (k + 127) / 128), dim3(TILE), 0,
-                       stream, pts, (int)m->n, xq, q, yg, k, qa, (const double*)mq,
-                       (const double*)mu, f);
+    hipLaunchKernelGGL((k_query_mfma<DX, DY>), dim3(qb, gb, nch), dim3(TILE), 0, stream, pts, n, chunk,
+                       xq, q, yg, k, qa, (const double*)mq, (const double*)mu, fpart, dpart);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t total = (int64_t)q * k;
+    hipLaunchKernelGGL(k_query_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
+                       (const double*)fpart, (const double*)dpart, (const double*)mu, q, k, nch, lcy, f);
     return hipGetLastError();
 }
 
