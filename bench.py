@@ -153,6 +153,16 @@ def main():
                 "kernel": "k_loo_diag<float,5,1,grad>", "kernel_ms": kern_ms,
                 "work_per_pair": f"F={PAIR_F:g} VALU ops + E={PAIR_E:g} v_exp_f32 x {EXP_SLOTS:g} slots"}
 
+    # Secondary: value-only evaluation (no gradient moments) at the final h.
+    h_last = torch.exp(theta.detach()).tolist()
+    model.loo_list([h_last])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        model.loo_list([h_last])
+    torch.cuda.synchronize()
+    vo_ms = 1e3 * (time.perf_counter() - t0) / 3
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(x32.astype(np.float64), y32.astype(np.float64), h0.tolist(),
@@ -169,6 +179,7 @@ def main():
                    "accumulation": "FP32 kernel values, Kahan-compensated tile sums, FP64 log/reduce"},
         "roofline": roofline, "cpu_baseline": cpu,
         "trace_first_last": [trace[0], trace[-1]] if trace else None,
+        "secondary": {"value_only_ms": vo_ms, "value_only_pair_evals_per_s": pairs / (vo_ms * 1e-3)},
     }
     print(json.dumps(out))
     model.close()
