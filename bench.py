@@ -24,22 +24,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Peak VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-# (one non-packed FP32 operation per lane per clock).
-VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
-# Issue cost of one v_exp_f32 in full-rate VALU slots on gfx950 (measured:
-# 1.63e13 exp/s vs 3.34e13 FMA/s at the same occupancy).
-EXP_SLOTS = 2.0
-# Algorithmic VALU work per ordered pair of the value+gradient pass (dx=5,
-# dy=1): 6 differences, 6 squares, 5 exponent accumulations (FMA), 1 add
-# for the product-kernel exponent, 2 kernel-sum adds and 11 moment FMAs
-# (F = 30), plus two exponentials (E = 2).
-PAIR_F, PAIR_E = 30.0, 2.0
+# Peak FP32 vector rate of MI355X in lane-operations per second: 256 CUs x
+# 4 SIMDs x 2.4 GHz x 32 lanes (the published 157.3 TFLOP/s counts an FMA as
+# two FLOPs).  Non-packed FP32 instructions reach it by dual issue: each SIMD
+# issues two wave64 VALU instructions (from different waves) per 4-cycle
+# quad; a probe measured 2.4-2.6 cycles per wave64 FMA at 4-8 waves/SIMD.
+VALU_PEAK_SLOTS = 256 * 4 * 32 * 2.4e9
+# Issue cost of one v_exp_f32 in those FP32 slots: the transcendental rate is
+# a quarter of the dual-issue FP32 rate (8 lanes/clock/SIMD; the probe
+# measured 9.7 cycles per wave64 exp, 83% of that).
+EXP_SLOTS = 4.0
+# Algorithmic FP32 work per ordered pair of the value+gradient pass (dx=5,
+# dy=1): 6 differences, 6 squares, 6 exponent FMAs, 2 kernel-sum adds and 11
+# moment FMAs (F = 31), plus two exponentials (E = 2).  The kernel issues one
+# more add per pair (the product kernel's own reference), not counted.
+PAIR_F, PAIR_E = 31.0, 2.0
 # Scaled HBM bytes of one k_loo_diag<float,5,1,grad> launch at N=500k, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs, each scaled by the same counter's
 # reading for a 256 MiB copy (profiles/k_loo_diag_f32_5x1_grad_photoz500k.md).
 # Set to None whenever that kernel changes, until the counters are re-taken.
-DIAG_TRAFFIC_BYTES = 976_613_000
+DIAG_TRAFFIC_BYTES = 986_713_000
 
 
 def parse():
@@ -176,7 +180,7 @@ def main():
         "config": {"workload": "photoz-shaped gradient ascent (value+gradient per step)", "n": n,
                    "dx": 5, "dy": 1, "bandwidths": "diagonal, 6 parameters",
                    "start": "normal-reference rule", "optimizer": "Adam lr 0.05 on log h",
-                   "accumulation": "FP32 kernel values, Kahan-compensated tile sums, FP64 log/reduce"},
+                   "accumulation": "FP32 kernel values and 32-pair subtile sums, FP64 per-point totals, FP64 log/reduce"},
         "roofline": roofline, "cpu_baseline": cpu,
         "trace_first_last": [trace[0], trace[-1]] if trace else None,
         "secondary": {"value_only_ms": vo_ms, "value_only_pair_evals_per_s": pairs / (vo_ms * 1e-3)},

@@ -19,6 +19,8 @@ __device__ __forceinline__ float fma_(float a, float b, float c) { return __buil
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float min_(float a, float b) { return __builtin_fminf(a, b); }
 __device__ __forceinline__ double min_(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float max_(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double max_(double a, double b) { return __builtin_fmax(a, b); }
 
 template <typename T>
 __device__ __forceinline__ T inf_();
@@ -66,6 +68,48 @@ __device__ __forceinline__ void load_row(double (&dst)[S], const double* src)
         dst[q] = v.x; dst[q + 1] = v.y;
     }
 }
+
+// Load the first P values of a point row (P <= S; the rest of the row is
+// padding) with the widest aligned loads.
+template <int P, int S>
+__device__ __forceinline__ void load_cols(float (&dst)[S], const float* src)
+{
+    static_assert(P <= S && S % 4 == 0, "bad row shape");
+    constexpr int Q4 = P / 4 * 4;
+#pragma unroll
+    for (int q = 0; q < Q4; q += 4) {
+        float4 v = *reinterpret_cast<const float4*>(src + q);
+        dst[q] = v.x; dst[q + 1] = v.y; dst[q + 2] = v.z; dst[q + 3] = v.w;
+    }
+    if constexpr (P - Q4 >= 2) {
+        float2 v = *reinterpret_cast<const float2*>(src + Q4);
+        dst[Q4] = v.x; dst[Q4 + 1] = v.y;
+    }
+    if constexpr ((P - Q4) % 2 == 1) dst[P - 1] = src[P - 1];
+}
+
+template <int P, int S>
+__device__ __forceinline__ void load_cols(double (&dst)[S], const double* src)
+{
+    static_assert(P <= S && S % 2 == 0, "bad row shape");
+    constexpr int Q2 = P / 2 * 2;
+#pragma unroll
+    for (int q = 0; q < Q2; q += 2) {
+        double2 v = *reinterpret_cast<const double2*>(src + q);
+        dst[q] = v.x; dst[q + 1] = v.y;
+    }
+    if constexpr (P % 2 == 1) dst[P - 1] = src[P - 1];
+}
+
+// A wave-uniform value kept in a vector register, so that the FP32 ops using
+// it have vector operands only (those issue at the higher rate on gfx950).
+__device__ __forceinline__ float vreg(float x)
+{
+    float r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+__device__ __forceinline__ double vreg(double x) { return x; }
 
 template <int S, typename T>
 __device__ __forceinline__ void store_row(T* dst, const T (&src)[S])

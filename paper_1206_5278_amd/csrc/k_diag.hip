@@ -20,13 +20,15 @@
 // differences (no |x|^2 cancellation), kernel values are v_exp_f32 of that
 // exponent relative to a per-point reference (a running minimum, so the
 // largest term is about 1 and nothing overflows or underflows: den' >= 1 and
-// num' >= 1 by construction), values are summed in FP32 over 32-point
-// subtiles and the subtile partials are folded into Kahan-compensated totals.
-// The reference is moved lazily, only when a subtile holds a term more than
-// 2^32 above it; the subtile is then recomputed against the new reference and
-// the totals rescaled, which is exact in real arithmetic (the common factor
-// cancels in num/den).  The log of the ratio, the gradient combination and
-// the sum over i run in FP64.
+// num' >= 1 by construction).  Values are summed in FP32 over 32-point
+// subtiles, the subtile sums are added into plain per-tile sums, and those
+// are folded into Kahan-compensated totals once per 256-point tile.  The
+// reference is moved lazily, only when a subtile holds a term more than 2^32
+// above it: the totals and the subtile's own sums are then rescaled, which is
+// exact in real arithmetic (the common factor cancels in num/den); a subtile
+// whose heaviest term may have overflowed is summed again against the moved
+// reference.  The log of the ratio, the gradient combination and the sum
+// over i run in FP64.
 
 #include "cde_device.h"
 #include "cde_kernels.h"
@@ -38,148 +40,272 @@ namespace {
 template <typename T, int DX, int DY, bool GRAD>
 struct DiagLane {
     static constexpr int S = row_stride(DX, DY);
-    static constexpr int GX = GRAD ? DX : 1;
-    static constexpr int GY = GRAD ? DY : 1;
     static constexpr int SUB = 32;
+    // Accumulated quantities: den, num, then (gradient) sum w dx_k^2,
+    // sum v dx_k^2 and sum v dy_l^2.  The first group (den, w moments) is
+    // relative to m, the second (num, v moments) to m2.
+    static constexpr int NA = GRAD ? 2 + 2 * DX + DY : 2;
+    static constexpr int MW = 2, MV = 2 + DX, MVY = 2 + 2 * DX;
 
-    T xi[DX], yi[DY], cx[DX], cy[DY];
-    T m, m2;  // references of the x-kernel sums and of the product-kernel sums
-    Kahan<T> den, num, mw[GX], mv[GX], mvy[GY];
+    // Per-point totals: FP64 columns in LDS (column a of thread t at
+    // lds[a * TILE + t]), touched once per tile, conflict-free, and kept off
+    // the registers of the pair loop.
+    static constexpr int LDS_DOUBLES = NA * TILE;
 
-    __device__ __forceinline__ void init_accumulators()
+    T xi[DX], yi[DY], ncx[DX], ncy[DY];  // coordinates of i; negated kernel scales
+    T m, m2;         // references of the x-kernel sums and of the product-kernel sums
+    double* lds;     // this thread's first total
+    T mid[NA];       // plain sums of the subtiles of the current tile
+
+    __device__ __forceinline__ void init_accumulators(double* lds_base)
     {
-        den.zero();
-        num.zero();
+        lds = lds_base + threadIdx.x;
 #pragma unroll
-        for (int k = 0; k < GX; ++k) { mw[k].zero(); mv[k].zero(); }
+        for (int a = 0; a < NA; ++a) lds[a * TILE] = 0.0;
+    }
+    __device__ __forceinline__ void scale_total(int a, T f) { lds[a * TILE] *= (double)f; }
+    __device__ __forceinline__ double total(int a) const { return lds[a * TILE]; }
+    __device__ __forceinline__ void begin_tile()
+    {
 #pragma unroll
-        for (int l = 0; l < GY; ++l) mvy[l].zero();
+        for (int a = 0; a < NA; ++a) mid[a] = T(0);
+    }
+    __device__ __forceinline__ void end_tile()
+    {
+#pragma unroll
+        for (int a = 0; a < NA; ++a) lds[a * TILE] += (double)mid[a];
+    }
+    __device__ __forceinline__ bool in_first(int a) const
+    {
+        return a == 0 || (GRAD && a >= MW && a < MV);
     }
 
-    // Base-2 exponents of the x-kernel and of the product kernel for one j.
-    __device__ __forceinline__ void exponents(const T* pj, T& ex, T& exy) const
+    // Negated base-2 exponents of the x-kernel and of the product kernel for
+    // one j (ncx, ncy hold the negated scales).
+    __device__ __forceinline__ void neg_exponents(const T* pj, T& g1, T& g2) const
     {
-        T e = T(0);
+        T g = T(0);
 #pragma unroll
         for (int k = 0; k < DX; ++k) {
             T d = xi[k] - pj[k];
-            e = fma_(d * d, cx[k], e);
+            g = fma_(d * d, ncx[k], g);
         }
-        T f = e;
+        T h = g;
 #pragma unroll
         for (int l = 0; l < DY; ++l) {
             T d = yi[l] - pj[DX + l];
-            f = fma_(d * d, cy[l], f);
+            h = fma_(d * d, ncy[l], h);
         }
-        ex = e;
-        exy = f;
+        g1 = g;
+        g2 = h;
     }
 
-    // Initial references: minima over the first points of the first tile.
+    // Initial references: minima of the exponents over the first points of
+    // the first tile.
     __device__ __forceinline__ void prologue(const T* tile, int len, int self)
     {
-        T a = inf_<T>(), b = inf_<T>();
+        T a = -inf_<T>(), b = -inf_<T>();
         for (int q = 0; q < len; ++q) {
             if (q == self) continue;
             T pj[S];
             load_row<S>(pj, tile + q * S);
-            T ex, exy;
-            exponents(pj, ex, exy);
-            a = min_(a, ex);
-            b = min_(b, exy);
+            T g1, g2;
+            neg_exponents(pj, g1, g2);
+            a = max_(a, g1);
+            b = max_(b, g2);
         }
-        m = a;
-        m2 = b;
+        m = -a;
+        m2 = -b;
     }
 
-    // One subtile of `len` points starting at tile row j0.  `self` is the
-    // tile row of point i itself (diagonal tile) or -1.
-    template <bool FULL, bool DIAG>
-    __device__ __forceinline__ void subtile(const T* tile, int j0, int len, int self)
+    // One pair (i, j): its kernel values relative to the current references
+    // and the squared coordinate differences the moments need.
+    struct Pair {
+        T w, v, sq[DX], sqy[DY];
+    };
+
+    // Evaluates pair (i, row jj).  The exponent is formed negated (reference
+    // minus exponent), so each kernel value is a plain 2^g.  TRACK also keeps
+    // the largest g of the subtile (its heaviest term); FIRST starts it.
+    template <bool MASK, bool TRACK, bool FIRST>
+    __device__ __forceinline__ void eval(const T* tile, int jj, int lim, int self, T dmn, Pair& r,
+                                         T& hi1, T& hi2) const
     {
-        const T slack = sizeof(T) == 4 ? T(32) : T(512);
-        for (;;) {
-            T pden = T(0), pnum = T(0), pmw[GX], pmv[GX], pmvy[GY];
+        T pj[S];
+        load_cols<DX + DY, S>(pj, tile + jj * S);
+        T g1 = m;
 #pragma unroll
-            for (int k = 0; k < GX; ++k) { pmw[k] = T(0); pmv[k] = T(0); }
+        for (int k = 0; k < DX; ++k) {
+            T d = xi[k] - pj[k];
+            r.sq[k] = d * d;
+            g1 = fma_(r.sq[k], ncx[k], g1);
+        }
+        T g2 = g1 + dmn;
 #pragma unroll
-            for (int l = 0; l < GY; ++l) pmvy[l] = T(0);
-            T mn1 = inf_<T>(), mn2 = inf_<T>();
-            const T dm = m - m2;
-            const int L = FULL ? SUB : len;
-#pragma unroll 8
-            for (int q = 0; q < L; ++q) {
-                const int jj = j0 + q;
-                T pj[S];
-                load_row<S>(pj, tile + jj * S);
-                T sq[DX], sqy[DY];
-                T e1 = -m;
+        for (int l = 0; l < DY; ++l) {
+            T d = yi[l] - pj[DX + l];
+            r.sqy[l] = d * d;
+            g2 = fma_(r.sqy[l], ncy[l], g2);
+        }
+        if (MASK) {
+            const bool off = (jj == self) || (jj >= lim);
+            g1 = off ? -inf_<T>() : g1;
+            g2 = off ? -inf_<T>() : g2;
+        }
+        r.w = exp2_<T>(g1);
+        r.v = exp2_<T>(g2);
+        if (TRACK) {
+            hi1 = FIRST ? g1 : max_(hi1, g1);
+            hi2 = FIRST ? g2 : max_(hi2, g2);
+        }
+    }
+
+    // Adds one evaluated pair to the subtile sums (FIRST starts them).
+    template <bool FIRST>
+    __device__ __forceinline__ void accum(T (&p)[NA], const Pair& r) const
+    {
+        if (FIRST) {
+            p[0] = r.w;
+            p[1] = r.v;
+            if (GRAD) {
+#pragma unroll
+                for (int k = 0; k < DX; ++k) { p[MW + k] = r.w * r.sq[k]; p[MV + k] = r.v * r.sq[k]; }
+#pragma unroll
+                for (int l = 0; l < DY; ++l) p[MVY + l] = r.v * r.sqy[l];
+            }
+        } else {
+            p[0] += r.w;
+            p[1] += r.v;
+            if (GRAD) {
 #pragma unroll
                 for (int k = 0; k < DX; ++k) {
-                    T d = xi[k] - pj[k];
-                    sq[k] = d * d;
-                    e1 = fma_(sq[k], cx[k], e1);
+                    p[MW + k] = fma_(r.w, r.sq[k], p[MW + k]);
+                    p[MV + k] = fma_(r.v, r.sq[k], p[MV + k]);
                 }
-                T e2 = e1 + dm;
 #pragma unroll
-                for (int l = 0; l < DY; ++l) {
-                    T d = yi[l] - pj[DX + l];
-                    sqy[l] = d * d;
-                    e2 = fma_(sqy[l], cy[l], e2);
-                }
-                if (DIAG) {
-                    const bool me = (jj == self);
-                    e1 = me ? inf_<T>() : e1;
-                    e2 = me ? inf_<T>() : e2;
-                }
-                mn1 = min_(mn1, e1);
-                mn2 = min_(mn2, e2);
-                const T w = exp2_<T>(-e1);
-                const T v = exp2_<T>(-e2);
-                pden += w;
-                pnum += v;
-                if (GRAD) {
-#pragma unroll
-                    for (int k = 0; k < DX; ++k) {
-                        pmw[k] = fma_(w, sq[k], pmw[k]);
-                        pmv[k] = fma_(v, sq[k], pmv[k]);
-                    }
-#pragma unroll
-                    for (int l = 0; l < DY; ++l) pmvy[l] = fma_(v, sqy[l], pmvy[l]);
-                }
-            }
-            const bool need = (mn1 < -slack) || (mn2 < -slack);
-            if (!__any(need)) {
-                den.add(pden);
-                num.add(pnum);
-                if (GRAD) {
-#pragma unroll
-                    for (int k = 0; k < DX; ++k) { mw[k].add(pmw[k]); mv[k].add(pmv[k]); }
-#pragma unroll
-                    for (int l = 0; l < DY; ++l) mvy[l].add(pmvy[l]);
-                }
-                return;
-            }
-            // A much heavier term appeared: move the reference to it, rescale
-            // the totals, and recompute this subtile against the new reference.
-            if (mn1 < -slack) {
-                const T f = exp2_<T>(mn1);
-                den.scale(f);
-#pragma unroll
-                for (int k = 0; k < GX; ++k) mw[k].scale(f);
-                m += mn1;
-            }
-            if (mn2 < -slack) {
-                const T f = exp2_<T>(mn2);
-                num.scale(f);
-#pragma unroll
-                for (int k = 0; k < GX; ++k) mv[k].scale(f);
-#pragma unroll
-                for (int l = 0; l < GY; ++l) mvy[l].scale(f);
-                m2 += mn2;
+                for (int l = 0; l < DY; ++l) p[MVY + l] = fma_(r.v, r.sqy[l], p[MVY + l]);
             }
         }
     }
+
+    // Sums of one subtile of SUB points starting at tile row j0, relative to
+    // the current references (and, with TRACK, the subtile's largest negated
+    // exponents).  MASK drops row `self` (point i itself) and rows at or
+    // beyond `lim`.  Without the gradient the loop is software-pipelined by
+    // one pair (pair q's exponentials are in flight while pair q-1 is added);
+    // with it, the moments already fill the registers of four waves per SIMD
+    // and the plain loop is kept.
+    template <bool MASK, bool TRACK>
+    __device__ __forceinline__ void sums(const T* tile, int j0, int lim, int self, T (&p)[NA],
+                                         T& hi1, T& hi2) const
+    {
+        const T dmn = m2 - m;
+        if constexpr (GRAD) {
+            Pair r;
+            eval<MASK, TRACK, true>(tile, j0, lim, self, dmn, r, hi1, hi2);
+            accum<true>(p, r);
+#pragma unroll
+            for (int q = 1; q < 8; ++q) {
+                eval<MASK, TRACK, false>(tile, j0 + q, lim, self, dmn, r, hi1, hi2);
+                accum<false>(p, r);
+            }
+#pragma unroll 8
+            for (int q = 8; q < SUB; ++q) {
+                eval<MASK, TRACK, false>(tile, j0 + q, lim, self, dmn, r, hi1, hi2);
+                accum<false>(p, r);
+            }
+        } else {
+            Pair cur, nxt;
+            eval<MASK, TRACK, true>(tile, j0, lim, self, dmn, cur, hi1, hi2);
+            eval<MASK, TRACK, false>(tile, j0 + 1, lim, self, dmn, nxt, hi1, hi2);
+            accum<true>(p, cur);
+            cur = nxt;
+#pragma unroll 6
+            for (int q = 2; q < SUB; ++q) {
+                eval<MASK, TRACK, false>(tile, j0 + q, lim, self, dmn, nxt, hi1, hi2);
+                accum<false>(p, cur);
+                cur = nxt;
+            }
+            accum<false>(p, cur);
+        }
+    }
+
+    // Moves the reference of each lane whose subtile holds a term above it
+    // to that heaviest term and rescales what the lane has summed so far
+    // (exact in real arithmetic: the common factor cancels in num/den).  With
+    // WITH_P the current subtile's sums are rescaled too.
+    template <bool WITH_P>
+    __device__ __forceinline__ void move_refs(T hi1, T hi2, T (&p)[NA])
+    {
+        if (hi1 > T(0)) {
+            const T f = exp2_<T>(-hi1);
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+                if (in_first(a)) {
+                    scale_total(a, f);
+                    mid[a] *= f;
+                    if (WITH_P) p[a] *= f;
+                }
+            m -= hi1;
+        }
+        if (hi2 > T(0)) {
+            const T f = exp2_<T>(-hi2);
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+                if (!in_first(a)) {
+                    scale_total(a, f);
+                    mid[a] *= f;
+                    if (WITH_P) p[a] *= f;
+                }
+            m2 -= hi2;
+        }
+    }
+
+    // One subtile, added to the tile sums.  The pair loop keeps no minima: a
+    // subtile sum above 2^slack (or an overflow) is what reveals a term far
+    // above its reference.  Then the subtile is summed again with its largest
+    // negated exponents tracked and the references move to the heaviest
+    // terms.  A term up to 2^big above its reference is representable, so
+    // below that the subtile's sums are rescaled with the totals (terms that
+    // underflowed against the old reference are negligible against the new,
+    // lower one); a heavier term, which may have overflowed, makes the
+    // subtile be summed a third time against the moved references.
+    template <bool MASK>
+    __device__ __forceinline__ void subtile(const T* tile, int j0, int lim, int self)
+    {
+        const T sum_lim = sizeof(T) == 4 ? T(0x1p32) : T(0x1p512);
+        const T big = sizeof(T) == 4 ? T(64) : T(640);
+        T p[NA], hi1, hi2;
+        sums<MASK, false>(tile, j0, lim, self, p, hi1, hi2);
+        if (__any((p[0] > sum_lim) || (p[1] > sum_lim))) {
+            sums<MASK, true>(tile, j0, lim, self, p, hi1, hi2);
+            if (__any((hi1 > big) || (hi2 > big))) {
+                move_refs<false>(hi1, hi2, p);
+                sums<MASK, false>(tile, j0, lim, self, p, hi1, hi2);
+            } else {
+                move_refs<true>(hi1, hi2, p);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NA; ++a) mid[a] += p[a];
+    }
+
+    // All rows of one LDS tile holding `cnt` points; `self` is the tile row
+    // of point i (diagonal tile) or -1.  Full off-diagonal tiles take the
+    // unmasked path.
+    __device__ __forceinline__ void tile_pass(const T* tile, int cnt, int self)
+    {
+        begin_tile();
+        if (self >= 0 || cnt < TILE) {
+            for (int j0 = 0; j0 < cnt; j0 += SUB) subtile<true>(tile, j0, cnt, self);
+        } else {
+            for (int j0 = 0; j0 < TILE; j0 += SUB) subtile<false>(tile, j0, TILE, -1);
+        }
+        end_tile();
+    }
+
+    __device__ __forceinline__ double den() const { return total(0); }
+    __device__ __forceinline__ double num() const { return total(1); }
 };
 
 }  // namespace
@@ -196,6 +322,7 @@ __global__ __launch_bounds__(TILE) void k_loo_diag(const T* __restrict__ pts, in
     constexpr int NV = GRAD ? P + 2 : 2;  // l_i, [gradient], non-finite count
     __shared__ T tile[TILE * S];
     __shared__ double red[4 * NV];
+    __shared__ double totals[L::LDS_DOUBLES];
 
     const DiagSet<T>& st = sets.s[blockIdx.y];
     const int tid = threadIdx.x;
@@ -206,11 +333,11 @@ __global__ __launch_bounds__(TILE) void k_loo_diag(const T* __restrict__ pts, in
         T own[S];
         load_row<S>(own, pts + (size_t)i * S);
 #pragma unroll
-        for (int k = 0; k < DX; ++k) { lane.xi[k] = own[k]; lane.cx[k] = st.c[k]; }
+        for (int k = 0; k < DX; ++k) { lane.xi[k] = own[k]; lane.ncx[k] = vreg(-st.c[k]); }
 #pragma unroll
-        for (int l = 0; l < DY; ++l) { lane.yi[l] = own[DX + l]; lane.cy[l] = st.c[DX + l]; }
+        for (int l = 0; l < DY; ++l) { lane.yi[l] = own[DX + l]; lane.ncy[l] = vreg(-st.c[DX + l]); }
     }
-    lane.init_accumulators();
+    lane.init_accumulators(totals);
 
     const int ntiles = (n + TILE - 1) / TILE;
     T pre[S];
@@ -221,24 +348,14 @@ __global__ __launch_bounds__(TILE) void k_loo_diag(const T* __restrict__ pts, in
         __syncthreads();
         if (t + 1 < ntiles) load_row<S>(pre, pts + ((size_t)(t + 1) * TILE + tid) * S);
         const int cnt = min(TILE, n - t * TILE);
-        const bool diag = (t == (int)blockIdx.x);
-        const int self = diag ? tid : -1;
+        const int self = (t == (int)blockIdx.x) ? tid : -1;
         if (t == 0) lane.prologue(tile, min(L::SUB, cnt), self);
-        for (int j0 = 0; j0 < cnt; j0 += L::SUB) {
-            const int len = min(L::SUB, cnt - j0);
-            if (len == L::SUB) {
-                if (diag) lane.template subtile<true, true>(tile, j0, len, self);
-                else lane.template subtile<true, false>(tile, j0, len, self);
-            } else {
-                if (diag) lane.template subtile<false, true>(tile, j0, len, self);
-                else lane.template subtile<false, false>(tile, j0, len, self);
-            }
-        }
+        lane.tile_pass(tile, cnt, self);
     }
 
     // Per-point finalisation in FP64.
     const bool valid = i < n;
-    const double D = lane.den.value(), U = lane.num.value();
+    const double D = lane.den(), U = lane.num();
     double v[NV];
     double ell;
     if (crit == CDE_COND)
@@ -249,15 +366,15 @@ __global__ __launch_bounds__(TILE) void k_loo_diag(const T* __restrict__ pts, in
     if (GRAD) {
 #pragma unroll
         for (int k = 0; k < DX; ++k) {
-            const double gv = lane.mv[k].value() / U;
-            const double gw = lane.mw[k].value() / D;
+            const double gv = lane.total(L::MV + k) / U;
+            const double gw = lane.total(L::MW + k) / D;
             const double g = crit == CDE_COND ? (gv - gw) * st.inv_h3[k]
                                               : gv * st.inv_h3[k] - st.inv_h[k];
             v[1 + k] = valid ? g : 0.0;
         }
 #pragma unroll
         for (int l = 0; l < DY; ++l) {
-            const double g = (lane.mvy[l].value() / U) * st.inv_h3[DX + l] - st.inv_h[DX + l];
+            const double g = (lane.total(L::MVY + l) / U) * st.inv_h3[DX + l] - st.inv_h[DX + l];
             v[1 + DX + l] = valid ? g : 0.0;
         }
     }
@@ -285,6 +402,7 @@ __global__ __launch_bounds__(TILE) void k_query(const T* __restrict__ pts, int n
     using L = DiagLane<T, DX, DY, false>;
     constexpr int S = L::S;
     __shared__ T tile[TILE * S];
+    __shared__ double totals[L::LDS_DOUBLES];
     const DiagSet<T>& st = sets.s[0];
     const int tid = threadIdx.x;
     const int64_t e = (int64_t)blockIdx.x * TILE + tid;
@@ -294,10 +412,10 @@ __global__ __launch_bounds__(TILE) void k_query(const T* __restrict__ pts, int n
 
     L lane;
 #pragma unroll
-    for (int kk = 0; kk < DX; ++kk) { lane.xi[kk] = xq[qq * DX + kk]; lane.cx[kk] = st.c[kk]; }
+    for (int kk = 0; kk < DX; ++kk) { lane.xi[kk] = xq[qq * DX + kk]; lane.ncx[kk] = -st.c[kk]; }
 #pragma unroll
-    for (int l = 0; l < DY; ++l) { lane.yi[l] = yg[gg * DY + l]; lane.cy[l] = st.c[DX + l]; }
-    lane.init_accumulators();
+    for (int l = 0; l < DY; ++l) { lane.yi[l] = yg[gg * DY + l]; lane.ncy[l] = -st.c[DX + l]; }
+    lane.init_accumulators(totals);
 
     const int ntiles = (n + TILE - 1) / TILE;
     T pre[S];
@@ -309,14 +427,10 @@ __global__ __launch_bounds__(TILE) void k_query(const T* __restrict__ pts, int n
         if (t + 1 < ntiles) load_row<S>(pre, pts + ((size_t)(t + 1) * TILE + tid) * S);
         const int cnt = min(TILE, n - t * TILE);
         if (t == 0) lane.prologue(tile, min(L::SUB, cnt), -1);
-        for (int j0 = 0; j0 < cnt; j0 += L::SUB) {
-            const int len = min(L::SUB, cnt - j0);
-            if (len == L::SUB) lane.template subtile<true, false>(tile, j0, len, -1);
-            else lane.template subtile<false, false>(tile, j0, len, -1);
-        }
+        lane.tile_pass(tile, cnt, -1);
     }
     if (e < total) {
-        const double D = lane.den.value(), U = lane.num.value();
+        const double D = lane.den(), U = lane.num();
         f[e] = exp(log(U / D) + ((double)lane.m - (double)lane.m2) * LN2 + st.log_cy);
     }
 }
