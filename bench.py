@@ -43,7 +43,7 @@ PAIR_F, PAIR_E = 31.0, 2.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs, each scaled by the same counter's
 # reading for a 256 MiB copy (profiles/k_loo_diag_f32_5x1_grad_photoz500k.md).
 # Set to None whenever that kernel changes, until the counters are re-taken.
-DIAG_TRAFFIC_BYTES = 986_713_000
+DIAG_TRAFFIC_BYTES = 958_886_000
 
 
 def parse():
@@ -145,8 +145,9 @@ def main():
     pairs = float(n) * (n - 1)
     value = pairs / (wall / args.steps)
 
-    # The event pair brackets k_loo_diag (>99.9% of it) and the few-microsecond
-    # block-partial reduction that follows it on the same stream.
+    # The event pair brackets the pair kernel k_loo_diag (>99.9% of it), the
+    # 0.13 ms chunk combine and the few-microsecond block-partial reduction
+    # that follow it on the same stream.
     kern_ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
     slots = pairs * (PAIR_F + EXP_SLOTS * PAIR_E)
     achieved = slots / (kern_ms * 1e-3) / 1e12

@@ -107,17 +107,20 @@ cde_status run_diag_list(cde_model* m, const double* h, int g, int crit, bool gr
     const int p = m->dx + m->dy;
     const int nblocks = (int)(m->npad / TILE);
     const int nv = grad ? p + 2 : 2;
-    const size_t part_bytes = sizeof(double) * (size_t)g * nblocks * nv;
-    const size_t cnt_bytes = sizeof(double) * (size_t)g;
-    cde_status st = ensure_scratch(m, part_bytes + cnt_bytes + 256);
+    const int per_launch = std::min(g, MAX_SETS_PER_LAUNCH);
+    const int chunks = diag_chunks<T>(m, per_launch, grad, MAX_DIAG_PARTIAL_DOUBLES);
+    const size_t part_doubles = (size_t)g * nblocks * nv + (size_t)g;  // rows, then counts
+    const size_t partial_doubles = diag_partial_doubles(m, per_launch, grad, chunks);
+    cde_status st = ensure_scratch(m, sizeof(double) * (part_doubles + partial_doubles) + 256);
     if (st != CDE_OK) return st;
     double* part = (double*)m->scratch;
+    double* partial = part + part_doubles;
     for (int s0 = 0; s0 < g; s0 += MAX_SETS_PER_LAUNCH) {
         const int cnt = std::min(MAX_SETS_PER_LAUNCH, g - s0);
         DiagSets<T> sets;
         std::memset(&sets, 0, sizeof sets);
         for (int s = 0; s < cnt; ++s) fill_set(sets.s[s], h + (size_t)(s0 + s) * p, m->dx, m->dy);
-        hipError_t e = launch_diag<T>(m, sets, cnt, crit, grad,
+        hipError_t e = launch_diag<T>(m, sets, cnt, crit, grad, chunks, partial,
                                       per_point ? per_point + (size_t)s0 * m->n : nullptr,
                                       part + (size_t)s0 * nblocks * nv, stream);
         if (e != hipSuccess) return hip_fail(e, "launch k_loo_diag");
@@ -161,6 +164,8 @@ cde_status cde_create(cde_model** out, const void* x_dev, const void* y_dev, int
         m->prec = precision;
         hipError_t e = hipGetDevice(&m->device);
         if (e != hipSuccess) { delete m; return hip_fail(e, "hipGetDevice"); }
+        e = hipDeviceGetAttribute(&m->ncu, hipDeviceAttributeMultiprocessorCount, m->device);
+        if (e != hipSuccess) { delete m; return hip_fail(e, "hipDeviceGetAttribute"); }
         const size_t elt = precision == CDE_F64 ? sizeof(double) : sizeof(float);
         const size_t pts_bytes = (size_t)m->npad * m->stride * elt;
         e = hipMalloc(&m->pts, pts_bytes);

@@ -33,6 +33,8 @@ struct DiagSet {
 };
 
 constexpr int MAX_SETS_PER_LAUNCH = 8;
+// Cap on the chunk partials of one diagonal launch (2 GiB of doubles).
+constexpr size_t MAX_DIAG_PARTIAL_DOUBLES = size_t(1) << 28;
 
 template <typename T>
 struct DiagSets {
@@ -48,6 +50,7 @@ struct cde_model {
     int32_t dx = 0, dy = 0, stride = 0;
     cde_precision prec = CDE_F32;
     int device = 0;
+    int ncu = 0;             // compute units of the device
     void* pts = nullptr;     // [npad][stride] of float or double
     // per-point nearest-neighbour squared distances (unscaled), min over j != i,
     // in x and in y separately; computed once, used as the grid kernel's shifts

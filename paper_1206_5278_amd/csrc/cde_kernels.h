@@ -10,10 +10,21 @@ template <typename T>
 hipError_t launch_pack(cde_model* m, const T* x, const T* y, hipStream_t stream);
 
 // Diagonal-bandwidth LOO pass (value, optionally gradient) for `nsets`
-// settings; writes one partial row per (setting, 256-point block) to `part`.
+// settings.  The j range is split into `chunks` chunks (diag_chunks); the
+// pair kernel writes per-(setting, chunk, point) partial sums to `partial`
+// (diag_partial_doubles), and a combine kernel merges the chunks in fixed
+// order, finalises each point in FP64 and writes one row per (setting,
+// 256-point block) to `part`.
 template <typename T>
 hipError_t launch_diag(const cde_model* m, const DiagSets<T>& sets, int nsets, int crit, bool grad,
-                       double* per_point, double* part, hipStream_t stream);
+                       int chunks, double* partial, double* per_point, double* part,
+                       hipStream_t stream);
+// Number of j chunks that best fills the device for `nsets` settings per
+// launch (a makespan model over the kernel's occupancy), within `max_doubles`
+// of partial storage.
+template <typename T>
+int diag_chunks(const cde_model* m, int nsets, bool grad, size_t max_doubles);
+size_t diag_partial_doubles(const cde_model* m, int nsets, bool grad, int chunks);
 
 // Density queries f(yg[g] | xq[q]) over all training points -> f [q][k].
 template <typename T>

@@ -30,6 +30,8 @@
 // reference.  The log of the ratio, the gradient combination and the sum
 // over i run in FP64.
 
+#include <cmath>
+
 #include "cde_device.h"
 #include "cde_kernels.h"
 
@@ -45,6 +47,7 @@ struct DiagLane {
     // sum v dx_k^2 and sum v dy_l^2.  The first group (den, w moments) is
     // relative to m, the second (num, v moments) to m2.
     static constexpr int NA = GRAD ? 2 + 2 * DX + DY : 2;
+    static constexpr int NP = NA + 2;  // partial record: m, m2, then the NA totals
     static constexpr int MW = 2, MV = 2 + DX, MVY = 2 + 2 * DX;
 
     // Per-point totals: FP64 columns in LDS (column a of thread t at
@@ -54,6 +57,7 @@ struct DiagLane {
 
     T xi[DX], yi[DY], ncx[DX], ncy[DY];  // coordinates of i; negated kernel scales
     T m, m2;         // references of the x-kernel sums and of the product-kernel sums
+    bool empty;      // no pair in this lane's j range
     double* lds;     // this thread's first total
     T mid[NA];       // plain sums of the subtiles of the current tile
 
@@ -75,7 +79,7 @@ struct DiagLane {
 #pragma unroll
         for (int a = 0; a < NA; ++a) lds[a * TILE] += (double)mid[a];
     }
-    __device__ __forceinline__ bool in_first(int a) const
+    static __host__ __device__ constexpr bool in_first(int a)
     {
         return a == 0 || (GRAD && a >= MW && a < MV);
     }
@@ -114,8 +118,11 @@ struct DiagLane {
             a = max_(a, g1);
             b = max_(b, g2);
         }
-        m = -a;
-        m2 = -b;
+        // No candidate: the chunk's first tile holds point i alone, so the
+        // chunk has no j != i; any finite reference serves (all terms are 0).
+        empty = !(a > -inf_<T>());
+        m = empty ? T(0) : -a;
+        m2 = empty ? T(0) : -b;
     }
 
     // One pair (i, j): its kernel values relative to the current references
@@ -310,18 +317,20 @@ struct DiagLane {
 
 }  // namespace
 
+// Pair pass over one chunk of j tiles for 256 points and one setting
+// (blockIdx.x: point block, blockIdx.y: setting, blockIdx.z: chunk of
+// `tiles_per_chunk` tiles).  Each lane writes its partial record (the two
+// references, then the NA totals relative to them) as NP planes of npad
+// doubles at partial[((setting * chunks + chunk) * NP + field) * npad + i];
+// an empty j range is marked by infinite references.
 template <typename T, int DX, int DY, bool GRAD>
-__global__ __launch_bounds__(TILE) void k_loo_diag(const T* __restrict__ pts, int n,
-                                                   DiagSets<T> sets, int crit,
-                                                   double* __restrict__ per_point,
-                                                   double* __restrict__ part)
+__global__ __launch_bounds__(TILE) void k_loo_diag(const T* __restrict__ pts, int n, int npad,
+                                                   DiagSets<T> sets, int tiles_per_chunk,
+                                                   double* __restrict__ partial)
 {
     using L = DiagLane<T, DX, DY, GRAD>;
     constexpr int S = L::S;
-    constexpr int P = DX + DY;
-    constexpr int NV = GRAD ? P + 2 : 2;  // l_i, [gradient], non-finite count
     __shared__ T tile[TILE * S];
-    __shared__ double red[4 * NV];
     __shared__ double totals[L::LDS_DOUBLES];
 
     const DiagSet<T>& st = sets.s[blockIdx.y];
@@ -340,41 +349,90 @@ __global__ __launch_bounds__(TILE) void k_loo_diag(const T* __restrict__ pts, in
     lane.init_accumulators(totals);
 
     const int ntiles = (n + TILE - 1) / TILE;
+    const int t0 = blockIdx.z * tiles_per_chunk;
+    const int t1 = min(ntiles, t0 + tiles_per_chunk);
     T pre[S];
-    load_row<S>(pre, pts + (size_t)tid * S);
-    for (int t = 0; t < ntiles; ++t) {
+    load_row<S>(pre, pts + ((size_t)t0 * TILE + tid) * S);
+    for (int t = t0; t < t1; ++t) {
         __syncthreads();
         store_row<S>(tile + tid * S, pre);
         __syncthreads();
-        if (t + 1 < ntiles) load_row<S>(pre, pts + ((size_t)(t + 1) * TILE + tid) * S);
+        if (t + 1 < t1) load_row<S>(pre, pts + ((size_t)(t + 1) * TILE + tid) * S);
         const int cnt = min(TILE, n - t * TILE);
         const int self = (t == (int)blockIdx.x) ? tid : -1;
-        if (t == 0) lane.prologue(tile, min(L::SUB, cnt), self);
+        if (t == t0) lane.prologue(tile, min(L::SUB, cnt), self);
         lane.tile_pass(tile, cnt, self);
     }
 
-    // Per-point finalisation in FP64.
+    double* o = partial + ((size_t)(blockIdx.y * gridDim.z + blockIdx.z) * L::NP) * npad + i;
+    o[0] = lane.empty ? inf_<double>() : (double)lane.m;
+    o[npad] = lane.empty ? inf_<double>() : (double)lane.m2;
+#pragma unroll
+    for (int a = 0; a < L::NA; ++a) o[(size_t)(2 + a) * npad] = lane.total(a);
+}
+
+// Merges the chunk partials of each point in chunk order and finalises it
+// in FP64: totals relative to the smallest reference M are the sum over
+// chunks of total_c * 2^(M - m_c) (each factor <= 1; an empty chunk, with
+// m_c infinite, contributes nothing).  Then l_i (and its gradient terms),
+// the per-point output and one fixed-order block row of part per (setting,
+// 256-point block).
+template <typename T, int DX, int DY, bool GRAD>
+__global__ __launch_bounds__(TILE) void k_diag_combine(const double* __restrict__ partial,
+                                                       int chunks, int n, int npad,
+                                                       DiagSets<T> sets, int crit,
+                                                       double* __restrict__ per_point,
+                                                       double* __restrict__ part)
+{
+    using L = DiagLane<T, DX, DY, GRAD>;
+    constexpr int NA = L::NA, NP = L::NP;
+    constexpr int P = DX + DY;
+    constexpr int NV = GRAD ? P + 2 : 2;  // l_i, [gradient], non-finite count
+    __shared__ double red[4 * NV];
+
+    const DiagSet<T>& st = sets.s[blockIdx.y];
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x * TILE + tid;
+    const double* base = partial + (size_t)blockIdx.y * chunks * NP * npad + i;
+
+    double M = inf_<double>(), M2 = inf_<double>();
+    for (int c = 0; c < chunks; ++c) {
+        M = fmin(M, base[(size_t)c * NP * npad]);
+        M2 = fmin(M2, base[((size_t)c * NP + 1) * npad]);
+    }
+    double tot[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) tot[a] = 0.0;
+    for (int c = 0; c < chunks; ++c) {
+        const double* r = base + (size_t)c * NP * npad;
+        const double mc = r[0], m2c = r[npad];
+        const double f1 = isinf(mc) ? 0.0 : exp2(M - mc);
+        const double f2 = isinf(m2c) ? 0.0 : exp2(M2 - m2c);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) tot[a] += r[(size_t)(2 + a) * npad] * (L::in_first(a) ? f1 : f2);
+    }
+
     const bool valid = i < n;
-    const double D = lane.den(), U = lane.num();
+    const double D = tot[0], U = tot[1];
     double v[NV];
     double ell;
     if (crit == CDE_COND)
-        ell = log(U / D) + ((double)lane.m - (double)lane.m2) * LN2 + st.log_cy;
+        ell = log(U / D) + (M - M2) * LN2 + st.log_cy;
     else
-        ell = log(U) - (double)lane.m2 * LN2 + st.log_cx + st.log_cy - log((double)(n - 1));
+        ell = log(U) - M2 * LN2 + st.log_cx + st.log_cy - log((double)(n - 1));
     v[0] = valid ? ell : 0.0;
     if (GRAD) {
 #pragma unroll
         for (int k = 0; k < DX; ++k) {
-            const double gv = lane.total(L::MV + k) / U;
-            const double gw = lane.total(L::MW + k) / D;
+            const double gv = tot[L::MV + k] / U;
+            const double gw = tot[L::MW + k] / D;
             const double g = crit == CDE_COND ? (gv - gw) * st.inv_h3[k]
                                               : gv * st.inv_h3[k] - st.inv_h[k];
             v[1 + k] = valid ? g : 0.0;
         }
 #pragma unroll
         for (int l = 0; l < DY; ++l) {
-            const double g = (lane.total(L::MVY + l) / U) * st.inv_h3[DX + l] - st.inv_h[DX + l];
+            const double g = (tot[L::MVY + l] / U) * st.inv_h3[DX + l] - st.inv_h[DX + l];
             v[1 + DX + l] = valid ? g : 0.0;
         }
     }
@@ -468,26 +526,70 @@ template hipError_t launch_query<float>(const cde_model*, const float*, int64_t,
 template hipError_t launch_query<double>(const cde_model*, const double*, int64_t, const double*,
                                          int64_t, const DiagSets<double>&, double*, hipStream_t);
 
+// Tiles per chunk for a given chunk count (every chunk non-empty).
+static int tiles_per_chunk(int ntiles, int chunks) { return (ntiles + chunks - 1) / chunks; }
+
 template <typename T, int DX, int DY, bool GRAD>
 static hipError_t launch_diag_t(const cde_model* m, const DiagSets<T>& sets, int nsets, int crit,
-                                double* per_point, double* part, hipStream_t stream)
+                                int chunks, double* partial, double* per_point, double* part,
+                                hipStream_t stream)
 {
-    dim3 grid((unsigned)(m->npad / TILE), (unsigned)nsets);
-    hipLaunchKernelGGL((k_loo_diag<T, DX, DY, GRAD>), grid, dim3(TILE), 0, stream,
-                       (const T*)m->pts, (int)m->n, sets, crit, per_point, part);
+    const int nblocks = (int)(m->npad / TILE);
+    const int tpc = tiles_per_chunk(nblocks, chunks);
+    const int used = (nblocks + tpc - 1) / tpc;
+    hipLaunchKernelGGL((k_loo_diag<T, DX, DY, GRAD>), dim3(nblocks, nsets, used), dim3(TILE), 0,
+                       stream, (const T*)m->pts, (int)m->n, (int)m->npad, sets, tpc, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_diag_combine<T, DX, DY, GRAD>), dim3(nblocks, nsets), dim3(TILE), 0,
+                       stream, (const double*)partial, used, (int)m->n, (int)m->npad, sets, crit,
+                       per_point, part);
     return hipGetLastError();
 }
 
-#define CDE_DIAG_CASE(DX_, DY_)                                                            \
-    case (DX_) * 8 + (DY_):                                                                \
-        return grad ? launch_diag_t<T, DX_, DY_, true>(m, sets, nsets, crit, per_point, part, \
-                                                       stream)                             \
-                    : launch_diag_t<T, DX_, DY_, false>(m, sets, nsets, crit, per_point,   \
-                                                        part, stream);
+// Chunk count by a makespan model: with B = blocks per chunk layer and R
+// resident blocks per CU, C chunks of ceil(ntiles / C) tiles run in
+// ceil(B C / (R * CUs)) rounds, each as long as its tiles plus the chunk's
+// start-up (the 32-pair reference pass, about 1/8 of a tile).  The smallest
+// C of least modelled time wins, within the partial-storage cap.
+template <typename T, int DX, int DY, bool GRAD>
+static int diag_chunks_t(const cde_model* m, int nsets, size_t max_doubles)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_loo_diag<T, DX, DY, GRAD>, TILE, 0) !=
+            hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const double slots = (double)per_cu * (m->ncu > 0 ? m->ncu : 1);
+    const int ntiles = (int)(m->npad / TILE);
+    const double layer = (double)ntiles * nsets;
+    constexpr int NP = DiagLane<T, DX, DY, GRAD>::NP;
+    int best = 1;
+    double best_t = 0.0;
+    for (int c = 1; c <= 64 && c <= ntiles; ++c) {
+        const int tpc = tiles_per_chunk(ntiles, c);
+        const int used = (ntiles + tpc - 1) / tpc;
+        if (used != c) continue;
+        if ((size_t)nsets * used * NP * (size_t)m->npad > max_doubles) break;
+        const double t = std::ceil(layer * used / slots) * (tpc + 0.125);
+        if (c == 1 || t < best_t * (1.0 - 1e-9)) {
+            best = c;
+            best_t = t;
+        }
+    }
+    return best;
+}
+
+#define CDE_DIAG_CASE(DX_, DY_)                                                                 \
+    case (DX_) * 8 + (DY_):                                                                     \
+        return grad ? launch_diag_t<T, DX_, DY_, true>(m, sets, nsets, crit, chunks, partial,    \
+                                                       per_point, part, stream)                 \
+                    : launch_diag_t<T, DX_, DY_, false>(m, sets, nsets, crit, chunks, partial,   \
+                                                        per_point, part, stream);
 
 template <typename T>
 hipError_t launch_diag(const cde_model* m, const DiagSets<T>& sets, int nsets, int crit, bool grad,
-                       double* per_point, double* part, hipStream_t stream)
+                       int chunks, double* partial, double* per_point, double* part,
+                       hipStream_t stream)
 {
     switch (m->dx * 8 + m->dy) {
         CDE_DIAG_CASE(1, 1) CDE_DIAG_CASE(1, 2) CDE_DIAG_CASE(2, 1) CDE_DIAG_CASE(2, 2)
@@ -499,9 +601,35 @@ hipError_t launch_diag(const cde_model* m, const DiagSets<T>& sets, int nsets, i
     }
 }
 
-template hipError_t launch_diag<float>(const cde_model*, const DiagSets<float>&, int, int, bool,
-                                       double*, double*, hipStream_t);
+#define CDE_CHUNK_CASE(DX_, DY_)                                                 \
+    case (DX_) * 8 + (DY_):                                                      \
+        return grad ? diag_chunks_t<T, DX_, DY_, true>(m, nsets, max_doubles)    \
+                    : diag_chunks_t<T, DX_, DY_, false>(m, nsets, max_doubles);
+
+template <typename T>
+int diag_chunks(const cde_model* m, int nsets, bool grad, size_t max_doubles)
+{
+    switch (m->dx * 8 + m->dy) {
+        CDE_CHUNK_CASE(1, 1) CDE_CHUNK_CASE(1, 2) CDE_CHUNK_CASE(2, 1) CDE_CHUNK_CASE(2, 2)
+        CDE_CHUNK_CASE(3, 1) CDE_CHUNK_CASE(3, 2) CDE_CHUNK_CASE(4, 1) CDE_CHUNK_CASE(4, 2)
+        CDE_CHUNK_CASE(5, 1) CDE_CHUNK_CASE(5, 2) CDE_CHUNK_CASE(6, 1) CDE_CHUNK_CASE(6, 2)
+        CDE_CHUNK_CASE(7, 1) CDE_CHUNK_CASE(7, 2) CDE_CHUNK_CASE(8, 1) CDE_CHUNK_CASE(8, 2)
+        CDE_CHUNK_CASE(16, 1) CDE_CHUNK_CASE(16, 2)
+        default: return 1;
+    }
+}
+
+size_t diag_partial_doubles(const cde_model* m, int nsets, bool grad, int chunks)
+{
+    const int na = grad ? 2 + 2 * m->dx + m->dy : 2;
+    return (size_t)nsets * chunks * (na + 2) * (size_t)m->npad;
+}
+
+template hipError_t launch_diag<float>(const cde_model*, const DiagSets<float>&, int, int, bool, int,
+                                       double*, double*, double*, hipStream_t);
 template hipError_t launch_diag<double>(const cde_model*, const DiagSets<double>&, int, int, bool,
-                                        double*, double*, hipStream_t);
+                                        int, double*, double*, double*, hipStream_t);
+template int diag_chunks<float>(const cde_model*, int, bool, size_t);
+template int diag_chunks<double>(const cde_model*, int, bool, size_t);
 
 }  // namespace cde

@@ -128,6 +128,44 @@ def test_tiny_hy_shift_path():
     P.assert_total(t, rt, rp)
 
 
+def _far_prologue_data(n, seed, far_x, far_y):
+    """Rows 0..39 sit far away (at far_x in x, far_y in y); the rest form a
+    tight cluster at the origin.  The per-point references of cluster points
+    start from rows 0..31, so their first cluster terms are 2^gap heavier."""
+    rng = np.random.default_rng(seed)
+    x = 1e-3 * rng.normal(size=(n, 1))
+    y = 1e-2 * rng.normal(size=(n, 1))
+    x[:40] += far_x
+    y[:40] += far_y
+    return x, y
+
+
+# (far_x, far_y, hx, hy): gap = c * far^2 with c = log2(e) / (2 h^2) decides the
+# path: gap 30 (24 cluster terms make a subtile sum above 2^32 with no single
+# term above 2^32), gap 43 (rescale in place), gap 288 (overflow: summed again),
+# and a gap in the y kernel alone (only the product-kernel reference moves).
+@pytest.mark.parametrize("far_x,far_y,hx,hy", [
+    (1.0, 0.0, 0.155, 0.3),
+    (1.0, 0.0, 0.13, 0.3),
+    (1.0, 0.0, 0.05, 0.3),
+    (0.0, 1.0, 0.3, 0.05),
+])
+@pytest.mark.parametrize("crit", ["cond", "joint"])
+def test_reference_moves(far_x, far_y, hx, hy, crit):
+    say(f"case: reference moves far=({far_x},{far_y}) h=({hx},{hy}) {crit}")
+    x, y = _far_prologue_data(600, 11, far_x, far_y)
+    (t, g, pp), (rt, rg, rp) = run_grad(x, y, [hx, hy], crit)
+    assert np.all(np.isfinite(pp))
+    P.assert_points(pp, rp)
+    P.assert_total(t, rt, rp)
+    P.assert_grad(g, rg)
+    # the value-only instance takes the same paths
+    _, _, xd, yd = P.f32_pair(x, y)
+    tot, pp2 = cde().Model(xd, yd).loo_list([[hx, hy]], crit, per_point=True)
+    torch.cuda.synchronize()
+    P.assert_points(pp2.cpu().numpy()[0], rp)
+
+
 def test_deterministic_bits():
     say("case: determinism")
     x, y = workloads.photoz(3000, seed=6)
