@@ -21,9 +21,12 @@
 // such tail values are far below the accuracy floor of a density estimate.
 //
 // Work decomposition: a 256-lane block owns 64 queries (16 per wave), a chunk
-// of up to 128 grid points (blockIdx.y) and a range of training points
+// of up to 128 grid points (blockIdx.y) and a chunk of training points
 // (blockIdx.z); chunk partial sums (FP64) are combined in a fixed order by
-// k_query_reduce, so results do not depend on the chunking's timing.
+// k_query_reduce.  The training-point chunks depend on n alone and every
+// query row is accumulated on its own, so a query's result does not depend
+// on which other queries share its launch; large batches run in slices of
+// queries that bound the partial storage.
 #include <type_traits>
 
 #include "cde_device.h"
@@ -263,13 +266,27 @@ __global__ void k_query_reduce(const double* __restrict__ fpart, const double* _
     f[e] = num > 0.0 ? exp(log_cy - mu[g] * LN2 + log(num / den)) : 0.0;
 }
 
+// Training-point chunks: whole tiles, at most 256 chunks, a function of n
+// only (never of the batch).
+static int64_t query_chunk_points(int64_t n)
+{
+    const int64_t ntiles = (n + TILE - 1) / TILE;
+    return (ntiles + 255) / 256 * TILE;
+}
+
+// Queries per slice: chunk partials of one slice within 2^26 doubles.
+static int64_t query_slice(int64_t nch, int64_t q, int64_t k)
+{
+    int64_t s = ((int64_t(1) << 26) / (nch * (k + 1))) / 64 * 64;
+    return std::min(q, std::max<int64_t>(64, s));
+}
+
 size_t query_work_doubles(const cde_model* m, int64_t q, int64_t k)
 {
-    const int64_t qb = (q + 63) / 64, gb = (k + 127) / 128;
-    const int64_t max_chunks = (m->n + TILE - 1) / TILE;
-    int64_t c = std::max<int64_t>(1, 1024 / std::max<int64_t>(1, qb * gb));
-    c = std::min(c, max_chunks);
-    return (size_t)(q + k + c * q * (k + 1) + 64);
+    const int64_t chunk = query_chunk_points(m->n);
+    const int64_t nch = (m->n + chunk - 1) / chunk;
+    const int64_t qs = query_slice(nch, q, k);
+    return (size_t)(q + k + nch * qs * (k + 1) + 64);
 }
 
 template <int DX, int DY>
@@ -286,17 +303,14 @@ static hipError_t query_t(const cde_model* m, const float* xq, int q, const floa
     qa.log_cy = lcy;
     const int n = (int)m->n;
     const float* pts = (const float*)m->pts;
-    const int qb = (q + 63) / 64, gb = (k + 127) / 128;
-    const int ntiles = (n + TILE - 1) / TILE;
-    // training-point chunks: enough blocks to fill the device, whole tiles each
-    int nch = std::max(1, 1024 / std::max(1, qb * gb));
-    nch = std::min(nch, ntiles);
-    const int chunk = (ntiles + nch - 1) / nch * TILE;
-    nch = (n + chunk - 1) / chunk;
+    const int gb = (k + 127) / 128;
+    const int chunk = (int)query_chunk_points(n);
+    const int nch = (n + chunk - 1) / chunk;
+    const int qs = (int)query_slice(nch, q, k);
     double* mq = work;
     double* mu = work + q;
     double* dpart = mu + k;
-    double* fpart = dpart + (size_t)nch * q;
+    double* fpart = dpart + (size_t)nch * qs;
     // shifts: exact minima over point chunks
     const int sch = 16 * TILE;
     const int nsch = (n + sch - 1) / sch;
@@ -308,13 +322,20 @@ static hipError_t query_t(const cde_model* m, const float* xq, int q, const floa
     hipLaunchKernelGGL((k_qshift_y<DX, DY>), dim3((k + TILE - 1) / TILE, nsch), dim3(TILE), 0, stream,
                        pts, n, sch, yg, k, qa, mu);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_query_mfma<DX, DY>), dim3(qb, gb, nch), dim3(TILE), 0, stream, pts, n, chunk,
-                       xq, q, yg, k, qa, (const double*)mq, (const double*)mu, fpart, dpart);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t total = (int64_t)q * k;
-    hipLaunchKernelGGL(k_query_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
-                       (const double*)fpart, (const double*)dpart, (const double*)mu, q, k, nch, lcy, f);
-    return hipGetLastError();
+    for (int q0 = 0; q0 < q; q0 += qs) {
+        const int qn = std::min(qs, q - q0);
+        const int qb = (qn + 63) / 64;
+        hipLaunchKernelGGL((k_query_mfma<DX, DY>), dim3(qb, gb, nch), dim3(TILE), 0, stream, pts, n,
+                           chunk, xq + (size_t)q0 * DX, qn, yg, k, qa, (const double*)(mq + q0),
+                           (const double*)mu, fpart, dpart);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int64_t total = (int64_t)qn * k;
+        hipLaunchKernelGGL(k_query_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
+                           (const double*)fpart, (const double*)dpart, (const double*)mu, qn, k, nch,
+                           lcy, f + (size_t)q0 * k);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 #define CDE_QM_CASE(DX_, DY_) \

@@ -265,6 +265,30 @@ def test_query_all_shapes(dx, dy):
     assert np.all(err <= 1e-5 * ref + 1e-7 * peak), float(np.max(err / (1e-5 * ref + 1e-7 * peak)))
 
 
+def test_query_rows_independent_of_batch():
+    # A query's value must not depend on the other queries of its launch: the
+    # serving path fuses queries.  n = 70,000 gives 137 training-point chunks
+    # and 3,000 queries on a 256-point grid run in two slices.
+    say("case: query rows alone vs in a batch of 3000")
+    x, y = workloads.gmm(70_000, seed=13, dx=2)
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    h = [0.3, 0.35, 0.2]
+    rng = np.random.default_rng(5)
+    xq = (xo[rng.choice(70_000, 3000)] + 0.05 * rng.normal(size=(3000, 2))).astype(np.float32)
+    yg = np.linspace(yo.min() - 1, yo.max() + 1, 256).astype(np.float32)
+    xq_d, yg_d = P.to_dev(xq, torch.float32), P.to_dev(yg, torch.float32)
+    full = m.query(xq_d, yg_d, h).cpu().numpy()
+    for rows in ([0], [1500], [2999], [7, 2000, 2998]):
+        part = m.query(xq_d[rows].contiguous(), yg_d, h).cpu().numpy()
+        assert np.array_equal(part, full[rows]), rows
+    ref = oracle.density(xo, yo, h, xq[[0, 2999]].astype(np.float64), yg.astype(np.float64),
+                         nthreads=NT)
+    peak = ref.max(axis=1, keepdims=True)
+    err = np.abs(full[[0, 2999]] - ref)
+    assert np.all(err <= 1e-5 * ref + 1e-7 * peak)
+
+
 def test_query_fp64_model():
     say("case: query fp64 model")
     x, y = workloads.tiny(500, seed=4)
