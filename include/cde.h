@@ -94,6 +94,16 @@ cde_status cde_destroy(cde_model* m);
 /* Device bytes held by the model (packed data, per-point shifts, scratch). */
 size_t cde_model_device_bytes(const cde_model* m);
 
+/* Device bytes a model of this shape holds after cde_create and one
+ * cde_loo_loglik call over an n_hx x n_hy grid with the default cross term
+ * (n_hx = n_hy = 0: after cde_create alone), i.e. what cde_model_device_bytes
+ * then reports: the budget a caller (such as an admission controller) needs
+ * for such a bandwidth-selection job (Section 3 criterion over a grid).
+ * Host-only arithmetic; it reads the current device's compute-unit count.
+ * Returns 0 for shapes or grid sizes cde_create or cde_loo_loglik reject.  */
+size_t cde_workspace_bytes(int64_t n, int32_t dx, int32_t dy, cde_precision precision,
+                           int32_t n_hx, int32_t n_hy);
+
 /* Exact LOO log-likelihood over a grid of scalar bandwidths (one hx for all
  * x-dimensions, one hy for all y-dimensions), Section 3 eq. (3).
  *   hx[n_hx], hy[n_hy]: host arrays, every value finite and > 0.

@@ -28,6 +28,7 @@ SIGNATURES = {
     "cde_create": (ctypes.c_int, [ctypes.POINTER(_vp), _vp, _vp, _i64, _i32, _i32, ctypes.c_int, _vp]),
     "cde_destroy": (ctypes.c_int, [_vp]),
     "cde_model_device_bytes": (ctypes.c_size_t, [_vp]),
+    "cde_workspace_bytes": (ctypes.c_size_t, [_i64, _i32, _i32, ctypes.c_int, _i32, _i32]),
     "cde_loo_loglik": (ctypes.c_int, [_vp, _dp, _i32, _dp, _i32, ctypes.c_int, ctypes.c_int, _vp, _vp,
                                       _vp, _vp]),
     "cde_loo_loglik_list": (ctypes.c_int, [_vp, _dp, _i32, ctypes.c_int, _vp, _vp, _vp]),
@@ -75,3 +76,11 @@ def check(status: int, where: str) -> None:
 def doubles(values) -> ctypes.Array:
     vals = [float(v) for v in values]
     return (ctypes.c_double * max(1, len(vals)))(*vals)
+
+
+def workspace_bytes(n: int, dx: int, dy: int, precision: int = CDE_F32, n_hx: int = 0,
+                    n_hy: int = 0) -> int:
+    """Device bytes of a model of this shape after one n_hx x n_hy grid call
+    (``cde_workspace_bytes``); 0 for shapes the library rejects."""
+    return int(load().cde_workspace_bytes(int(n), int(dx), int(dy), int(precision), int(n_hx),
+                                          int(n_hy)))

@@ -75,6 +75,8 @@ struct DeviceGuard {
     }
 };
 
+size_t round_scratch(size_t bytes) { return (bytes + 4095) & ~size_t(4095); }
+
 cde_status ensure_scratch(cde_model* m, size_t bytes)
 {
     if (m->scratch_bytes >= bytes) return CDE_OK;
@@ -85,7 +87,7 @@ cde_status ensure_scratch(cde_model* m, size_t bytes)
         m->scratch_bytes = 0;
         if (e != hipSuccess) return hip_fail(e, "hipFree(scratch)");
     }
-    bytes = (bytes + 4095) & ~size_t(4095);
+    bytes = round_scratch(bytes);
     hipError_t e = hipMalloc(&m->scratch, bytes);
     if (e != hipSuccess) {
         m->scratch = nullptr;
@@ -99,6 +101,26 @@ cde_status ensure_scratch(cde_model* m, size_t bytes)
 // Value (and gradient) for a list of diagonal settings, reduced into
 // totals[g] (and grad[g][dx+dy]); per-setting non-finite counts are summed
 // into *nonfinite when given.
+// Scratch of a list/gradient call over g settings: block rows and counts,
+// then the chunk partials of one launch.
+template <typename T>
+size_t diag_list_scratch(const cde_model* m, int g, bool grad, int* chunks_out)
+{
+    const int nblocks = (int)(m->npad / TILE);
+    const int nv = grad ? m->dx + m->dy + 2 : 2;
+    const int per_launch = std::min(g, MAX_SETS_PER_LAUNCH);
+    const int chunks = diag_chunks<T>(m, per_launch, grad, MAX_DIAG_PARTIAL_DOUBLES);
+    if (chunks_out) *chunks_out = chunks;
+    const size_t part_doubles = (size_t)g * nblocks * nv + (size_t)g;  // rows, then counts
+    return sizeof(double) * (part_doubles + diag_partial_doubles(m, per_launch, grad, chunks)) + 256;
+}
+
+// Scratch of an FP32 grid call (grid workspace, then per-setting counts).
+size_t grid_call_scratch(const cde_model* m, int n_hx, int n_hy)
+{
+    return grid_work_bytes(m, n_hx, n_hy) + sizeof(double) * (size_t)n_hx * n_hy + 256;
+}
+
 template <typename T>
 cde_status run_diag_list(cde_model* m, const double* h, int g, int crit, bool grad, double* totals,
                          double* grad_out, double* per_point, int64_t* nonfinite,
@@ -107,11 +129,11 @@ cde_status run_diag_list(cde_model* m, const double* h, int g, int crit, bool gr
     const int p = m->dx + m->dy;
     const int nblocks = (int)(m->npad / TILE);
     const int nv = grad ? p + 2 : 2;
+    int chunks = 1;
+    const size_t scratch = diag_list_scratch<T>(m, g, grad, &chunks);
     const int per_launch = std::min(g, MAX_SETS_PER_LAUNCH);
-    const int chunks = diag_chunks<T>(m, per_launch, grad, MAX_DIAG_PARTIAL_DOUBLES);
-    const size_t part_doubles = (size_t)g * nblocks * nv + (size_t)g;  // rows, then counts
-    const size_t partial_doubles = diag_partial_doubles(m, per_launch, grad, chunks);
-    cde_status st = ensure_scratch(m, sizeof(double) * (part_doubles + partial_doubles) + 256);
+    const size_t part_doubles = (size_t)g * nblocks * nv + (size_t)g;
+    cde_status st = ensure_scratch(m, scratch);
     if (st != CDE_OK) return st;
     double* part = (double*)m->scratch;
     double* partial = part + part_doubles;
@@ -202,6 +224,35 @@ cde_status cde_destroy(cde_model* m)
 
 size_t cde_model_device_bytes(const cde_model* m) { return m ? m->bytes : 0; }
 
+size_t cde_workspace_bytes(int64_t n, int32_t dx, int32_t dy, cde_precision precision, int32_t n_hx,
+                           int32_t n_hy)
+{
+    try {
+        if (n < 2 || n >= (int64_t(1) << 31) - TILE || !supported_dims(dx, dy)) return 0;
+        if (precision != CDE_F32 && precision != CDE_F64) return 0;
+        if (n_hx < 0 || n_hy < 0 || n_hx > 64 || n_hy > 64 || (n_hx == 0) != (n_hy == 0)) return 0;
+        cde_model t;  // shape only: no device memory
+        t.n = n;
+        t.npad = (n + TILE - 1) / TILE * TILE;
+        t.dx = dx;
+        t.dy = dy;
+        t.stride = row_stride(dx, dy);
+        t.prec = precision;
+        if (hipGetDevice(&t.device) != hipSuccess ||
+            hipDeviceGetAttribute(&t.ncu, hipDeviceAttributeMultiprocessorCount, t.device) != hipSuccess)
+            t.ncu = 0;
+        const size_t elt = precision == CDE_F64 ? sizeof(double) : sizeof(float);
+        size_t bytes = (size_t)t.npad * t.stride * elt;
+        if (n_hx == 0) return bytes;
+        if (precision == CDE_F64)
+            return bytes + round_scratch(diag_list_scratch<double>(&t, n_hx * n_hy, false, nullptr));
+        return bytes + sizeof(double) * 2 * (size_t)t.npad +
+               round_scratch(grid_call_scratch(&t, n_hx, n_hy));
+    } catch (...) {
+        return 0;
+    }
+}
+
 cde_status cde_loo_loglik_list(cde_model* m, const double* h, int32_t g, cde_criterion criterion,
                                double* totals_dev, double* per_point_dev, void* stream)
 {
@@ -275,7 +326,7 @@ cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const do
             m->bytes += 16 * sizeof(float);
         }
         const size_t wb = grid_work_bytes(m, n_hx, n_hy);
-        cde_status st = ensure_scratch(m, wb + sizeof(double) * (size_t)g + 256);
+        cde_status st = ensure_scratch(m, grid_call_scratch(m, n_hx, n_hy));
         if (st != CDE_OK) return st;
         double* counts = (double*)((char*)m->scratch + wb);
         hipError_t e = launch_grid(m, hx, n_hx, hy, n_hy, criterion, xt, totals_dev, per_point_dev,

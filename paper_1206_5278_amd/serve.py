@@ -253,10 +253,12 @@ class GpuExecutor(Executor):
     def __init__(self, sets, n_streams: int = 4, grid_points: int = 256):
         import torch
 
+        from . import _binding
         from .drivers import normal_reference_bandwidths
         from .model import Model
         self.torch = torch
         self.Model = Model
+        self.B = _binding
         self.dev = torch.device("cuda:0")
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_streams)]
         self.rr = 0
@@ -287,10 +289,8 @@ class GpuExecutor(Executor):
             k = self.sets[r.set_id]["k"]
             return int(r.xq.shape[0]) * (k * 8 + 64) + 4096
         n, dx = r.x.shape
-        npad = (n + 255) // 256 * 256
-        g = len(r.hx) * len(r.hy)
-        stride = (dx + 1 + 3) // 4 * 4
-        return npad * (stride * 4 + 16 + 8 * (2 * g + len(r.hx)) + g) + (1 << 20)
+        dy = r.y.shape[1] if r.y.ndim > 1 else 1
+        return self.B.workspace_bytes(n, dx, dy, self.B.CDE_F32, len(r.hx), len(r.hy)) + (1 << 20)
 
     def launch_queries(self, set_id, reqs):
         torch = self.torch

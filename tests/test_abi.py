@@ -73,3 +73,20 @@ def test_product_path_does_not_reference_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "cde_oracle" not in text and "oracle_loo" not in text, f
+
+
+def test_workspace_bytes_host_arithmetic(lib):
+    from paper_1206_5278_amd import _binding as B
+    # after cde_create alone: the packed [npad][stride] rows (stride = dx + dy rounded up to 4)
+    assert B.workspace_bytes(1000, 5, 1, B.CDE_F32) == 1024 * 8 * 4
+    assert B.workspace_bytes(1000, 5, 1, B.CDE_F64) == 1024 * 8 * 8
+    assert B.workspace_bytes(256, 16, 2, B.CDE_F32) == 256 * 20 * 4
+    # a grid call adds shifts and scratch, growing with the grid
+    base = B.workspace_bytes(5000, 3, 1, B.CDE_F32)
+    g8 = B.workspace_bytes(5000, 3, 1, B.CDE_F32, 8, 8)
+    g16 = B.workspace_bytes(5000, 3, 1, B.CDE_F32, 16, 16)
+    assert base < g8 < g16
+    # rejected shapes and grid sizes give 0
+    for args in [(1, 1, 1, 0), (100, 0, 1, 0), (100, 9, 1, 0), (100, 1, 3, 0), (100, 1, 1, 7),
+                 (100, 1, 1, 0, 65, 1), (100, 1, 1, 0, 4, 0), (100, 1, 1, 0, -1, -1)]:
+        assert B.workspace_bytes(*args) == 0, args

@@ -289,6 +289,21 @@ def test_query_rows_independent_of_batch():
     assert np.all(err <= 1e-5 * ref + 1e-7 * peak)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_workspace_bytes_matches_model(dtype):
+    # cde_workspace_bytes predicts what a model holds after one grid call
+    say(f"case: workspace bytes {dtype}")
+    from paper_1206_5278_amd import _binding as B
+    x, y = workloads.gmm(3000, seed=21, dx=3)
+    m = cde().Model(P.to_dev(x, dtype), P.to_dev(y, dtype))
+    prec = B.CDE_F32 if dtype == torch.float32 else B.CDE_F64
+    assert m._lib.cde_model_device_bytes(m._h) == B.workspace_bytes(3000, 3, 1, prec)
+    hs = list(workloads.geomspace(0.1, 3.0, 16))
+    m.loo_grid(hs, hs)
+    torch.cuda.synchronize()
+    assert m._lib.cde_model_device_bytes(m._h) == B.workspace_bytes(3000, 3, 1, prec, 16, 16)
+
+
 def test_query_fp64_model():
     say("case: query fp64 model")
     x, y = workloads.tiny(500, seed=4)
