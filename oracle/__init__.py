@@ -9,7 +9,9 @@ imports the product library.
 The arithmetic lives in ``cde_oracle.c`` (plain C, double precision, no
 blocking or factorisation); this module only marshals numpy arrays.
 Definitions followed (Holmes, Gray & Isbell): Section 2 (scaled kernel,
-eq. 1), Section 3 eq. (3) and the A_i expansion of Section 3.2.
+eq. 1), Section 3 eq. (3) and the A_i expansion of Section 3.2; the Gaussian
+kernel, and the Epanechnikov kernel of Section 5 (``loo_epan``,
+``density_epan``).
 """
 from __future__ import annotations
 
@@ -58,6 +60,12 @@ def load_library(path: str):
     lib.oracle_density.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, dp,
                                    dp, ctypes.c_long, dp, ctypes.c_long, dp, ctypes.c_int]
     lib.oracle_density.restype = ctypes.c_int
+    lib.oracle_loo_epan.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, dp,
+                                    ctypes.c_int, lp, ctypes.c_long, dp, ctypes.c_int]
+    lib.oracle_loo_epan.restype = ctypes.c_int
+    lib.oracle_density_epan.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, dp,
+                                        dp, ctypes.c_long, dp, ctypes.c_long, dp]
+    lib.oracle_density_epan.restype = ctypes.c_int
     return lib
 
 
@@ -167,4 +175,40 @@ def density(x, y, h, xq, yg, nthreads=1, lib=None):
                            _ptr(f), int(nthreads))
     if s:
         raise ValueError(f"oracle_density failed with status {s}")
+    return f
+
+
+def loo_epan(x, y, h, criterion="cond", idx=None, nthreads=1, lib=None):
+    """Per-point LOO log-likelihood with the Epanechnikov kernel (values only);
+    arguments as ``loo``.  Points with no j inside both windows get -inf."""
+    lib = _load(lib)
+    x, y = _f64(x), _f64(y)
+    n, dx = x.shape
+    dy = y.shape[1]
+    h = _bw(h, dx, dy)
+    idx_a, m = _idx(idx, n)
+    ell = np.empty(m)
+    s = lib.oracle_loo_epan(_ptr(x), _ptr(y), n, dx, dy, _ptr(h), _CRIT[criterion],
+                            None if idx_a is None else _ptr(idx_a, ctypes.c_long), m,
+                            _ptr(ell), int(nthreads))
+    if s:
+        raise ValueError(f"oracle_loo_epan failed with status {s}")
+    return ell
+
+
+def density_epan(x, y, h, xq, yg, lib=None):
+    """f(yg[g] | xq[q]) with the Epanechnikov kernel (eq. 1): returns [q, k]."""
+    lib = _load(lib)
+    x, y = _f64(x), _f64(y)
+    n, dx = x.shape
+    dy = y.shape[1]
+    h = _bw(h, dx, dy)
+    xq = _f64(xq).reshape(-1, dx)
+    yg = _f64(yg).reshape(-1, dy)
+    q, k = xq.shape[0], yg.shape[0]
+    f = np.empty((q, k))
+    s = lib.oracle_density_epan(_ptr(x), _ptr(y), n, dx, dy, _ptr(h), _ptr(xq), q, _ptr(yg), k,
+                                _ptr(f))
+    if s:
+        raise ValueError(f"oracle_density_epan failed with status {s}")
     return f

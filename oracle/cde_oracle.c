@@ -41,6 +41,20 @@
  * where Mw_k = sum_j exp(a_j-Mx) dx_k^2, Mv_k = sum_j exp(a_j+b_j-Mxy) dx_k^2
  * and Mvy_l = sum_j exp(a_j+b_j-Mxy) dy_l^2.
  *
+ * Epanechnikov kernel (the kernel of the paper's experiments, Section 5),
+ * radial over the bandwidth-scaled coordinates as in Section 2's K_h of a
+ * norm: K_h(t) = c_d / prod_k h_k * max(0, 1 - sum_k (t_k/h_k)^2) with the
+ * multivariate normalisation c_d = (d+2) / (2 V_d), V_d = pi^{d/2} /
+ * Gamma(d/2 + 1) the volume of the unit d-ball (Silverman's multivariate
+ * Epanechnikov kernel; c_1 = 3/4, c_2 = 2/pi).  With wx_j = max(0, 1 -
+ * sum_k (dx_k/hx_k)^2) and wy_j likewise, D = sum_{j!=i} wx_j and U =
+ * sum_{j!=i} wx_j wy_j in j order, and
+ *   CONDITIONAL: l_i = log c_y + log U - log D
+ *   JOINT      : l_i = log c_x + log c_y + log U - log(n-1)
+ * with log c_x = log c_dx - sum_k log hx_k.  U = 0 (no j inside both
+ * windows; the divergence of L at tiny bandwidths noted in Section 5) gives
+ * l_i = -inf.
+ *
  * Threads: points i are split into contiguous ranges, one per thread; each
  * l_i is computed by exactly the same code whatever the split, so results are
  * bitwise independent of the thread count.  Totals are formed by the caller
@@ -53,8 +67,11 @@
 
 #define ORACLE_COND 0
 #define ORACLE_JOINT 1
+#define ORACLE_GAUSSIAN 0
+#define ORACLE_EPANECHNIKOV 1
 
 static const double HALF_LOG_2PI = 0.91893853320467274178032973640562;
+static const double PI = 3.14159265358979323846264338327950288;
 
 typedef struct {
     const double* x;     /* [n][dx] */
@@ -63,6 +80,7 @@ typedef struct {
     int dx, dy;
     const double* h;     /* [dx+dy]: hx..., hy... */
     int criterion;
+    int kernel;          /* ORACLE_GAUSSIAN or ORACLE_EPANECHNIKOV */
     const long* idx;     /* points to evaluate, or NULL for 0..m-1 */
     long m;
     double* ell;         /* [m] */
@@ -156,6 +174,54 @@ static int loo_point(const loo_job* J, long i, double* a, double* ab,
     return 0;
 }
 
+/* log of the multivariate Epanechnikov kernel's normalisation for
+ * bandwidths h[0..d): log((d+2) / (2 V_d)) - sum_k log h_k. */
+static double log_norm_epan(const double* h, int d)
+{
+    const double log_vd = 0.5 * d * log(PI) - lgamma(0.5 * d + 1.0);
+    double s = log((d + 2.0) / 2.0) - log_vd;
+    for (int k = 0; k < d; ++k) s -= log(h[k]);
+    return s;
+}
+
+/* One point i with the Epanechnikov kernel: fills *ell. */
+static int loo_point_epan(const loo_job* J, long i, double* ell)
+{
+    const long n = J->n;
+    const int dx = J->dx, dy = J->dy;
+    const double* hx = J->h;
+    const double* hy = J->h + dx;
+    const double* xi = J->x + (size_t)i * dx;
+    const double* yi = J->y + (size_t)i * dy;
+    double D = 0.0, U = 0.0;
+    for (long j = 0; j < n; ++j) {
+        if (j == i) continue;           /* leave point i out (eq. 3) */
+        const double* xj = J->x + (size_t)j * dx;
+        const double* yj = J->y + (size_t)j * dy;
+        double sx = 0.0, sy = 0.0;
+        for (int k = 0; k < dx; ++k) {
+            double t = (xi[k] - xj[k]) / hx[k];
+            sx += t * t;
+        }
+        for (int l = 0; l < dy; ++l) {
+            double t = (yi[l] - yj[l]) / hy[l];
+            sy += t * t;
+        }
+        const double wx = sx < 1.0 ? 1.0 - sx : 0.0;
+        const double wy = sy < 1.0 ? 1.0 - sy : 0.0;
+        D += wx;
+        U += wx * wy;
+    }
+    const double lcy = log_norm_epan(hy, dy);
+    if (!(U > 0.0))
+        *ell = -INFINITY;
+    else if (J->criterion == ORACLE_JOINT)
+        *ell = log_norm_epan(hx, dx) + lcy + log(U) - log((double)(n - 1));
+    else
+        *ell = lcy + log(U) - log(D);
+    return 0;
+}
+
 static void* loo_worker(void* arg)
 {
     loo_job* J = (loo_job*)arg;
@@ -170,7 +236,10 @@ static void* loo_worker(void* arg)
     const int p = J->dx + J->dy;
     for (long t = J->lo; t < J->hi; ++t) {
         long i = J->idx ? J->idx[t] : t;
-        loo_point(J, i, a, ab, &J->ell[t], J->dell ? J->dell + (size_t)t * p : NULL);
+        if (J->kernel == ORACLE_EPANECHNIKOV)
+            loo_point_epan(J, i, &J->ell[t]);
+        else
+            loo_point(J, i, a, ab, &J->ell[t], J->dell ? J->dell + (size_t)t * p : NULL);
     }
     free(a);
     free(ab);
@@ -240,6 +309,25 @@ int oracle_loo(const double* x, const double* y, long n, int dx, int dy,
     return run_jobs(&J, m, nthreads);
 }
 
+/* Per-point LOO log-likelihood with the Epanechnikov kernel for one diagonal
+ * bandwidth setting h[dx+dy] (values only); arguments as oracle_loo. */
+int oracle_loo_epan(const double* x, const double* y, long n, int dx, int dy,
+                    const double* h, int criterion, const long* idx, long m,
+                    double* ell, int nthreads)
+{
+    if (check_args(x, y, n, dx, dy, h) || !ell || m < 0) return 1;
+    if (!idx && m != n) return 1;
+    if (idx)
+        for (long t = 0; t < m; ++t)
+            if (idx[t] < 0 || idx[t] >= n) return 1;
+    loo_job J;
+    memset(&J, 0, sizeof J);
+    J.x = x; J.y = y; J.n = n; J.dx = dx; J.dy = dy; J.h = h;
+    J.criterion = criterion; J.kernel = ORACLE_EPANECHNIKOV;
+    J.idx = idx; J.m = m; J.ell = ell; J.dell = NULL;
+    return run_jobs(&J, m, nthreads);
+}
+
 /* Scalar bandwidth grid, evaluated directly setting by setting: for every
  * (a, b) the exponent of each pair is formed from hx[a] and hy[b] and
  * exponentiated as a whole (no factorisation of the two kernels).  Output is
@@ -263,9 +351,13 @@ int oracle_loo_grid(const double* x, const double* y, long n, int dx, int dy,
     return 0;
 }
 
-/* Sum in index order with Neumaier's compensation. */
+/* Sum in index order with Neumaier's compensation.  A non-finite entry
+ * makes the plain sum the answer (-inf for a diverged point, NaN for NaN). */
 double oracle_sum(const double* v, long m)
 {
+    double p = 0.0;
+    for (long t = 0; t < m; ++t) p += v[t];
+    if (!isfinite(p)) return p;
     double s = 0.0, c = 0.0;
     for (long t = 0; t < m; ++t) {
         double u = s + v[t];
@@ -370,4 +462,39 @@ int oracle_density(const double* x, const double* y, long n, int dx, int dy,
     free(jobs);
     free(th);
     return status;
+}
+
+/* Density queries with the Epanechnikov kernel, eq. (1) over all n training
+ * points: f[qq][g] = c_y sum_i wx wy / sum_i wx (0 where no training x lies
+ * inside the x window, i.e. where eq. (1) is 0/0). */
+int oracle_density_epan(const double* x, const double* y, long n, int dx, int dy,
+                        const double* h, const double* xq, long q, const double* yg,
+                        long k, double* f)
+{
+    if (check_args(x, y, n, dx, dy, h) || !xq || !yg || !f || q < 0 || k < 0) return 1;
+    const double* hx = h;
+    const double* hy = h + dx;
+    const double cy = exp(log_norm_epan(hy, dy));
+    for (long qq = 0; qq < q; ++qq) {
+        for (long g = 0; g < k; ++g) {
+            double D = 0.0, U = 0.0;
+            for (long i = 0; i < n; ++i) {
+                double sx = 0.0, sy = 0.0;
+                for (int kk = 0; kk < dx; ++kk) {
+                    double t = (xq[(size_t)qq * dx + kk] - x[(size_t)i * dx + kk]) / hx[kk];
+                    sx += t * t;
+                }
+                for (int l = 0; l < dy; ++l) {
+                    double t = (yg[(size_t)g * dy + l] - y[(size_t)i * dy + l]) / hy[l];
+                    sy += t * t;
+                }
+                const double wx = sx < 1.0 ? 1.0 - sx : 0.0;
+                const double wy = sy < 1.0 ? 1.0 - sy : 0.0;
+                D += wx;
+                U += wx * wy;
+            }
+            f[(size_t)qq * k + g] = D > 0.0 ? cy * U / D : 0.0;
+        }
+    }
+    return 0;
 }

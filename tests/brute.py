@@ -1,7 +1,8 @@
 """Independent 50-digit brute force of the LOO likelihood (test helper).
 
 Written from the definitions only (scaled Gaussian kernel, Section 2;
-eq. (1); eq. (3) with the A_i expansion of Section 3.2): every kernel value is
+eq. (1); eq. (3) with the A_i expansion of Section 3.2; the Epanechnikov
+kernel of Section 5 in its multivariate radial form): every kernel value is
 formed in full, constants included, with Python's ``decimal`` arithmetic and
 its own exp/ln, and summed directly -- no log-sum-exp, no shifts.  It shares
 nothing with the C oracle and is used only on tiny inputs.
@@ -66,3 +67,55 @@ def density(x, y, hx, hy, xq, yq):
         num += kx * gauss_kernel([a - b for a, b in zip(YQ, Y[i])], HY)
         den += kx
     return num / den
+
+
+def unit_ball_volume(d):
+    """Volume of the unit d-ball by the recurrence V_d = (2 pi / d) V_{d-2},
+    V_0 = 1, V_1 = 2."""
+    v = [Decimal(1), Decimal(2)]
+    for k in range(2, d + 1):
+        v.append(2 * PI / k * v[k - 2])
+    return v[d]
+
+
+def epan_kernel(delta, h):
+    """Radial Epanechnikov K_h(delta) = (d+2)/(2 V_d) / prod_k h_k *
+    max(0, 1 - sum_k (d_k/h_k)^2)."""
+    d = len(delta)
+    u = Decimal(0)
+    scale = Decimal(1)
+    for dk, hk in zip(delta, h):
+        t = dk / hk
+        u += t * t
+        scale *= hk
+    if u >= 1:
+        return Decimal(0)
+    return (Decimal(d + 2) / (2 * unit_ball_volume(d))) / scale * (1 - u)
+
+
+def ell_epan(x, y, hx, hy, criterion="cond"):
+    """Per-point LOO log-likelihood with the Epanechnikov kernel, as floats
+    (-inf where no j has a non-zero product kernel)."""
+    n = len(x)
+    X = [[_d(v) for v in row] for row in x]
+    Y = [[_d(v) for v in row] for row in y]
+    HX = [_d(v) for v in hx]
+    HY = [_d(v) for v in hy]
+    out = []
+    for i in range(n):
+        num = Decimal(0)
+        den = Decimal(0)
+        for j in range(n):
+            if j == i:
+                continue
+            kx = epan_kernel([a - b for a, b in zip(X[i], X[j])], HX)
+            ky = epan_kernel([a - b for a, b in zip(Y[i], Y[j])], HY)
+            num += kx * ky
+            den += kx
+        if num == 0:
+            out.append(float("-inf"))
+        elif criterion == "cond":
+            out.append(float((num / den).ln()))
+        else:
+            out.append(float((num / (n - 1)).ln()))
+    return out

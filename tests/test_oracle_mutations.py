@@ -35,6 +35,48 @@ MUTATIONS = {
 }
 
 
+# Mistakes planted in the Epanechnikov kernel's code.
+EPAN_MUTATIONS = {
+    "epan_norm_missing_half": ("double s = log((d + 2.0) / 2.0) - log_vd;",
+                               "double s = log(d + 2.0) - log_vd;"),
+    "epan_ball_volume_exponent": ("0.5 * d * log(PI) - lgamma(0.5 * d + 1.0)",
+                                  "d * log(PI) - lgamma(0.5 * d + 1.0)"),
+    "epan_y_window_uses_x": ("        const double wy = sy < 1.0 ? 1.0 - sy : 0.0;\n        D += wx;\n        U += wx * wy;\n    }\n    const double lcy",
+                             "        const double wy = sy < 1.0 ? 1.0 - sx : 0.0;\n        D += wx;\n        U += wx * wy;\n    }\n    const double lcy"),
+    "epan_den_weighted_by_y": ("        D += wx;\n        U += wx * wy;\n    }\n    const double lcy",
+                               "        D += wx * wy;\n        U += wx * wy;\n    }\n    const double lcy"),
+    "epan_window_not_squared": ("            double t = (xi[k] - xj[k]) / hx[k];\n            sx += t * t;\n        }\n        for (int l = 0; l < dy; ++l) {\n            double t = (yi[l] - yj[l]) / hy[l];\n            sy += t * t;\n        }\n        const double wx",
+                                "            double t = (xi[k] - xj[k]) / hx[k];\n            sx += fabs(t);\n        }\n        for (int l = 0; l < dy; ++l) {\n            double t = (yi[l] - yj[l]) / hy[l];\n            sy += t * t;\n        }\n        const double wx"),
+    "epan_joint_missing_cx": ("*ell = log_norm_epan(hx, dx) + lcy + log(U) - log((double)(n - 1));",
+                              "*ell = lcy + log(U) - log((double)(n - 1));"),
+    "epan_self_pair_included": ("    double D = 0.0, U = 0.0;\n    for (long j = 0; j < n; ++j) {\n        if (j == i) continue;           /* leave point i out (eq. 3) */",
+                                "    double D = 0.0, U = 0.0;\n    for (long j = 0; j < n; ++j) {\n"),
+}
+
+
+def battery_epan(lib) -> list:
+    """Independent Epanechnikov checks; returns the names of those that fail."""
+    failed = []
+    rng = np.random.default_rng(8)
+    n, dx, dy = 9, 2, 1
+    x = rng.normal(0, 1, size=(n, dx))
+    y = rng.normal(0, 1, size=(n, dy))
+    hx, hy = np.array([1.8, 2.2]), np.array([1.6])
+    h = np.concatenate([hx, hy])
+    for crit in ("cond", "joint"):
+        got = oracle.loo_epan(x, y, h, crit, lib=lib)
+        ref = np.array(brute.ell_epan(x, y, hx, hy, crit))
+        if not (np.array_equal(np.isfinite(got), np.isfinite(ref)) and
+                np.allclose(got[np.isfinite(ref)], ref[np.isfinite(ref)], rtol=1e-12, atol=1e-12)):
+            failed.append(f"epan_brute_{crit}")
+    xq = rng.normal(0, 1, size=(1, dx))
+    yg = np.linspace(y.min() - 2.0, y.max() + 2.0, 20001)
+    f = oracle.density_epan(x, y, h, xq, yg, lib=lib)
+    if abs(np.trapezoid(f[0], yg) - 1.0) > 1e-6:
+        failed.append("epan_density_integral")
+    return failed
+
+
 def battery(lib) -> list:
     """Independent checks; returns the names of those that fail."""
     failed = []
@@ -95,3 +137,19 @@ def test_planted_mistake_is_caught(name, tmp_path):
     so = oracle.build(str(mutated), str(tmp_path / "libmut.so"))
     lib = oracle.load_library(so)
     assert battery(lib), f"mutation {name} was not detected by any pin"
+
+
+def test_unmutated_oracle_passes_epan_battery():
+    assert battery_epan(None) == []
+
+
+@pytest.mark.parametrize("name", sorted(EPAN_MUTATIONS))
+def test_planted_epan_mistake_is_caught(name, tmp_path):
+    old, new = EPAN_MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not unique: {old!r}"
+    mutated = tmp_path / "mut.c"
+    mutated.write_text(src.replace(old, new))
+    so = oracle.build(str(mutated), str(tmp_path / "libmut.so"))
+    lib = oracle.load_library(so)
+    assert battery_epan(lib), f"mutation {name} was not detected by any pin"
