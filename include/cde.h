@@ -5,8 +5,11 @@
  *
  * Method: Holmes, Gray & Isbell, "Fast Nonparametric Conditional Density
  * Estimation".
- *   - Kernel (Section 2): K_h(t) = h^{-d} K(t/h) with K the Gaussian, used
- *     here as a product over dimensions with one bandwidth per dimension.
+ *   - Kernel (Section 2): K_h(t) = h^{-d} K(t/h).  K is the Gaussian, used
+ *     as a product over dimensions with one bandwidth per dimension, or the
+ *     Epanechnikov kernel of the paper's experiments (Section 5), radial over
+ *     the bandwidth-scaled coordinates: c_d (1 - |t/h|^2)_+ / prod h with
+ *     c_d = (d+2) / (2 V_d), V_d the volume of the unit d-ball.
  *   - Estimator (Section 2, eq. 1): f(y|x) = sum_i K_hy(y-y_i) K_hx(x-x_i) /
  *     sum_i K_hx(x-x_i).  The paper calls the y-bandwidth h1 and the
  *     x-bandwidth h2; this header writes hx and hy.
@@ -41,9 +44,17 @@
 extern "C" {
 #endif
 
-#define CDE_ABI_VERSION 1
+#define CDE_ABI_VERSION 2
 
 typedef struct cde_model cde_model; /* opaque handle */
+
+typedef enum {
+    CDE_GAUSSIAN = 0,     /* product Gaussian, one bandwidth per dimension */
+    CDE_EPANECHNIKOV = 1  /* radial Epanechnikov over scaled coordinates (Section 5's
+                             kernel); exactly zero outside its window, so a point
+                             with no j inside both windows has l_i = -inf, the
+                             divergence at tiny bandwidths Section 5 notes */
+} cde_kernel;
 
 typedef enum {
     CDE_OK = 0,
@@ -95,7 +106,7 @@ cde_status cde_destroy(cde_model* m);
 size_t cde_model_device_bytes(const cde_model* m);
 
 /* Device bytes a model of this shape holds after cde_create and one
- * cde_loo_loglik call over an n_hx x n_hy grid with the default cross term
+ * cde_loo_loglik call over an n_hx x n_hy grid (Gaussian kernel, default cross term)
  * (n_hx = n_hy = 0: after cde_create alone), i.e. what cde_model_device_bytes
  * then reports: the budget a caller (such as an admission controller) needs
  * for such a bandwidth-selection job (Section 3 criterion over a grid).
@@ -111,24 +122,35 @@ size_t cde_workspace_bytes(int64_t n, int32_t dx, int32_t dy, cde_precision prec
  *   per_point_dev: optional [n_hx*n_hy][n] doubles (l_i per setting) or NULL.
  *   n_nonfinite_dev: optional [1] int64: number of non-finite l_i (0 for
  *   finite data; a non-finite l_i makes its total non-finite), or NULL.
- *   xterm: CDE_XTERM_MFMA_BF16X3 is accepted for dx >= 16 only.
+ *   kernel: CDE_GAUSSIAN or CDE_EPANECHNIKOV (the latter runs every setting
+ *   as a diagonal setting over the model's spatial order, built on first use;
+ *   per-point outputs stay in the caller's point order).
+ *   xterm: CDE_XTERM_MFMA_BF16X3 is accepted for dx >= 16, FP32 data and the
+ *   Gaussian kernel only.
  *   Limits: n_hx, n_hy in [1, 64]. */
 cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const double* hy,
-                          int32_t n_hy, cde_criterion criterion, cde_xterm xterm,
+                          int32_t n_hy, cde_criterion criterion, cde_kernel kernel,
+                          cde_xterm xterm,
                           double* totals_dev, double* per_point_dev,
                           int64_t* n_nonfinite_dev, void* stream);
 
 /* Exact LOO log-likelihood for a list of g diagonal bandwidth settings.
  *   h: host [g][dx+dy] (hx_1..hx_dx, hy_1..hy_dy per setting).
- *   totals_dev: [g] doubles; per_point_dev: optional [g][n] doubles or NULL.
+ *   kernel: CDE_GAUSSIAN, or CDE_EPANECHNIKOV (FP64 pair arithmetic over
+ *   the model's spatial order, built on first use: the Morton order of x,
+ *   with (point block, j tile) pairs whose x boxes lie a window apart
+ *   skipped, since every term there is exactly zero).
+ *   totals_dev: [g] doubles; per_point_dev: optional [g][n] doubles (in the
+ *   caller's point order) or NULL.
  *   Limits: 1 <= g <= 4096. */
 cde_status cde_loo_loglik_list(cde_model* m, const double* h, int32_t g,
-                               cde_criterion criterion, double* totals_dev,
-                               double* per_point_dev, void* stream);
+                               cde_criterion criterion, cde_kernel kernel,
+                               double* totals_dev, double* per_point_dev, void* stream);
 
 /* Value and bandwidth gradient for one diagonal setting (adjoint of eq. 3).
  *   h: host [dx+dy].  total_dev: [1] double S(h).  grad_dev: [dx+dy] doubles,
  *   dS/dh_k (with respect to the bandwidths themselves, not their logs).
+ *   Gaussian kernel.
  *   per_point_dev: optional [n] doubles (l_i) or NULL. */
 cde_status cde_loo_grad(cde_model* m, const double* h, cde_criterion criterion,
                         double* total_dev, double* grad_dev, double* per_point_dev,
@@ -138,7 +160,7 @@ cde_status cde_loo_grad(cde_model* m, const double* h, cde_criterion criterion,
  * left out): f_dev[qq][g] = f(ygrid[g] | xq[qq]).
  *   xq_dev: [q][dx], ygrid_dev: [k][dy], device memory of the model's
  *   precision type.  h: host [dx+dy].  f_dev: [q][k] doubles.
- *   Limits: q >= 0, 0 <= k <= 4096. */
+ *   Gaussian kernel.  Limits: q >= 0, 0 <= k <= 4096. */
 cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const void* ygrid_dev,
                              int64_t k, const double* h, double* f_dev, void* stream);
 

@@ -17,6 +17,8 @@ CDE_OK, CDE_EINVAL, CDE_ENOMEM, CDE_EDEVICE, CDE_EUNSUPPORTED = range(5)
 CDE_F32, CDE_F64 = 0, 1
 CDE_COND, CDE_JOINT = 0, 1
 CDE_XTERM_AUTO, CDE_XTERM_VALU, CDE_XTERM_MFMA_BF16X3 = 0, 1, 2
+CDE_GAUSSIAN, CDE_EPANECHNIKOV = 0, 1
+ABI_VERSION = 2
 
 # Every symbol the header declares, with (restype, argtypes).
 _vp = ctypes.c_void_p
@@ -29,9 +31,10 @@ SIGNATURES = {
     "cde_destroy": (ctypes.c_int, [_vp]),
     "cde_model_device_bytes": (ctypes.c_size_t, [_vp]),
     "cde_workspace_bytes": (ctypes.c_size_t, [_i64, _i32, _i32, ctypes.c_int, _i32, _i32]),
-    "cde_loo_loglik": (ctypes.c_int, [_vp, _dp, _i32, _dp, _i32, ctypes.c_int, ctypes.c_int, _vp, _vp,
-                                      _vp, _vp]),
-    "cde_loo_loglik_list": (ctypes.c_int, [_vp, _dp, _i32, ctypes.c_int, _vp, _vp, _vp]),
+    "cde_loo_loglik": (ctypes.c_int, [_vp, _dp, _i32, _dp, _i32, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "cde_loo_loglik_list": (ctypes.c_int, [_vp, _dp, _i32, ctypes.c_int, ctypes.c_int, _vp, _vp,
+                                           _vp]),
     "cde_loo_grad": (ctypes.c_int, [_vp, _dp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "cde_density_query": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _dp, _vp, _vp]),
 }

@@ -154,6 +154,91 @@ cde_status run_diag_list(cde_model* m, const double* h, int g, int crit, bool gr
     return CDE_OK;
 }
 
+// Radial Epanechnikov setting (Section 5's kernel in the scaled form of
+// Section 2): K_h(t) = c_d / prod h * max(0, 1 - |t/h|^2), c_d = (d+2)/(2 V_d).
+double log_epan_norm(const double* h, int d)
+{
+    const double log_vd = 0.5 * d * std::log(3.14159265358979323846) - std::lgamma(0.5 * d + 1.0);
+    double s = std::log((d + 2.0) / 2.0) - log_vd;
+    for (int k = 0; k < d; ++k) s -= std::log(h[k]);
+    return s;
+}
+
+void fill_epan(EpanSet& s, const double* h, int dx, int dy)
+{
+    std::memset(&s, 0, sizeof s);
+    for (int k = 0; k < dx + dy; ++k) s.inv_h[k] = 1.0 / h[k];
+    s.log_cx = log_epan_norm(h, dx);
+    s.log_cy = log_epan_norm(h + dx, dy);
+}
+
+// Spatial order of the points, built on first use (one-time device memory:
+// sorted FP64 rows, permutation, tile boxes).
+cde_status ensure_index(cde_model* m, hipStream_t stream)
+{
+    if (m->index_ready) return CDE_OK;
+    const size_t spts_bytes = sizeof(double) * (size_t)m->npad * m->stride;
+    const size_t perm_bytes = sizeof(int) * (size_t)m->npad;
+    const size_t box_bytes = sizeof(double) * (size_t)(m->npad / TILE) * 2 * m->dx;
+    struct {
+        void** p;
+        size_t b;
+        const char* what;
+    } allocs[] = {{&m->spts, spts_bytes, "hipMalloc(sorted points)"},
+                  {&m->perm, perm_bytes, "hipMalloc(permutation)"},
+                  {&m->tbox, box_bytes, "hipMalloc(tile boxes)"}};
+    for (auto& a : allocs) {
+        if (*a.p) continue;
+        hipError_t e = hipMalloc(a.p, a.b);
+        if (e != hipSuccess) {
+            *a.p = nullptr;
+            return hip_fail(e, a.what);
+        }
+        m->bytes += a.b;
+    }
+    const size_t wb = index_work_bytes(m);
+    cde_status st = ensure_scratch(m, wb);
+    if (st != CDE_OK) return st;
+    hipError_t e = launch_build_index(m, m->scratch, m->scratch_bytes, stream);
+    if (e != hipSuccess) return hip_fail(e, "build spatial index");
+    m->index_ready = true;
+    return CDE_OK;
+}
+
+// Epanechnikov values for a list of g diagonal settings: totals[g], per-point
+// values in the caller's order, per-setting non-finite counts summed into
+// *nonfinite when given.
+cde_status run_epan_list(cde_model* m, const double* h, int g, int crit, double* totals,
+                         double* per_point, int64_t* nonfinite, hipStream_t stream)
+{
+    cde_status st = ensure_index(m, stream);
+    if (st != CDE_OK) return st;
+    const int p = m->dx + m->dy;
+    const int nblocks = (int)(m->npad / TILE);
+    const int per_launch = std::min(g, MAX_SETS_PER_LAUNCH);
+    const int chunks = epan_chunks(m, per_launch, MAX_DIAG_PARTIAL_DOUBLES);
+    const size_t part_doubles = (size_t)g * nblocks * 2 + (size_t)g;
+    const size_t partial_doubles = (size_t)per_launch * chunks * 2 * (size_t)m->npad;
+    st = ensure_scratch(m, sizeof(double) * (part_doubles + partial_doubles) + 256);
+    if (st != CDE_OK) return st;
+    double* part = (double*)m->scratch;
+    double* partial = part + part_doubles;
+    for (int s0 = 0; s0 < g; s0 += MAX_SETS_PER_LAUNCH) {
+        const int cnt = std::min(MAX_SETS_PER_LAUNCH, g - s0);
+        EpanSets sets;
+        std::memset(&sets, 0, sizeof sets);
+        for (int s = 0; s < cnt; ++s) fill_epan(sets.s[s], h + (size_t)(s0 + s) * p, m->dx, m->dy);
+        hipError_t e = launch_epan(m, sets, cnt, crit, chunks, partial,
+                                   per_point ? per_point + (size_t)s0 * m->n : nullptr,
+                                   part + (size_t)s0 * nblocks * 2, stream);
+        if (e != hipSuccess) return hip_fail(e, "launch k_loo_epan");
+    }
+    double* counts = part + (size_t)g * nblocks * 2;
+    hipError_t e = launch_reduce_parts(part, g, nblocks, 2, totals, nullptr, counts, nonfinite, stream);
+    if (e != hipSuccess) return hip_fail(e, "launch k_reduce_parts");
+    return CDE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -213,7 +298,7 @@ cde_status cde_destroy(cde_model* m)
     if (!m) return CDE_OK;
     DeviceGuard guard(m->device);
     cde_status st = CDE_OK;
-    for (void* p : {m->pts, m->nn, m->xmean, m->scratch}) {
+    for (void* p : {m->pts, m->nn, m->xmean, m->spts, m->perm, m->tbox, m->scratch}) {
         if (!p) continue;
         hipError_t e = hipFree(p);
         if (e != hipSuccess && st == CDE_OK) st = hip_fail(e, "hipFree");
@@ -254,7 +339,8 @@ size_t cde_workspace_bytes(int64_t n, int32_t dx, int32_t dy, cde_precision prec
 }
 
 cde_status cde_loo_loglik_list(cde_model* m, const double* h, int32_t g, cde_criterion criterion,
-                               double* totals_dev, double* per_point_dev, void* stream)
+                               cde_kernel kernel, double* totals_dev, double* per_point_dev,
+                               void* stream)
 {
     try {
         if (!m) return fail(CDE_EINVAL, "cde_loo_loglik_list: model is NULL");
@@ -264,8 +350,12 @@ cde_status cde_loo_loglik_list(cde_model* m, const double* h, int32_t g, cde_cri
             return fail(CDE_EINVAL, "cde_loo_loglik_list: unknown criterion");
         if (!valid_bandwidths(h, g * (m->dx + m->dy)))
             return fail(CDE_EINVAL, "cde_loo_loglik_list: bandwidths must be finite and > 0");
+        if (kernel != CDE_GAUSSIAN && kernel != CDE_EPANECHNIKOV)
+            return fail(CDE_EINVAL, "cde_loo_loglik_list: unknown kernel");
         DeviceGuard guard(m->device);
         hipStream_t s = (hipStream_t)stream;
+        if (kernel == CDE_EPANECHNIKOV)
+            return run_epan_list(m, h, g, criterion, totals_dev, per_point_dev, nullptr, s);
         return m->prec == CDE_F64
                    ? run_diag_list<double>(m, h, g, criterion, false, totals_dev, nullptr,
                                            per_point_dev, nullptr, s)
@@ -277,7 +367,7 @@ cde_status cde_loo_loglik_list(cde_model* m, const double* h, int32_t g, cde_cri
 }
 
 cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const double* hy,
-                          int32_t n_hy, cde_criterion criterion, cde_xterm xterm,
+                          int32_t n_hy, cde_criterion criterion, cde_kernel kernel, cde_xterm xterm,
                           double* totals_dev, double* per_point_dev, int64_t* n_nonfinite_dev,
                           void* stream)
 {
@@ -292,20 +382,27 @@ cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const do
             return fail(CDE_EINVAL, "cde_loo_loglik: unknown criterion");
         if (xterm != CDE_XTERM_AUTO && xterm != CDE_XTERM_VALU && xterm != CDE_XTERM_MFMA_BF16X3)
             return fail(CDE_EINVAL, "cde_loo_loglik: unknown xterm");
+        if (kernel != CDE_GAUSSIAN && kernel != CDE_EPANECHNIKOV)
+            return fail(CDE_EINVAL, "cde_loo_loglik: unknown kernel");
         const bool xt = xterm == CDE_XTERM_MFMA_BF16X3;
-        if (xt && (m->dx < 16 || m->prec != CDE_F32))
-            return fail(CDE_EUNSUPPORTED, "cde_loo_loglik: the MFMA cross term needs dx >= 16 and FP32 data");
+        if (xt && (m->dx < 16 || m->prec != CDE_F32 || kernel != CDE_GAUSSIAN))
+            return fail(CDE_EUNSUPPORTED,
+                        "cde_loo_loglik: the MFMA cross term needs dx >= 16, FP32 data and the Gaussian kernel");
         DeviceGuard guard(m->device);
         hipStream_t s = (hipStream_t)stream;
         const int g = n_hx * n_hy;
-        if (m->prec == CDE_F64) {
-            // FP64 models: every setting as a diagonal setting (FP64 throughout).
+        if (m->prec == CDE_F64 || kernel == CDE_EPANECHNIKOV) {
+            // FP64 models, and the Epanechnikov kernel: every setting as a
+            // diagonal setting (FP64 throughout).
             const int p = m->dx + m->dy;
             std::vector<double> h((size_t)g * p);
             for (int a = 0; a < n_hx; ++a)
                 for (int b = 0; b < n_hy; ++b)
                     for (int k = 0; k < p; ++k)
                         h[(size_t)(a * n_hy + b) * p + k] = k < m->dx ? hx[a] : hy[b];
+            if (kernel == CDE_EPANECHNIKOV)
+                return run_epan_list(m, h.data(), g, criterion, totals_dev, per_point_dev,
+                                     n_nonfinite_dev, s);
             return run_diag_list<double>(m, h.data(), g, criterion, false, totals_dev, nullptr,
                                          per_point_dev, n_nonfinite_dev, s);
         }

@@ -33,6 +33,17 @@ struct DiagSet {
 };
 
 constexpr int MAX_SETS_PER_LAUNCH = 8;
+// One diagonal setting for the Epanechnikov kernel: inverse bandwidths and
+// the log normalisations log c_x, log c_y of the radial kernel.
+struct EpanSet {
+    double inv_h[MAXP];
+    double log_cx;
+    double log_cy;
+};
+struct EpanSets {
+    EpanSet s[MAX_SETS_PER_LAUNCH];
+};
+
 // Cap on the chunk partials of one diagonal launch (2 GiB of doubles).
 constexpr size_t MAX_DIAG_PARTIAL_DOUBLES = size_t(1) << 28;
 
@@ -58,6 +69,11 @@ struct cde_model {
     bool nn_ready = false;
     void* xmean = nullptr;   // [16] floats: column means of x (cross-term option)
     bool xmean_ready = false;
+    // spatial order (compact-support kernels; built on first use)
+    void* spts = nullptr;    // [npad][stride] doubles: rows in Morton order of x
+    void* perm = nullptr;    // [npad] ints: sorted position -> original index
+    void* tbox = nullptr;    // [npad/TILE][2][dx] doubles: x box of each sorted tile
+    bool index_ready = false;
     void* scratch = nullptr; // block partials and flags
     size_t scratch_bytes = 0;
     size_t bytes = 0;

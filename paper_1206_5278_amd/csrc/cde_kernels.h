@@ -25,6 +25,23 @@ hipError_t launch_diag(const cde_model* m, const DiagSets<T>& sets, int nsets, i
 template <typename T>
 int diag_chunks(const cde_model* m, int nsets, bool grad, size_t max_doubles);
 size_t diag_partial_doubles(const cde_model* m, int nsets, bool grad, int chunks);
+// Shared makespan model behind diag_chunks and epan_chunks: `kern` is the
+// pair kernel (for its occupancy), np the partial planes per chunk.
+int choose_chunks(const void* kern, const cde_model* m, int nsets, int np, size_t max_doubles);
+
+// Spatial order of the model's points (Morton order of x, sorted FP64 rows,
+// permutation, per-tile x boxes) into m->spts / m->perm / m->tbox; `work`
+// holds index_work_bytes(m) bytes of temporaries.
+size_t index_work_bytes(const cde_model* m);
+hipError_t launch_build_index(cde_model* m, void* work, size_t work_bytes, hipStream_t stream);
+
+// Epanechnikov LOO pass over the spatially ordered points for `nsets`
+// settings (up to 8): pair kernel with exact tile skipping into `partial`
+// ([nsets][chunks][2][npad] doubles), then the fixed-order combine into
+// per_point (original order) and block rows (l, non-finite) in `part`.
+hipError_t launch_epan(const cde_model* m, const EpanSets& sets, int nsets, int crit, int chunks,
+                       double* partial, double* per_point, double* part, hipStream_t stream);
+int epan_chunks(const cde_model* m, int nsets, size_t max_doubles);
 
 // Density queries f(yg[g] | xq[q]) over all training points -> f [q][k].
 template <typename T>

@@ -529,6 +529,35 @@ template hipError_t launch_query<double>(const cde_model*, const double*, int64_
 // Tiles per chunk for a given chunk count (every chunk non-empty).
 static int tiles_per_chunk(int ntiles, int chunks) { return (ntiles + chunks - 1) / chunks; }
 
+// Chunk count by a makespan model: with B = blocks per chunk layer and R
+// resident blocks per CU of `kern`, C chunks of ceil(ntiles / C) tiles run in
+// ceil(B C / (R * CUs)) rounds, each as long as its tiles plus the chunk's
+// start-up (about 1/8 of a tile).  The smallest C of least modelled time
+// wins, within `max_doubles` of partial storage (np planes per chunk).
+int choose_chunks(const void* kern, const cde_model* m, int nsets, int np, size_t max_doubles)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TILE, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const double slots = (double)per_cu * (m->ncu > 0 ? m->ncu : 1);
+    const int ntiles = (int)(m->npad / TILE);
+    const double layer = (double)ntiles * nsets;
+    int best = 1;
+    double best_t = 0.0;
+    for (int c = 1; c <= 64 && c <= ntiles; ++c) {
+        const int tpc = tiles_per_chunk(ntiles, c);
+        const int used = (ntiles + tpc - 1) / tpc;
+        if (used != c) continue;
+        if ((size_t)nsets * used * np * (size_t)m->npad > max_doubles) break;
+        const double t = std::ceil(layer * used / slots) * (tpc + 0.125);
+        if (c == 1 || t < best_t * (1.0 - 1e-9)) {
+            best = c;
+            best_t = t;
+        }
+    }
+    return best;
+}
+
 template <typename T, int DX, int DY, bool GRAD>
 static hipError_t launch_diag_t(const cde_model* m, const DiagSets<T>& sets, int nsets, int crit,
                                 int chunks, double* partial, double* per_point, double* part,
@@ -547,36 +576,11 @@ static hipError_t launch_diag_t(const cde_model* m, const DiagSets<T>& sets, int
     return hipGetLastError();
 }
 
-// Chunk count by a makespan model: with B = blocks per chunk layer and R
-// resident blocks per CU, C chunks of ceil(ntiles / C) tiles run in
-// ceil(B C / (R * CUs)) rounds, each as long as its tiles plus the chunk's
-// start-up (the 32-pair reference pass, about 1/8 of a tile).  The smallest
-// C of least modelled time wins, within the partial-storage cap.
 template <typename T, int DX, int DY, bool GRAD>
 static int diag_chunks_t(const cde_model* m, int nsets, size_t max_doubles)
 {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_loo_diag<T, DX, DY, GRAD>, TILE, 0) !=
-            hipSuccess || per_cu < 1)
-        per_cu = 1;
-    const double slots = (double)per_cu * (m->ncu > 0 ? m->ncu : 1);
-    const int ntiles = (int)(m->npad / TILE);
-    const double layer = (double)ntiles * nsets;
-    constexpr int NP = DiagLane<T, DX, DY, GRAD>::NP;
-    int best = 1;
-    double best_t = 0.0;
-    for (int c = 1; c <= 64 && c <= ntiles; ++c) {
-        const int tpc = tiles_per_chunk(ntiles, c);
-        const int used = (ntiles + tpc - 1) / tpc;
-        if (used != c) continue;
-        if ((size_t)nsets * used * NP * (size_t)m->npad > max_doubles) break;
-        const double t = std::ceil(layer * used / slots) * (tpc + 0.125);
-        if (c == 1 || t < best_t * (1.0 - 1e-9)) {
-            best = c;
-            best_t = t;
-        }
-    }
-    return best;
+    return choose_chunks((const void*)k_loo_diag<T, DX, DY, GRAD>, m, nsets,
+                         DiagLane<T, DX, DY, GRAD>::NP, max_doubles);
 }
 
 #define CDE_DIAG_CASE(DX_, DY_)                                                                 \

@@ -17,6 +17,7 @@ import torch
 from . import _binding as B
 
 CRITERIA = {"cond": B.CDE_COND, "conditional": B.CDE_COND, "joint": B.CDE_JOINT}
+KERNELS = {"gaussian": B.CDE_GAUSSIAN, "epanechnikov": B.CDE_EPANECHNIKOV}
 
 
 def _stream_ptr(stream) -> int:
@@ -91,8 +92,9 @@ class Model:
 
     # ------------------------------------------------------------- the calls
     def loo_grid(self, hx, hy, criterion: str = "cond", per_point: bool = False,
-                 stream=None, out=None, xterm: int = B.CDE_XTERM_AUTO):
-        """Exact LOO log-likelihood totals over the scalar grid hx x hy.
+                 stream=None, out=None, xterm: int = B.CDE_XTERM_AUTO, kernel: str = "gaussian"):
+        """Exact LOO log-likelihood totals over the scalar grid hx x hy
+        (kernel "gaussian" or "epanechnikov").
 
         Returns (totals [len(hx)*len(hy)] float64 on the device, hx-major;
         per-point [G, n] or None; non-finite count tensor [1] int64)."""
@@ -103,20 +105,24 @@ class Model:
         pp = torch.empty((g, self.n), dtype=torch.float64, device=self.device) if per_point else None
         nonfin = torch.empty(1, dtype=torch.int64, device=self.device)
         st = self._lib.cde_loo_loglik(self._h, B.doubles(hx), len(hx), B.doubles(hy), len(hy),
-                                      CRITERIA[criterion], int(xterm), totals.data_ptr(),
+                                      CRITERIA[criterion], KERNELS[kernel], int(xterm),
+                                      totals.data_ptr(),
                                       pp.data_ptr() if pp is not None else None, nonfin.data_ptr(),
                                       _stream_ptr(stream))
         B.check(st, "cde_loo_loglik")
         return totals, pp, nonfin
 
-    def loo_list(self, hs, criterion: str = "cond", per_point: bool = False, stream=None):
-        """Totals for a list of diagonal settings hs [g][dx+dy] (or pairs)."""
+    def loo_list(self, hs, criterion: str = "cond", per_point: bool = False, stream=None,
+                 kernel: str = "gaussian"):
+        """Totals for a list of diagonal settings hs [g][dx+dy] (or pairs), with
+        the Gaussian or the Epanechnikov kernel."""
         rows = [self._bw(h) for h in hs]
         flat = [v for r in rows for v in r]
         totals = torch.empty(len(rows), dtype=torch.float64, device=self.device)
         pp = torch.empty((len(rows), self.n), dtype=torch.float64, device=self.device) if per_point else None
         st = self._lib.cde_loo_loglik_list(self._h, B.doubles(flat), len(rows), CRITERIA[criterion],
-                                           totals.data_ptr(), pp.data_ptr() if pp is not None else None,
+                                           KERNELS[kernel], totals.data_ptr(),
+                                           pp.data_ptr() if pp is not None else None,
                                            _stream_ptr(stream))
         B.check(st, "cde_loo_loglik_list")
         return totals, pp

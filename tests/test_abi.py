@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.cde_abi_version() == 1
+    assert lib.cde_abi_version() == 2
 
 
 def test_invalid_arguments_return_status(lib):
@@ -58,8 +58,8 @@ def test_invalid_arguments_return_status(lib):
     assert b"precision" in lib.cde_last_error()
     hv = B.doubles([1.0, 1.0])
     assert lib.cde_loo_grad(None, hv, 0, 8, 8, None, None) == B.CDE_EINVAL
-    assert lib.cde_loo_loglik(None, hv, 1, hv, 1, 0, 0, 8, None, None, None) == B.CDE_EINVAL
-    assert lib.cde_loo_loglik_list(None, hv, 1, 0, 8, None, None) == B.CDE_EINVAL
+    assert lib.cde_loo_loglik(None, hv, 1, hv, 1, 0, 0, 0, 8, None, None, None) == B.CDE_EINVAL
+    assert lib.cde_loo_loglik_list(None, hv, 1, 0, 0, 8, None, None) == B.CDE_EINVAL
     assert lib.cde_density_query(None, 8, 1, 8, 1, hv, 8, None) == B.CDE_EINVAL
     assert lib.cde_destroy(None) == B.CDE_OK
     assert lib.cde_model_device_bytes(None) == 0
