@@ -180,13 +180,15 @@ cde_status ensure_index(cde_model* m, hipStream_t stream)
     const size_t spts_bytes = sizeof(double) * (size_t)m->npad * m->stride;
     const size_t perm_bytes = sizeof(int) * (size_t)m->npad;
     const size_t box_bytes = sizeof(double) * (size_t)(m->npad / TILE) * 2 * m->dx;
+    const size_t sbox_bytes = sizeof(double) * (size_t)(m->npad / SUBROWS) * 2 * m->dx;
     struct {
         void** p;
         size_t b;
         const char* what;
     } allocs[] = {{&m->spts, spts_bytes, "hipMalloc(sorted points)"},
                   {&m->perm, perm_bytes, "hipMalloc(permutation)"},
-                  {&m->tbox, box_bytes, "hipMalloc(tile boxes)"}};
+                  {&m->tbox, box_bytes, "hipMalloc(tile boxes)"},
+                  {&m->sbox, sbox_bytes, "hipMalloc(subtile boxes)"}};
     for (auto& a : allocs) {
         if (*a.p) continue;
         hipError_t e = hipMalloc(a.p, a.b);
@@ -298,7 +300,7 @@ cde_status cde_destroy(cde_model* m)
     if (!m) return CDE_OK;
     DeviceGuard guard(m->device);
     cde_status st = CDE_OK;
-    for (void* p : {m->pts, m->nn, m->xmean, m->spts, m->perm, m->tbox, m->scratch}) {
+    for (void* p : {m->pts, m->nn, m->xmean, m->spts, m->perm, m->tbox, m->sbox, m->scratch}) {
         if (!p) continue;
         hipError_t e = hipFree(p);
         if (e != hipSuccess && st == CDE_OK) st = hip_fail(e, "hipFree");

@@ -10,6 +10,7 @@
 namespace cde {
 
 constexpr int TILE = 256;           // points per tile (i-block and j-tile)
+constexpr int SUBROWS = 32;         // rows per subtile box of the spatial index
 constexpr int MAXP = 18;            // dx + dy for the largest instantiated shape (16 + 2)
 constexpr double LOG2E = 1.4426950408889634073599246810019;
 constexpr double LN2 = 0.69314718055994530941723212145818;
@@ -73,6 +74,7 @@ struct cde_model {
     void* spts = nullptr;    // [npad][stride] doubles: rows in Morton order of x
     void* perm = nullptr;    // [npad] ints: sorted position -> original index
     void* tbox = nullptr;    // [npad/TILE][2][dx] doubles: x box of each sorted tile
+    void* sbox = nullptr;    // [npad/SUBROWS][2][dx] doubles: x box of each sorted subtile
     bool index_ready = false;
     void* scratch = nullptr; // block partials and flags
     size_t scratch_bytes = 0;

@@ -14,7 +14,10 @@
 // The kernel is exactly zero outside its window, so a (point block, j tile)
 // pair whose x boxes (in the model's spatial order) are at scaled distance
 // above 1 contributes exactly nothing and is skipped without loading it; the
-// margin 2^-40 keeps that decision clear of the rounding of the distances.
+// candidate tiles of a block are tested in parallel and compacted in order.
+// Inside a loaded tile each wave skips the 32-row subtiles whose boxes lie a
+// window from its own 64 points.  The margin 2^-40 keeps these decisions
+// clear of the rounding of the distances.
 // Everything else follows the Gaussian diagonal pass: one lane per point i,
 // j tiles through LDS, blockIdx.y a setting, blockIdx.z a chunk of j tiles,
 // partial sums per chunk combined in a fixed order.  The pair arithmetic is
@@ -33,82 +36,132 @@ namespace {
 
 constexpr double SKIP_MARGIN = 1.0 + 0x1p-40;
 
+// Scaled squared gap between two x boxes (lo[0..DX), hi[0..DX) each).
+template <int DX>
+__device__ __forceinline__ double box_gap2(const double* alo, const double* ahi, const double* blo,
+                                           const double* bhi, const double (&inv)[DX])
+{
+    double d2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < DX; ++k) {
+        const double gap = fmax(0.0, fmax(blo[k] - ahi[k], alo[k] - bhi[k])) * inv[k];
+        d2 = fma(gap, gap, d2);
+    }
+    return d2;
+}
+
 template <int DX, int DY>
 __global__ __launch_bounds__(TILE) void k_loo_epan(const double* __restrict__ spts,
-                                                   const double* __restrict__ tbox, int n, int npad,
+                                                   const double* __restrict__ tbox,
+                                                   const double* __restrict__ sbox, int n, int npad,
                                                    EpanSets sets, int tiles_per_chunk,
                                                    double* __restrict__ partial)
 {
     constexpr int S = row_stride(DX, DY);
     constexpr int P = DX + DY;
+    constexpr int NSUB = TILE / SUBROWS;
     __shared__ double tile[TILE * S];
+    __shared__ int list[TILE];
+    __shared__ int wcount[4];
     const EpanSet& st = sets.s[blockIdx.y];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int b = blockIdx.x;
     const int i = b * TILE + tid;
 
-    double inv[P];
+    double inv[P], invx[DX];
 #pragma unroll
     for (int k = 0; k < P; ++k) inv[k] = st.inv_h[k];
+#pragma unroll
+    for (int k = 0; k < DX; ++k) invx[k] = inv[k];
     double own[S], xs[P];
     load_row<S>(own, spts + (size_t)i * S);
 #pragma unroll
     for (int k = 0; k < P; ++k) xs[k] = own[k] * inv[k];
 
-    const double* ib = tbox + (size_t)b * 2 * DX;
-    // scaled squared gap between this block's x box and tile t's
-    auto far = [&](int t) {
-        const double* jb = tbox + (size_t)t * 2 * DX;
-        double d2 = 0.0;
+    // this wave's x box (its 64 points; padding rows excluded)
+    double wlo[DX], whi[DX];
 #pragma unroll
-        for (int k = 0; k < DX; ++k) {
-            const double gap = fmax(0.0, fmax(jb[k] - ib[DX + k], ib[k] - jb[DX + k])) * inv[k];
-            d2 = fma(gap, gap, d2);
+    for (int k = 0; k < DX; ++k) {
+        double a = i < n ? own[k] : __builtin_inf();
+        double c = i < n ? own[k] : -__builtin_inf();
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            a = fmin(a, __shfl_xor(a, off, 64));
+            c = fmax(c, __shfl_xor(c, off, 64));
         }
-        return d2 > SKIP_MARGIN;
-    };
+        wlo[k] = a;
+        whi[k] = c;
+    }
+    double blo[DX], bhi[DX];
+#pragma unroll
+    for (int k = 0; k < DX; ++k) {
+        blo[k] = tbox[(size_t)b * 2 * DX + k];
+        bhi[k] = tbox[(size_t)b * 2 * DX + DX + k];
+    }
 
     const int ntiles = (n + TILE - 1) / TILE;
     const int t0 = blockIdx.z * tiles_per_chunk;
     const int t1 = min(ntiles, t0 + tiles_per_chunk);
     double D = 0.0, U = 0.0;
-    int t = t0;
-    while (t < t1 && far(t)) ++t;
-    double pre[S];
-    if (t < t1) load_row<S>(pre, spts + ((size_t)t * TILE + tid) * S);
-    while (t < t1) {
-        int nxt = t + 1;
-        while (nxt < t1 && far(nxt)) ++nxt;
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < S; ++k) tile[tid * S + k] = k < P ? pre[k] * inv[k] : 0.0;
-        __syncthreads();
-        if (nxt < t1) load_row<S>(pre, spts + ((size_t)nxt * TILE + tid) * S);
-        const int cnt = min(TILE, n - t * TILE);
-        const int self = (t == b) ? tid : -1;
-        const bool mask = self >= 0 || cnt < TILE;
-#pragma unroll 4
-        for (int q = 0; q < TILE; ++q) {
-            double pj[S];
-            load_cols<P, S>(pj, tile + q * S);
-            double ux = 0.0, uy = 0.0;
-#pragma unroll
-            for (int k = 0; k < DX; ++k) {
-                const double d = xs[k] - pj[k];
-                ux = fma(d, d, ux);
-            }
-#pragma unroll
-            for (int l = 0; l < DY; ++l) {
-                const double d = xs[DX + l] - pj[DX + l];
-                uy = fma(d, d, uy);
-            }
-            double wx = fmax(1.0 - ux, 0.0);
-            const double wy = fmax(1.0 - uy, 0.0);
-            if (mask && (q == self || q >= cnt)) wx = 0.0;
-            D += wx;
-            U = fma(wx, wy, U);
+    for (int base = t0; base < t1; base += TILE) {
+        // Candidate tiles base..base+255 in parallel, compacted in order.
+        const int cand = base + tid;
+        bool act = false;
+        if (cand < t1) {
+            const double* cb = tbox + (size_t)cand * 2 * DX;
+            act = box_gap2<DX>(blo, bhi, cb, cb + DX, invx) <= SKIP_MARGIN;
         }
-        t = nxt;
+        const unsigned long long mask = __ballot(act);
+        __syncthreads();  // the previous round has finished with list[] and tile[]
+        if (lane == 0) wcount[wave] = __popcll(mask);
+        __syncthreads();
+        int ofs = 0;
+        for (int w = 0; w < wave; ++w) ofs += wcount[w];
+        const int nact = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        if (act) list[ofs + __popcll(mask & ((1ull << lane) - 1ull))] = cand;
+        __syncthreads();
+
+        double pre[S];
+        if (nact > 0) load_row<S>(pre, spts + ((size_t)list[0] * TILE + tid) * S);
+        for (int a = 0; a < nact; ++a) {
+            const int t = list[a];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < S; ++k) tile[tid * S + k] = k < P ? pre[k] * inv[k] : 0.0;
+            __syncthreads();
+            if (a + 1 < nact) load_row<S>(pre, spts + ((size_t)list[a + 1] * TILE + tid) * S);
+            const int cnt = min(TILE, n - t * TILE);
+            const int self = (t == b) ? tid : -1;
+            const bool mask_rows = self >= 0 || cnt < TILE;
+            for (int sb = 0; sb < NSUB; ++sb) {
+                if (sb * SUBROWS >= cnt) break;
+                // this wave's box against the subtile's: skip when a window apart
+                const double* xb = sbox + ((size_t)t * NSUB + sb) * 2 * DX;
+                if (box_gap2<DX>(wlo, whi, xb, xb + DX, invx) > SKIP_MARGIN) continue;
+#pragma unroll 4
+                for (int r = 0; r < SUBROWS; ++r) {
+                    const int q = sb * SUBROWS + r;
+                    double pj[S];
+                    load_cols<P, S>(pj, tile + q * S);
+                    double ux = 0.0, uy = 0.0;
+#pragma unroll
+                    for (int k = 0; k < DX; ++k) {
+                        const double d = xs[k] - pj[k];
+                        ux = fma(d, d, ux);
+                    }
+#pragma unroll
+                    for (int l = 0; l < DY; ++l) {
+                        const double d = xs[DX + l] - pj[DX + l];
+                        uy = fma(d, d, uy);
+                    }
+                    double wx = fmax(1.0 - ux, 0.0);
+                    const double wy = fmax(1.0 - uy, 0.0);
+                    if (mask_rows && (q == self || q >= cnt)) wx = 0.0;
+                    D += wx;
+                    U = fma(wx, wy, U);
+                }
+            }
+        }
     }
     double* o = partial + ((size_t)(blockIdx.y * gridDim.z + blockIdx.z) * 2) * npad + i;
     o[0] = D;
@@ -164,8 +217,8 @@ static hipError_t launch_epan_t(const cde_model* m, const EpanSets& sets, int ns
     const int tpc = (nblocks + chunks - 1) / chunks;
     const int used = (nblocks + tpc - 1) / tpc;
     hipLaunchKernelGGL((k_loo_epan<DX, DY>), dim3(nblocks, nsets, used), dim3(TILE), 0, stream,
-                       (const double*)m->spts, (const double*)m->tbox, (int)m->n, (int)m->npad, sets,
-                       tpc, partial);
+                       (const double*)m->spts, (const double*)m->tbox, (const double*)m->sbox,
+                       (int)m->n, (int)m->npad, sets, tpc, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_epan_combine, dim3(nblocks, nsets), dim3(TILE), 0, stream,

@@ -112,6 +112,28 @@ __global__ __launch_bounds__(TILE) void k_tile_boxes(const double* __restrict__ 
     }
 }
 
+// x box of each 32-row subtile of the sorted rows (rows < n only), same
+// layout as the tile boxes; one thread per subtile.
+__global__ void k_sub_boxes(const double* __restrict__ spts, int n, int nsub, int dx, int stride,
+                            double* __restrict__ box)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nsub) return;
+    for (int k = 0; k < dx; ++k) {
+        double a = __builtin_inf(), b = -__builtin_inf();
+        for (int r = 0; r < SUBROWS; ++r) {
+            const int s = g * SUBROWS + r;
+            if (s < n) {
+                const double v = spts[(size_t)s * stride + k];
+                a = fmin(a, v);
+                b = fmax(b, v);
+            }
+        }
+        box[((size_t)g * 2 + 0) * dx + k] = a;
+        box[((size_t)g * 2 + 1) * dx + k] = b;
+    }
+}
+
 template <typename T>
 static hipError_t build_index_t(cde_model* m, void* work, size_t work_bytes, hipStream_t stream)
 {
@@ -145,6 +167,10 @@ static hipError_t build_index_t(cde_model* m, void* work, size_t work_bytes, hip
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_boxes, dim3(npad / TILE), dim3(TILE), 0, stream, (const double*)m->spts, n,
                        dx, stride, (double*)m->tbox);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int nsub = npad / SUBROWS;
+    hipLaunchKernelGGL(k_sub_boxes, dim3((nsub + 255) / 256), dim3(256), 0, stream, (const double*)m->spts,
+                       n, nsub, dx, stride, (double*)m->sbox);
     return hipGetLastError();
 }
 
