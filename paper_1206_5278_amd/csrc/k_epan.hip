@@ -50,6 +50,39 @@ __device__ __forceinline__ double box_gap2(const double* alo, const double* ahi,
     return d2;
 }
 
+// One 32-row subtile of the staged (pre-scaled) tile against this lane's
+// point: adds the x weights to D and the product weights to U.  MASK drops
+// row `self` (point i itself) and rows at or beyond `cnt`.
+template <int DX, int DY, bool MASK>
+__device__ __forceinline__ void epan_subtile(const double* tile, int q0, int cnt, int self,
+                                             const double (&xs)[DX + DY], double& D, double& U)
+{
+    constexpr int S = row_stride(DX, DY);
+    constexpr int P = DX + DY;
+#pragma unroll 4
+    for (int r = 0; r < SUBROWS; ++r) {
+        const int q = q0 + r;
+        double pj[S];
+        load_cols<P, S>(pj, tile + q * S);
+        double ux = 0.0, uy = 0.0;
+#pragma unroll
+        for (int k = 0; k < DX; ++k) {
+            const double d = xs[k] - pj[k];
+            ux = fma(d, d, ux);
+        }
+#pragma unroll
+        for (int l = 0; l < DY; ++l) {
+            const double d = xs[DX + l] - pj[DX + l];
+            uy = fma(d, d, uy);
+        }
+        double wx = fmax(1.0 - ux, 0.0);
+        const double wy = fmax(1.0 - uy, 0.0);
+        if (MASK && (q == self || q >= cnt)) wx = 0.0;
+        D += wx;
+        U = fma(wx, wy, U);
+    }
+}
+
 template <int DX, int DY>
 __global__ __launch_bounds__(TILE) void k_loo_epan(const double* __restrict__ spts,
                                                    const double* __restrict__ tbox,
@@ -138,28 +171,10 @@ __global__ __launch_bounds__(TILE) void k_loo_epan(const double* __restrict__ sp
                 // this wave's box against the subtile's: skip when a window apart
                 const double* xb = sbox + ((size_t)t * NSUB + sb) * 2 * DX;
                 if (box_gap2<DX>(wlo, whi, xb, xb + DX, invx) > SKIP_MARGIN) continue;
-#pragma unroll 4
-                for (int r = 0; r < SUBROWS; ++r) {
-                    const int q = sb * SUBROWS + r;
-                    double pj[S];
-                    load_cols<P, S>(pj, tile + q * S);
-                    double ux = 0.0, uy = 0.0;
-#pragma unroll
-                    for (int k = 0; k < DX; ++k) {
-                        const double d = xs[k] - pj[k];
-                        ux = fma(d, d, ux);
-                    }
-#pragma unroll
-                    for (int l = 0; l < DY; ++l) {
-                        const double d = xs[DX + l] - pj[DX + l];
-                        uy = fma(d, d, uy);
-                    }
-                    double wx = fmax(1.0 - ux, 0.0);
-                    const double wy = fmax(1.0 - uy, 0.0);
-                    if (mask_rows && (q == self || q >= cnt)) wx = 0.0;
-                    D += wx;
-                    U = fma(wx, wy, U);
-                }
+                if (mask_rows)
+                    epan_subtile<DX, DY, true>(tile, sb * SUBROWS, cnt, self, xs, D, U);
+                else
+                    epan_subtile<DX, DY, false>(tile, sb * SUBROWS, cnt, self, xs, D, U);
             }
         }
     }
