@@ -1,7 +1,7 @@
 """Epanechnikov-kernel LOO likelihood (the kernel of the paper's experiments,
-Section 5) on the photoz-shaped set, N = 500,000, dx = 5, dy = 1.
+Section 4) on the photoz-shaped set, N = 500,000, dx = 5, dy = 1.
 
-Bandwidths follow Section 5's convention: one scalar h on data scaled by each
+Bandwidths follow Section 4's convention: one scalar h on data scaled by each
 dimension's standard deviation, i.e. h_k = h * sd_k.  For each h the script
 times the value pass (pair kernel with exact tile skipping plus the chunk
 combine), checks sampled points against the FP64 oracle (each against all

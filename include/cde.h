@@ -7,7 +7,7 @@
  * Estimation".
  *   - Kernel (Section 2): K_h(t) = h^{-d} K(t/h).  K is the Gaussian, used
  *     as a product over dimensions with one bandwidth per dimension, or the
- *     Epanechnikov kernel of the paper's experiments (Section 5), radial over
+ *     Epanechnikov kernel of the paper's experiments (Section 4), radial over
  *     the bandwidth-scaled coordinates: c_d (1 - |t/h|^2)_+ / prod h with
  *     c_d = (d+2) / (2 V_d), V_d the volume of the unit d-ball.
  *   - Estimator (Section 2, eq. 1): f(y|x) = sum_i K_hy(y-y_i) K_hx(x-x_i) /
@@ -50,10 +50,10 @@ typedef struct cde_model cde_model; /* opaque handle */
 
 typedef enum {
     CDE_GAUSSIAN = 0,     /* product Gaussian, one bandwidth per dimension */
-    CDE_EPANECHNIKOV = 1  /* radial Epanechnikov over scaled coordinates (Section 5's
+    CDE_EPANECHNIKOV = 1  /* radial Epanechnikov over scaled coordinates (Section 4's
                              kernel); exactly zero outside its window, so a point
                              with no j inside both windows has l_i = -inf, the
-                             divergence at tiny bandwidths Section 5 notes */
+                             divergence at tiny bandwidths Section 4.1 notes */
 } cde_kernel;
 
 typedef enum {

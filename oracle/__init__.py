@@ -10,7 +10,7 @@ The arithmetic lives in ``cde_oracle.c`` (plain C, double precision, no
 blocking or factorisation); this module only marshals numpy arrays.
 Definitions followed (Holmes, Gray & Isbell): Section 2 (scaled kernel,
 eq. 1), Section 3 eq. (3) and the A_i expansion of Section 3.2; the Gaussian
-kernel, and the Epanechnikov kernel of Section 5 (``loo_epan``,
+kernel, and the Epanechnikov kernel of Section 4 (``loo_epan``,
 ``density_epan``).
 """
 from __future__ import annotations

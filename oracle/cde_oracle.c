@@ -41,7 +41,7 @@
  * where Mw_k = sum_j exp(a_j-Mx) dx_k^2, Mv_k = sum_j exp(a_j+b_j-Mxy) dx_k^2
  * and Mvy_l = sum_j exp(a_j+b_j-Mxy) dy_l^2.
  *
- * Epanechnikov kernel (the kernel of the paper's experiments, Section 5),
+ * Epanechnikov kernel (the kernel of the paper's experiments, Section 4),
  * radial over the bandwidth-scaled coordinates as in Section 2's K_h of a
  * norm: K_h(t) = c_d / prod_k h_k * max(0, 1 - sum_k (t_k/h_k)^2) with the
  * multivariate normalisation c_d = (d+2) / (2 V_d), V_d = pi^{d/2} /
@@ -52,7 +52,7 @@
  *   CONDITIONAL: l_i = log c_y + log U - log D
  *   JOINT      : l_i = log c_x + log c_y + log U - log(n-1)
  * with log c_x = log c_dx - sum_k log hx_k.  U = 0 (no j inside both
- * windows; the divergence of L at tiny bandwidths noted in Section 5) gives
+ * windows; the divergence of L at tiny bandwidths noted in Section 4.1) gives
  * l_i = -inf.
  *
  * Threads: points i are split into contiguous ranges, one per thread; each

@@ -154,7 +154,7 @@ cde_status run_diag_list(cde_model* m, const double* h, int g, int crit, bool gr
     return CDE_OK;
 }
 
-// Radial Epanechnikov setting (Section 5's kernel in the scaled form of
+// Radial Epanechnikov setting (Section 4's kernel in the scaled form of
 // Section 2): K_h(t) = c_d / prod h * max(0, 1 - |t/h|^2), c_d = (d+2)/(2 V_d).
 double log_epan_norm(const double* h, int d)
 {

@@ -1,6 +1,6 @@
 // k_epan.hip -- exact LOO log-likelihood with the Epanechnikov kernel.
 //
-// Kernel (the paper's experiments, Section 5; scaled-kernel form of
+// Kernel (the paper's experiments, Section 4; scaled-kernel form of
 // Section 2, radial over bandwidth-scaled coordinates):
 //     K_h(t) = c_d / prod_k h_k * max(0, 1 - sum_k (t_k / h_k)^2),
 // c_d = (d + 2) / (2 V_d), V_d the volume of the unit d-ball.  Per point i,
@@ -9,7 +9,7 @@
 //     CONDITIONAL: l_i = log c_y + log U - log D
 //     JOINT      : l_i = log c_x + log c_y + log U - log(n - 1)
 // and l_i = -inf when U = 0 (no j inside both windows: the divergence at
-// tiny bandwidths that Section 5 notes).
+// tiny bandwidths that Section 4.1 notes).
 //
 // The kernel is exactly zero outside its window, so a (point block, j tile)
 // pair whose x boxes (in the model's spatial order) are at scaled distance

@@ -1,5 +1,5 @@
 // k_index.hip -- a spatial order of a model's points, for compact-support
-// kernels (the Epanechnikov kernel of the paper's experiments, Section 5).
+// kernels (the Epanechnikov kernel of the paper's experiments, Section 4).
 //
 // A kernel that is exactly zero outside its window lets a (point block, j
 // tile) pair be skipped when the two tiles' bounding boxes lie a window

@@ -2,7 +2,7 @@
 
 Written from the definitions only (scaled Gaussian kernel, Section 2;
 eq. (1); eq. (3) with the A_i expansion of Section 3.2; the Epanechnikov
-kernel of Section 5 in its multivariate radial form): every kernel value is
+kernel of Section 4 in its multivariate radial form): every kernel value is
 formed in full, constants included, with Python's ``decimal`` arithmetic and
 its own exp/ln, and summed directly -- no log-sum-exp, no shifts.  It shares
 nothing with the C oracle and is used only on tiny inputs.

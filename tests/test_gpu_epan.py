@@ -1,5 +1,5 @@
 """GPU parity of the Epanechnikov-kernel LOO likelihood (the kernel of the
-paper's experiments, Section 5) against the FP64 CPU oracle, through the C
+paper's experiments, Section 4) against the FP64 CPU oracle, through the C
 ABI: every shape, both precisions and criteria, ragged and multi-chunk sizes,
 bandwidths from "every point diverges" to "no tile is skipped", the grid
 call, per-point order (the GPU works in a spatial order and must scatter back)

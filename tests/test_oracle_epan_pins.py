@@ -1,9 +1,9 @@
-"""Pins of the oracle's Epanechnikov kernel (Section 5's kernel, radial over
+"""Pins of the oracle's Epanechnikov kernel (Section 4's kernel, radial over
 bandwidth-scaled coordinates, multivariate normalisation), each against
 something other than the oracle itself: a 50-digit brute force whose unit-ball
 volume comes from its own recurrence, closed forms, the LOO kernel density
 estimate it reduces to, the normalisation of the density, invariances, and
-the divergence at tiny bandwidths noted in Section 5."""
+the divergence at tiny bandwidths noted in Section 4.1."""
 import math
 
 import numpy as np
