@@ -66,6 +66,11 @@ def load_library(path: str):
     lib.oracle_density_epan.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, dp,
                                         dp, ctypes.c_long, dp, ctypes.c_long, dp]
     lib.oracle_density_epan.restype = ctypes.c_int
+    lib.oracle_cond_mean.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, dp, dp,
+                                     ctypes.c_long, dp]
+    lib.oracle_cond_mean.restype = ctypes.c_int
+    lib.oracle_density_summary.argtypes = [dp, dp, ctypes.c_long, ctypes.c_long, ctypes.c_double, dp]
+    lib.oracle_density_summary.restype = ctypes.c_int
     return lib
 
 
@@ -212,3 +217,33 @@ def density_epan(x, y, h, xq, yg, lib=None):
     if s:
         raise ValueError(f"oracle_density_epan failed with status {s}")
     return f
+
+
+def cond_mean(x, y, h, xq, lib=None):
+    """E[y | xq] of eq. (1)'s density (Gaussian kernel): returns [q, dy]."""
+    lib = _load(lib)
+    x, y = _f64(x), _f64(y)
+    n, dx = x.shape
+    dy = y.shape[1]
+    h = _bw(h, dx, dy)
+    xq = _f64(xq).reshape(-1, dx)
+    q = xq.shape[0]
+    out = np.empty((q, dy))
+    s = lib.oracle_cond_mean(_ptr(x), _ptr(y), n, dx, dy, _ptr(h), _ptr(xq), q, _ptr(out))
+    if s:
+        raise ValueError(f"oracle_cond_mean failed with status {s}")
+    return out
+
+
+def density_summary(f, yg, alpha=0.05, lib=None):
+    """Per row of f [q, k] on the increasing grid yg [k]: [q, 4] = mass, mode,
+    lo, hi of the narrowest 1 - alpha interval (see cde_oracle.c)."""
+    lib = _load(lib)
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1, np.size(yg)))
+    yg = np.ascontiguousarray(np.asarray(yg, dtype=np.float64).ravel())
+    q, k = f.shape
+    out = np.empty((q, 4))
+    s = lib.oracle_density_summary(_ptr(f), _ptr(yg), q, k, float(alpha), _ptr(out))
+    if s:
+        raise ValueError(f"oracle_density_summary failed with status {s}")
+    return out

@@ -55,6 +55,23 @@
  * windows; the divergence of L at tiny bandwidths noted in Section 4.1) gives
  * l_i = -inf.
  *
+ * Query-side products (Section 1 lists the expectation, modes and prediction
+ * intervals as what a conditional density yields; Section 4.2 predicts y by
+ * the expectation of f(y|x) and builds prediction intervals by searching for
+ * the narrowest set of quantiles with the desired coverage):
+ *   - conditional mean E[y|x] = sum_i K_hx(x-x_i) y_i / sum_i K_hx(x-x_i),
+ *     the mean of eq. (1)'s density (Gaussian kernel; the y-kernel is
+ *     symmetric, so each component's mean is y_i);
+ *   - summary of a density f on an increasing y grid (dy = 1): mass = the
+ *     trapezoid integral; mode = the first grid point of maximal f; the
+ *     narrowest interval [lo, hi] holding 1 - alpha of the grid's CDF G
+ *     (trapezoid partial sums over mass, linear between grid points), over
+ *     the candidates with lo on a grid point (hi = G^-1(G(lo) + 1 - alpha))
+ *     and then those with hi on a grid point (lo = G^-1(G(hi) - (1 - alpha))),
+ *     the first of least width in that order (a later candidate replaces it
+ *     only when narrower by more than 1e-12 of the grid's span, so ties do
+ *     not depend on rounding).
+ *
  * Threads: points i are split into contiguous ranges, one per thread; each
  * l_i is computed by exactly the same code whatever the split, so results are
  * bitwise independent of the thread count.  Totals are formed by the caller
@@ -496,5 +513,101 @@ int oracle_density_epan(const double* x, const double* y, long n, int dx, int dy
             f[(size_t)qq * k + g] = D > 0.0 ? cy * U / D : 0.0;
         }
     }
+    return 0;
+}
+
+/* Conditional mean (Gaussian kernel): mean[qq][l] = sum_i w_i y_il / sum_i w_i
+ * with w_i = exp(-1/2 sum_k ((xq_k - x_ik)/hx_k)^2), shifted by the largest
+ * exponent (the common factor cancels in the ratio).  h holds hx in its first
+ * dx entries (the y bandwidth does not enter the mean). */
+int oracle_cond_mean(const double* x, const double* y, long n, int dx, int dy,
+                     const double* h, const double* xq, long q, double* mean)
+{
+    if (check_args(x, y, n, dx, dy, h) || !xq || !mean || q < 0) return 1;
+    double* a = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!a) return 2;
+    for (long qq = 0; qq < q; ++qq) {
+        double M = -INFINITY;
+        for (long i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int k = 0; k < dx; ++k) {
+                double t = (xq[(size_t)qq * dx + k] - x[(size_t)i * dx + k]) / h[k];
+                s += t * t;
+            }
+            a[i] = -0.5 * s;
+            if (a[i] > M) M = a[i];
+        }
+        for (int l = 0; l < dy; ++l) {
+            double D = 0.0, S = 0.0;
+            for (long i = 0; i < n; ++i) {
+                const double w = exp(a[i] - M);
+                D += w;
+                S += w * y[(size_t)i * dy + l];
+            }
+            mean[(size_t)qq * dy + l] = S / D;
+        }
+    }
+    free(a);
+    return 0;
+}
+
+/* Smallest y on the grid's piecewise-linear CDF with G(y) >= p (0 <= p <= 1),
+ * G[0..k) non-decreasing with G[0] = 0. */
+static double grid_inverse(const double* G, const double* yg, long k, double p)
+{
+    long g = 0;
+    while (g < k - 1 && G[g] < p) ++g;
+    if (g == 0 || G[g] <= G[g - 1]) return yg[g];
+    return yg[g - 1] + (p - G[g - 1]) / (G[g] - G[g - 1]) * (yg[g] - yg[g - 1]);
+}
+
+/* Summary of each row of f[q][k] on the increasing grid yg[k] (k >= 2):
+ * out[qq][0..4) = mass, mode, lo, hi as described in the header.  A row of
+ * zero mass gives mass 0, mode yg[0] and lo = hi = NaN. */
+int oracle_density_summary(const double* f, const double* yg, long q, long k, double alpha,
+                           double* out)
+{
+    if (!f || !yg || !out || q < 0 || k < 2 || !(alpha > 0.0) || !(alpha < 1.0)) return 1;
+    double* G = (double*)malloc(sizeof(double) * (size_t)k);
+    if (!G) return 2;
+    for (long qq = 0; qq < q; ++qq) {
+        const double* r = f + (size_t)qq * k;
+        double* o = out + (size_t)qq * 4;
+        double c = 0.0;
+        G[0] = 0.0;
+        for (long g = 0; g + 1 < k; ++g) {
+            c += (r[g] + r[g + 1]) * 0.5 * (yg[g + 1] - yg[g]);
+            G[g + 1] = c;
+        }
+        const double mass = c;
+        long imax = 0;
+        for (long g = 1; g < k; ++g)
+            if (r[g] > r[imax]) imax = g;
+        o[0] = mass;
+        o[1] = yg[imax];
+        if (!(mass > 0.0)) {
+            o[2] = o[3] = NAN;
+            continue;
+        }
+        for (long g = 0; g < k; ++g) G[g] = G[g] / mass;
+        const double cover = 1.0 - alpha;
+        const double tie = 1e-12 * (yg[k - 1] - yg[0]);
+        double best = INFINITY, blo = NAN, bhi = NAN;
+        for (long g = 0; g < k; ++g) {          /* lo on a grid point */
+            const double p = G[g] + cover;
+            if (p > 1.0) break;
+            const double hi = grid_inverse(G, yg, k, p);
+            if (hi - yg[g] < best - tie) { best = hi - yg[g]; blo = yg[g]; bhi = hi; }
+        }
+        for (long g = 0; g < k; ++g) {          /* hi on a grid point */
+            const double p = G[g] - cover;
+            if (p < 0.0) continue;
+            const double lo = grid_inverse(G, yg, k, p);
+            if (yg[g] - lo < best - tie) { best = yg[g] - lo; blo = lo; bhi = yg[g]; }
+        }
+        o[2] = blo;
+        o[3] = bhi;
+    }
+    free(G);
     return 0;
 }

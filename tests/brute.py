@@ -119,3 +119,19 @@ def ell_epan(x, y, hx, hy, criterion="cond"):
         else:
             out.append(float((num / (n - 1)).ln()))
     return out
+
+
+def cond_mean(x, y, hx, xq):
+    """E[y | xq] = sum_i K_hx(xq - x_i) y_i / sum_i K_hx(xq - x_i) (first y
+    column), every kernel value formed in full."""
+    X = [[_d(v) for v in row] for row in x]
+    Y = [_d(row[0]) for row in y]
+    HX = [_d(v) for v in hx]
+    XQ = [_d(v) for v in xq]
+    num = Decimal(0)
+    den = Decimal(0)
+    for i in range(len(X)):
+        k = gauss_kernel([a - b for a, b in zip(XQ, X[i])], HX)
+        num += k * Y[i]
+        den += k
+    return float(num / den)

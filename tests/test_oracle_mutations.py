@@ -77,6 +77,44 @@ def battery_epan(lib) -> list:
     return failed
 
 
+# Mistakes planted in the query-side products.
+PRODUCT_MUTATIONS = {
+    "mean_unweighted": ("S += w * y[(size_t)i * dy + l];", "S += y[(size_t)i * dy + l];"),
+    "summary_left_rule": ("c += (r[g] + r[g + 1]) * 0.5 * (yg[g + 1] - yg[g]);",
+                          "c += r[g] * (yg[g + 1] - yg[g]);"),
+    "summary_mode_last_max": ("if (r[g] > r[imax]) imax = g;", "if (r[g] >= r[imax]) imax = g;"),
+    "summary_wrong_coverage": ("const double p = G[g] + cover;", "const double p = G[g] + alpha;"),
+}
+
+
+def battery_products(lib) -> list:
+    """Independent checks of the conditional mean and the density summary."""
+    from scipy.stats import norm as _norm
+    failed = []
+    rng = np.random.default_rng(12)
+    x = rng.normal(size=(8, 2))
+    y = rng.normal(size=(8, 1))
+    xq = rng.normal(size=(2, 2))
+    got = oracle.cond_mean(x, y, [0.8, 1.2, 0.5], xq, lib=lib)[:, 0]
+    ref = [brute.cond_mean(x, y, [0.8, 1.2], q) for q in xq]
+    if not np.allclose(got, ref, rtol=1e-12, atol=1e-13):
+        failed.append("mean_brute")
+    yg = np.linspace(-8, 10, 9001)
+    out = oracle.density_summary(_norm.pdf(yg, 1.0, 1.5)[None], yg, 0.05, lib=lib)[0]
+    z = _norm.ppf(0.975)
+    if abs(out[0] - 1.0) > 1e-6 or abs(out[2] - (1 - z * 1.5)) > 0.01 or abs(out[3] - (1 + z * 1.5)) > 0.01:
+        failed.append("summary_gaussian")
+    yu = np.linspace(0.0, 1.0, 101)
+    out = oracle.density_summary(np.ones((1, 101)), yu, 0.1, lib=lib)[0]
+    if out[1] != 0.0:
+        failed.append("summary_uniform_mode")
+    yl = np.linspace(0.0, 1.0, 11)  # f(y) = y: the trapezoid rule is exact, mass 1/2
+    out = oracle.density_summary(yl[None], yl, 0.1, lib=lib)[0]
+    if abs(out[0] - 0.5) > 1e-14:
+        failed.append("summary_linear_mass")
+    return failed
+
+
 def battery(lib) -> list:
     """Independent checks; returns the names of those that fail."""
     failed = []
@@ -153,3 +191,19 @@ def test_planted_epan_mistake_is_caught(name, tmp_path):
     so = oracle.build(str(mutated), str(tmp_path / "libmut.so"))
     lib = oracle.load_library(so)
     assert battery_epan(lib), f"mutation {name} was not detected by any pin"
+
+
+def test_unmutated_oracle_passes_products_battery():
+    assert battery_products(None) == []
+
+
+@pytest.mark.parametrize("name", sorted(PRODUCT_MUTATIONS))
+def test_planted_product_mistake_is_caught(name, tmp_path):
+    old, new = PRODUCT_MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not unique: {old!r}"
+    mutated = tmp_path / "mut.c"
+    mutated.write_text(src.replace(old, new))
+    so = oracle.build(str(mutated), str(tmp_path / "libmut.so"))
+    lib = oracle.load_library(so)
+    assert battery_products(lib), f"mutation {name} was not detected by any pin"
