@@ -164,6 +164,32 @@ cde_status cde_loo_grad(cde_model* m, const double* h, cde_criterion criterion,
 cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const void* ygrid_dev,
                              int64_t k, const double* h, double* f_dev, void* stream);
 
+/* Conditional mean E[y | x_q] = sum_i K_hx(x_q - x_i) y_i / sum_i K_hx(x_q - x_i),
+ * the mean of eq. (1)'s density (each y-kernel component has mean y_i): the
+ * prediction of y by the expectation of f(y|x) in Section 4.2.  Gaussian
+ * kernel, FP64 arithmetic.
+ *   xq_dev: [q][dx] device memory of the model's precision type.  h: host
+ *   [dx+dy] (the y bandwidths do not enter the mean).  mean_dev: [q][dy]
+ *   doubles.  */
+cde_status cde_conditional_mean(cde_model* m, const void* xq_dev, int64_t q, const double* h,
+                                double* mean_dev, void* stream);
+
+/* Summaries of conditional densities on a y grid (dy = 1): the mode and the
+ * narrowest prediction interval of Section 4 (there: the narrowest set of
+ * quantiles with coverage 1 - alpha, found from a sample; here, deterministic
+ * on the grid).  For each row of f_dev [q][k] (e.g. from cde_density_query on
+ * the increasing grid ygrid_dev [k], doubles), out_dev[row] = {mass, mode, lo,
+ * hi}: mass = trapezoid integral of the row; mode = the first grid point of
+ * maximal f; [lo, hi] = the narrowest interval holding 1 - alpha of the
+ * grid's CDF G (trapezoid partial sums over mass, linear between grid
+ * points), over the intervals with one end on a grid point (lower ends
+ * first, then upper ends), the first of least width (a later one replaces it
+ * only when narrower by more than 1e-12 of the grid's span).  A row of zero
+ * mass gives lo = hi = NaN.  No model is needed.
+ *   Limits: q >= 0, 2 <= k <= 4096, 0 < alpha < 1.  */
+cde_status cde_density_summary(const double* f_dev, const double* ygrid_dev, int64_t q, int64_t k,
+                               double alpha, double* out_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -499,4 +499,45 @@ cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const 
     }
 }
 
+cde_status cde_conditional_mean(cde_model* m, const void* xq_dev, int64_t q, const double* h,
+                                double* mean_dev, void* stream)
+{
+    try {
+        if (!m) return fail(CDE_EINVAL, "cde_conditional_mean: model is NULL");
+        if (q < 0) return fail(CDE_EINVAL, "cde_conditional_mean: q must be >= 0");
+        if (q > 0 && (!xq_dev || !mean_dev)) return fail(CDE_EINVAL, "cde_conditional_mean: NULL device pointer");
+        if (!valid_bandwidths(h, m->dx + m->dy))
+            return fail(CDE_EINVAL, "cde_conditional_mean: bandwidths must be finite and > 0");
+        if (q == 0) return CDE_OK;
+        if (q >= (int64_t(1) << 40)) return fail(CDE_EUNSUPPORTED, "cde_conditional_mean: q too large");
+        DeviceGuard guard(m->device);
+        hipStream_t s = (hipStream_t)stream;
+        cde_status st = ensure_scratch(m, sizeof(double) * cond_mean_work_doubles(m, q) + 256);
+        if (st != CDE_OK) return st;
+        hipError_t e = launch_cond_mean(m, xq_dev, q, h, mean_dev, (double*)m->scratch, s);
+        if (e != hipSuccess) return hip_fail(e, "launch conditional mean");
+        return CDE_OK;
+    } catch (...) {
+        return fail(CDE_EDEVICE, "cde_conditional_mean: unexpected exception");
+    }
+}
+
+cde_status cde_density_summary(const double* f_dev, const double* ygrid_dev, int64_t q, int64_t k,
+                               double alpha, double* out_dev, void* stream)
+{
+    try {
+        if (q < 0 || k < 2 || k > 4096) return fail(CDE_EINVAL, "cde_density_summary: need q >= 0, 2 <= k <= 4096");
+        if (!(alpha > 0.0) || !(alpha < 1.0)) return fail(CDE_EINVAL, "cde_density_summary: alpha must be in (0, 1)");
+        if (q > 0 && (!f_dev || !ygrid_dev || !out_dev))
+            return fail(CDE_EINVAL, "cde_density_summary: NULL device pointer");
+        if (q == 0) return CDE_OK;
+        if (q >= (int64_t(1) << 31)) return fail(CDE_EUNSUPPORTED, "cde_density_summary: q >= 2^31");
+        hipError_t e = launch_density_summary(f_dev, ygrid_dev, q, k, alpha, out_dev, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "launch density summary");
+        return CDE_OK;
+    } catch (...) {
+        return fail(CDE_EDEVICE, "cde_density_summary: unexpected exception");
+    }
+}
+
 }  // extern "C"

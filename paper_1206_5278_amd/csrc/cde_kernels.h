@@ -43,6 +43,16 @@ hipError_t launch_epan(const cde_model* m, const EpanSets& sets, int nsets, int 
                        double* partial, double* per_point, double* part, hipStream_t stream);
 int epan_chunks(const cde_model* m, int nsets, size_t max_doubles);
 
+// Conditional mean E[y | xq] (Gaussian kernel) for q queries of the model's
+// precision: mean [q][dy] doubles; `work` holds cond_mean_work_doubles().
+hipError_t launch_cond_mean(const cde_model* m, const void* xq, int64_t q, const double* h, double* mean,
+                            double* work, hipStream_t stream);
+size_t cond_mean_work_doubles(const cde_model* m, int64_t q);
+// Mass, mode and narrowest 1 - alpha interval of each row of f [q][k] on the
+// increasing grid yg [k]: out [q][4] doubles.
+hipError_t launch_density_summary(const double* f, const double* yg, int64_t q, int64_t k, double alpha,
+                                  double* out, hipStream_t stream);
+
 // Density queries f(yg[g] | xq[q]) over all training points -> f [q][k].
 template <typename T>
 hipError_t launch_query(const cde_model* m, const T* xq, int64_t q, const T* yg, int64_t k,

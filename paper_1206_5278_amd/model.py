@@ -142,6 +142,16 @@ class Model:
         B.check(st, "cde_loo_grad")
         return total, grad, pp
 
+    def conditional_mean(self, xq: torch.Tensor, h, stream=None) -> torch.Tensor:
+        """E[y | xq] (mean of eq. (1)'s density, Gaussian kernel): [q, dy] float64."""
+        xq = xq.reshape(-1, self.dx).to(self.dtype).contiguous()
+        q = int(xq.shape[0])
+        out = torch.empty((q, self.dy), dtype=torch.float64, device=self.device)
+        st = self._lib.cde_conditional_mean(self._h, xq.data_ptr(), q, B.doubles(self._bw(h)),
+                                            out.data_ptr(), _stream_ptr(stream))
+        B.check(st, "cde_conditional_mean")
+        return out
+
     def query(self, xq: torch.Tensor, ygrid: torch.Tensor, h, stream=None, out=None):
         """f(ygrid[g] | xq[q]) of eq. (1) over all training points: [q, k] float64."""
         xq = xq.reshape(-1, self.dx).to(self.dtype).contiguous()
@@ -152,6 +162,21 @@ class Model:
                                          B.doubles(self._bw(h)), f.data_ptr(), _stream_ptr(stream))
         B.check(st, "cde_density_query")
         return f
+
+
+def density_summary(f: torch.Tensor, ygrid, alpha: float = 0.05, stream=None) -> torch.Tensor:
+    """Mass, mode and narrowest 1 - alpha interval of each row of f [q, k]
+    on the increasing grid ygrid [k] (``cde_density_summary``): [q, 4] float64."""
+    f = f.to(torch.float64).contiguous()
+    yg = torch.as_tensor(ygrid, dtype=torch.float64, device=f.device).reshape(-1).contiguous()
+    q, k = int(f.shape[0]), int(f.shape[1])
+    if yg.numel() != k:
+        raise ValueError("ygrid must have one value per column of f")
+    out = torch.empty((q, 4), dtype=torch.float64, device=f.device)
+    st = B.load().cde_density_summary(f.data_ptr(), yg.data_ptr(), q, k, float(alpha), out.data_ptr(),
+                                      _stream_ptr(stream))
+    B.check(st, "cde_density_summary")
+    return out
 
 
 def argmax_first_finite(totals) -> int:
