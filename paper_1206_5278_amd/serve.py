@@ -255,10 +255,12 @@ class GpuExecutor(Executor):
 
         from . import _binding
         from .drivers import normal_reference_bandwidths
-        from .model import Model
+        from .model import Model, density_summary
         self.torch = torch
         self.Model = Model
         self.B = _binding
+        self.density_summary = density_summary
+        self.alpha = 0.05
         self.dev = torch.device("cuda:0")
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_streams)]
         self.rr = 0
@@ -276,7 +278,9 @@ class GpuExecutor(Executor):
             ys = y32[:, 0].astype(np.float64)
             yg = np.linspace(ys.min() - 3 * ys.std(), ys.max() + 3 * ys.std(), grid_points)
             ygd = torch.from_numpy(yg.astype(np.float32).reshape(-1, 1)).to(self.dev)
-            self.sets.append({"model": m, "h": h, "ygrid": ygd, "k": grid_points, "dx": x32.shape[1]})
+            yg64 = torch.from_numpy(yg.astype(np.float32).astype(np.float64)).to(self.dev)
+            self.sets.append({"model": m, "h": h, "ygrid": ygd, "ygrid64": yg64, "k": grid_points,
+                              "dx": x32.shape[1]})
         torch.cuda.synchronize()
 
     def _stream(self):
@@ -287,7 +291,7 @@ class GpuExecutor(Executor):
     def footprint(self, r):
         if r.kind == "query":
             k = self.sets[r.set_id]["k"]
-            return int(r.xq.shape[0]) * (k * 8 + 64) + 4096
+            return int(r.xq.shape[0]) * (k * 8 + 128) + 4096
         n, dx = r.x.shape
         dy = r.y.shape[1] if r.y.ndim > 1 else 1
         return self.B.workspace_bytes(n, dx, dy, self.B.CDE_F32, len(r.hx), len(r.hy)) + (1 << 20)
@@ -300,9 +304,14 @@ class GpuExecutor(Executor):
             xq = np.concatenate([r.xq for r in reqs]).astype(np.float32)
             xqd = torch.from_numpy(xq).to(self.dev, non_blocking=False)
             f = st["model"].query(xqd, st["ygrid"], st["h"], stream=s)
+            # query-side products: E[y|x], mass, mode and the narrowest
+            # (1 - alpha) interval of each row (per-row results, so fusing
+            # requests changes no bit)
+            mean = st["model"].conditional_mean(xqd, st["h"], stream=s)
+            summ = self.density_summary(f, st["ygrid64"], self.alpha, stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
-        return {"ev": ev, "f": f, "reqs": reqs, "keep": xqd}
+        return {"ev": ev, "f": f, "mean": mean, "summary": summ, "reqs": reqs, "keep": xqd}
 
     def launch_job(self, r):
         torch = self.torch
@@ -322,10 +331,12 @@ class GpuExecutor(Executor):
     def finish(self, h):
         if "f" in h:
             f = h["f"].cpu().numpy()
+            mean = h["mean"].cpu().numpy()
+            summ = h["summary"].cpu().numpy()
             o = 0
             for r in h["reqs"]:
                 q = r.xq.shape[0]
-                r.result = f[o:o + q]
+                r.result = {"f": f[o:o + q], "mean": mean[o:o + q], "summary": summ[o:o + q]}
                 o += q
         else:
             r = h["req"]

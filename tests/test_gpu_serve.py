@@ -44,10 +44,11 @@ def test_serve_alone_vs_mixed_identical_and_oracle():
         out[batched] = {r.rid: r.result for r in s.completed}
     for rid in out[False]:
         a, b = out[False][rid], out[True][rid]
-        if isinstance(a, dict):
+        if "totals" in a:
             assert np.array_equal(a["totals"], b["totals"]) and a["argmax"] == b["argmax"]
         else:
-            assert np.array_equal(a, b)
+            for key in ("f", "mean", "summary"):
+                assert np.array_equal(a[key], b[key], equal_nan=True), key
     # spot-check against the oracle: one job (per-setting totals) and one query
     job = next(r for r in reqs if r.kind == "job")
     ref = oracle.totals(oracle.loo_grid(job.x.astype(np.float64), job.y.astype(np.float64),
@@ -62,6 +63,12 @@ def test_serve_alone_vs_mixed_identical_and_oracle():
                            ys.astype(np.float32).astype(np.float64), st["h"],
                            q.xq.astype(np.float64), st["ygrid"].cpu().numpy().astype(np.float64),
                            nthreads=NT)
-    f = out[True][q.rid]
+    f = out[True][q.rid]["f"]
     peak = f_ref.max(axis=1, keepdims=True)
     assert np.all(np.abs(f - f_ref) <= 1e-5 * f_ref + 1e-7 * peak)
+    # the products returned with it
+    xs64, ys64 = xs.astype(np.float32).astype(np.float64), ys.astype(np.float32).astype(np.float64)
+    m_ref = oracle.cond_mean(xs64, ys64, st["h"], q.xq.astype(np.float32).astype(np.float64))
+    assert np.all(np.abs(out[True][q.rid]["mean"] - m_ref) <= 1e-12 * np.abs(ys64).max())
+    s_ref = oracle.density_summary(f, st["ygrid64"].cpu().numpy(), 0.05)
+    assert np.array_equal(out[True][q.rid]["summary"], s_ref, equal_nan=True)
