@@ -15,15 +15,16 @@
 // scaled y-distance of grid point g (FP64 prepasses; exact minima, so the
 // nearest point has w' = 1 and den' >= 1).  Distances and the shifted
 // exponents are formed in FP64 and rounded to FP32 after the subtraction.
-// Kernel values and products are FP32; sums over a 256-point tile are folded
-// into Kahan-compensated FP32 totals.  A value of f more than ~2^-100 below
+// Kernel values and products are FP32 (see k_query_mfma for the sums).  A value of f more than ~2^-100 below
 // its query's peak is not carried to full relative precision (FP32 range);
 // such tail values are far below the accuracy floor of a density estimate.
 //
 // Work decomposition: a 256-lane block owns 64 queries (16 per wave), a chunk
-// of up to 128 grid points (blockIdx.y) and a chunk of training points
-// (blockIdx.z); chunk partial sums (FP64) are combined in a fixed order by
-// k_query_reduce.  The training-point chunks depend on n alone and every
+// of 64, 128 or 256 grid points (blockIdx.y) and a chunk of training points
+// (blockIdx.z).  The y-kernel values of a panel of 32 training points and
+// the block's grid points are formed once per block in LDS and read by all
+// four waves as MFMA B operands; the x-kernel values are formed per wave.
+// Chunk partial sums (FP64) are combined in a fixed order by k_query_reduce.  The training-point chunks depend on n alone and every
 // query row is accumulated on its own, so a query's result does not depend
 // on which other queries share its launch; large batches run in slices of
 // queries that bound the partial storage.
@@ -61,6 +62,43 @@ __global__ void k_fill_inf(double* p, int cnt)
 
 }  // namespace
 
+// Scaled squared distances in FP64 of a query's x (or a grid point's y) to
+// a training row staged as doubles.  The shift prepasses and the main kernel
+// use these same expressions, so the shifted exponent of every live pair is
+// >= 0 exactly.
+template <int DX>
+__device__ __forceinline__ double xdist2(const double (&xo)[DX], const double* pj, const QueryArgs& qa)
+{
+    double d2 = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < DX; ++kk) {
+        const double d = xo[kk] - pj[kk];
+        d2 = fma_(d * d, qa.cx[kk], d2);
+    }
+    return d2;
+}
+
+template <int DX, int DY>
+__device__ __forceinline__ double ydist2(const double (&yo)[DY], const double* pj, const QueryArgs& qa)
+{
+    double e = 0.0;
+#pragma unroll
+    for (int l = 0; l < DY; ++l) {
+        const double d = yo[l] - pj[DX + l];
+        e = fma_(d * d, qa.cy[l], e);
+    }
+    return e;
+}
+
+// One tile of packed FP32 rows staged in LDS as doubles, [TILE][DX + DY]
+// (exact conversions).
+template <int DX, int DY>
+__device__ __forceinline__ void stage_tile_d(double* tile, const float* pre, int tid)
+{
+#pragma unroll
+    for (int d = 0; d < DX + DY; ++d) tile[tid * (DX + DY) + d] = (double)pre[d];
+}
+
 // m_q = min_i sum_k c_k (x_qk - x_ik)^2 (FP64): lane = query, blockIdx.y =
 // range of training points.
 template <int DX, int DY>
@@ -68,8 +106,8 @@ __global__ __launch_bounds__(TILE) void k_qshift_x(const float* __restrict__ pts
                                                    const float* __restrict__ xq, int q,
                                                    QueryArgs qa, double* __restrict__ mq)
 {
-    constexpr int S = row_stride(DX, DY);
-    __shared__ float tile[TILE * S];
+    constexpr int S = row_stride(DX, DY), SD = DX + DY;
+    __shared__ double tile[TILE * SD];
     const int tid = threadIdx.x;
     const int e = blockIdx.x * TILE + tid;
     const int ec = e < q ? e : q - 1;
@@ -82,20 +120,10 @@ __global__ __launch_bounds__(TILE) void k_qshift_x(const float* __restrict__ pts
         __syncthreads();
         float pre[S];
         load_row<S>(pre, pts + ((size_t)t0 + tid) * S);
-        store_row<S>(tile + tid * S, pre);
+        stage_tile_d<DX, DY>(tile, pre, tid);
         __syncthreads();
         const int cnt = min(TILE, j1 - t0);
-        for (int j = 0; j < cnt; ++j) {
-            float pj[S];
-            load_row<S>(pj, tile + j * S);
-            double d2 = 0.0;
-#pragma unroll
-            for (int k = 0; k < DX; ++k) {
-                const double d = xo[k] - (double)pj[k];
-                d2 = fma_(d * d, qa.cx[k], d2);
-            }
-            best = min_(best, d2);
-        }
+        for (int j = 0; j < cnt; ++j) best = min_(best, xdist2<DX>(xo, tile + j * SD, qa));
     }
     if (e < q) atomic_min_nonneg(mq + e, best);
 }
@@ -106,8 +134,8 @@ __global__ __launch_bounds__(TILE) void k_qshift_y(const float* __restrict__ pts
                                                    const float* __restrict__ yg, int k,
                                                    QueryArgs qa, double* __restrict__ mu)
 {
-    constexpr int S = row_stride(DX, DY);
-    __shared__ float tile[TILE * S];
+    constexpr int S = row_stride(DX, DY), SD = DX + DY;
+    __shared__ double tile[TILE * SD];
     const int tid = threadIdx.x;
     const int e = blockIdx.x * TILE + tid;
     const int ec = e < k ? e : k - 1;
@@ -120,25 +148,26 @@ __global__ __launch_bounds__(TILE) void k_qshift_y(const float* __restrict__ pts
         __syncthreads();
         float pre[S];
         load_row<S>(pre, pts + ((size_t)t0 + tid) * S);
-        store_row<S>(tile + tid * S, pre);
+        stage_tile_d<DX, DY>(tile, pre, tid);
         __syncthreads();
         const int cnt = min(TILE, j1 - t0);
-        for (int j = 0; j < cnt; ++j) {
-            float pj[S];
-            load_row<S>(pj, tile + j * S);
-            double d2 = 0.0;
-#pragma unroll
-            for (int l = 0; l < DY; ++l) {
-                const double d = yo[l] - (double)pj[DX + l];
-                d2 = fma_(d * d, qa.cy[l], d2);
-            }
-            best = min_(best, d2);
-        }
+        for (int j = 0; j < cnt; ++j) best = min_(best, ydist2<DX, DY>(yo, tile + j * SD, qa));
     }
     if (e < k) atomic_min_nonneg(mu + e, best);
 }
 
-template <int DX, int DY>
+// Numerator and denominator partials of one chunk of training points for 64
+// queries (16 per wave) and GW = 16 GT grid points.  The training tile is
+// staged in LDS as doubles; for each panel of 32 of its points the block
+// first writes the y-kernel values k'(i, g) of all GW grid points to LDS
+// (computed once per block, shared by the four waves), then each wave runs
+// 4-point MFMA steps: A = the x-kernel values w'(q, i) of its 16 queries
+// (lane % 16 = query, lane / 16 = point), B = the y-kernel values read from
+// LDS (lane / 16 = point, lane % 16 = grid column).  Each panel's MFMA sums
+// (8 roundings) are added into FP32 chunk sums (at most 64 panels), so a
+// chunk partial carries a relative error of at most about 72 x 2^-24 of its
+// all-positive terms; chunks are combined in FP64.
+template <int DX, int DY, int GT>
 __global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ pts, int n, int chunk,
                                                      const float* __restrict__ xq, int q,
                                                      const float* __restrict__ yg, int k,
@@ -147,93 +176,90 @@ __global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ p
                                                      double* __restrict__ fpart,
                                                      double* __restrict__ dpart)
 {
-    constexpr int S = row_stride(DX, DY);
-    constexpr int GT = 8;  // grid tiles of 16 per block (128 grid points)
-    __shared__ float tile[TILE * S];
+    constexpr int S = row_stride(DX, DY), SD = DX + DY;
+    constexpr int GW = 16 * GT;
+    // LDS row of y-kernel values, padded to 16 (mod 32 and mod 64 in {16, 48}):
+    // the four 16-lane groups of a B read then fall in disjoint banks.
+    constexpr int YS = (GW % 32 == 16) ? GW : GW + 16;
+    constexpr int SUB = 32;
+    constexpr int PSTEP = TILE / GW;  // panel rows filled per pass of the block
+    constexpr int YPT = SUB / PSTEP;  // y-kernel values per thread per panel
+    static_assert(TILE % GW == 0 && SUB % PSTEP == 0, "grid width must divide the tile");
+    __shared__ double tile[TILE * SD];
+    __shared__ float ykv[SUB * YS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q0 = blockIdx.x * 64 + wave * 16;
-    const int g0 = blockIdx.y * 16 * GT;
+    const int g0 = blockIdx.y * GW;
     const int c = blockIdx.z;
-    const int kr = lane >> 4;  // k-row of the MFMA operands: training point i0 + kr
+    const int kr = lane >> 4;
 
-    // A role: query q0 + lane%16
-    const int qa_idx = min(q0 + (lane & 15), q - 1);
+    // A role: query q0 + lane % 16
+    const int qi = min(q0 + (lane & 15), q - 1);
     double xo[DX];
 #pragma unroll
-    for (int kk = 0; kk < DX; ++kk) xo[kk] = (double)xq[(size_t)qa_idx * DX + kk];
-    const double m_q = mq[qa_idx];
-    // B role: grid points g0 + 16 t + lane%16, t < GT
-    double yo[GT][DY];
-    double mu_g[GT];
+    for (int kk = 0; kk < DX; ++kk) xo[kk] = (double)xq[(size_t)qi * DX + kk];
+    const double m_q = mq[qi];
+    // y-kernel role: grid column tid % GW, panel rows tid / GW + PSTEP r
+    const int gcol = tid % GW;
+    const int gy = min(g0 + gcol, k - 1);
+    double yo[DY];
 #pragma unroll
-    for (int t = 0; t < GT; ++t) {
-        const int g = min(g0 + 16 * t + (lane & 15), k - 1);
-#pragma unroll
-        for (int l = 0; l < DY; ++l) yo[t][l] = (double)yg[(size_t)g * DY + l];
-        mu_g[t] = mu[g];
-    }
-    const int ntg = min(GT, (k - g0 + 15) / 16);  // grid tiles present in this chunk
+    for (int l = 0; l < DY; ++l) yo[l] = (double)yg[(size_t)gy * DY + l];
+    const double mu_g = mu[gy];
+    const int prow = tid / GW;
 
-    v4f acc[GT];
-    Kahan<float> tot[GT][4];
+    // Panel sums (MFMA, 32 points) are added into FP32 chunk sums; a chunk
+    // holds at most 8 tiles (64 panels).
+    float tot[GT][4];
 #pragma unroll
-    for (int t = 0; t < GT; ++t) {
-        acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < GT; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) tot[t][r].zero();
-    }
-    float dp = 0.f;
-    Kahan<float> dtot;
-    dtot.zero();
+        for (int r = 0; r < 4; ++r) tot[t][r] = 0.f;
+    double dtot = 0.0;
 
     const int j0 = c * chunk, j1 = min(n, j0 + chunk);
     float pre[S];
     load_row<S>(pre, pts + ((size_t)j0 + tid) * S);
     for (int t0 = j0; t0 < j1; t0 += TILE) {
         __syncthreads();
-        store_row<S>(tile + tid * S, pre);
-        __syncthreads();
+        stage_tile_d<DX, DY>(tile, pre, tid);
         if (t0 + TILE < j1) load_row<S>(pre, pts + ((size_t)t0 + TILE + tid) * S);
         const int cnt = min(TILE, j1 - t0);
-        for (int i4 = 0; i4 < cnt; i4 += 4) {
-            const int ii = i4 + kr;
-            float pj[S];
-            load_row<S>(pj, tile + ii * S);  // rows >= cnt are packed rows (in bounds)
-            const bool live = ii < cnt;
-            double d2 = 0.0;
+        float dp = 0.f;
+        for (int s0 = 0; s0 < cnt; s0 += SUB) {
+            __syncthreads();  // tile staged / previous panel read by every wave
+            // Rows past cnt (padding or the next chunk's points) get finite
+            // values <= 1 from the clamp; their x-kernel values are 0.
 #pragma unroll
-            for (int kk = 0; kk < DX; ++kk) {
-                const double d = xo[kk] - (double)pj[kk];
-                d2 = fma_(d * d, qa.cx[kk], d2);
+            for (int r = 0; r < YPT; ++r) {
+                const int p = prow + PSTEP * r;
+                const float a = (float)(ydist2<DX, DY>(yo, tile + (s0 + p) * SD, qa) - mu_g);
+                ykv[p * YS + gcol] = exp2_<float>(-fmaxf(a, 0.f));
             }
-            const float xa = live ? (float)(d2 - m_q) : QEXCLUDED;
-            const float w = exp2_<float>(-xa);
-            dp += w;
+            __syncthreads();
+            v4f acc[GT];
 #pragma unroll
-            for (int t = 0; t < GT; ++t) {
-                if (t < ntg) {
-                    double e = 0.0;
+            for (int s = 0; s < SUB; s += 4) {
+                const int ii = s0 + s + kr;
+                const double d2 = xdist2<DX>(xo, tile + ii * SD, qa);
+                const float xa = ii < cnt ? (float)(d2 - m_q) : QEXCLUDED;
+                const float w = exp2_<float>(-xa);
+                dp += w;
+                const float* brow = ykv + (s + kr) * YS + (lane & 15);
 #pragma unroll
-                    for (int l = 0; l < DY; ++l) {
-                        const double d = yo[t][l] - (double)pj[DX + l];
-                        e = fma_(d * d, qa.cy[l], e);
-                    }
-                    const float ya = live ? (float)(e - mu_g[t]) : QEXCLUDED;
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, exp2_<float>(-ya), acc[t], 0, 0, 0);
-                }
+                for (int t = 0; t < GT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                        w, brow[16 * t], s == 0 ? v4f{0.f, 0.f, 0.f, 0.f} : acc[t], 0, 0, 0);
             }
-        }
 #pragma unroll
-        for (int t = 0; t < GT; ++t) {
+            for (int t = 0; t < GT; ++t)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) tot[t][r].add(acc[t][r]);
-            acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+                for (int r = 0; r < 4; ++r) tot[t][r] += acc[t][r];
         }
-        dtot.add(dp);
-        dp = 0.f;
+        dtot += (double)dp;
     }
     // den' partial of query q0 + lane%16: the four k-rows in a fixed order
-    double dsum = dtot.value();
+    double dsum = dtot;
     dsum += __shfl_xor(dsum, 16, 64);
     dsum += __shfl_xor(dsum, 32, 64);
     if (blockIdx.y == 0 && lane < 16 && q0 + lane < q) dpart[(size_t)c * q + q0 + lane] = dsum;
@@ -245,7 +271,7 @@ __global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ p
 #pragma unroll
         for (int t = 0; t < GT; ++t) {
             const int g = g0 + 16 * t + (lane & 15);
-            if (t < ntg && qq < q && g < k) fpart[((size_t)c * q + qq) * k + g] = tot[t][r].value();
+            if (qq < q && g < k) fpart[((size_t)c * q + qq) * k + g] = (double)tot[t][r];
         }
     }
 }
@@ -266,12 +292,20 @@ __global__ void k_query_reduce(const double* __restrict__ fpart, const double* _
     f[e] = num > 0.0 ? exp(log_cy - mu[g] * LN2 + log(num / den)) : 0.0;
 }
 
-// Training-point chunks: whole tiles, at most 256 chunks, a function of n
-// only (never of the batch).
+// Training-point chunks: whole tiles, at most 256 chunks while that keeps a
+// chunk within 8 tiles (the FP32 chunk sums above), a function of n only
+// (never of the batch).
 static int64_t query_chunk_points(int64_t n)
 {
     const int64_t ntiles = (n + TILE - 1) / TILE;
-    return (ntiles + 255) / 256 * TILE;
+    return std::min<int64_t>(8, (ntiles + 255) / 256) * TILE;
+}
+
+// Grid tiles of 16 points per block: 4, 8 or 16 (a function of k only).
+static int query_grid_tiles(int64_t k)
+{
+    const int64_t nt = (k + 15) / 16;
+    return nt <= 4 ? 4 : nt <= 8 ? 8 : 16;
 }
 
 // Queries per slice: chunk partials of one slice within 2^26 doubles.
@@ -303,7 +337,8 @@ static hipError_t query_t(const cde_model* m, const float* xq, int q, const floa
     qa.log_cy = lcy;
     const int n = (int)m->n;
     const float* pts = (const float*)m->pts;
-    const int gb = (k + 127) / 128;
+    const int gt = query_grid_tiles(k);
+    const int gb = (k + 16 * gt - 1) / (16 * gt);
     const int chunk = (int)query_chunk_points(n);
     const int nch = (n + chunk - 1) / chunk;
     const int qs = (int)query_slice(nch, q, k);
@@ -325,9 +360,18 @@ static hipError_t query_t(const cde_model* m, const float* xq, int q, const floa
     for (int q0 = 0; q0 < q; q0 += qs) {
         const int qn = std::min(qs, q - q0);
         const int qb = (qn + 63) / 64;
-        hipLaunchKernelGGL((k_query_mfma<DX, DY>), dim3(qb, gb, nch), dim3(TILE), 0, stream, pts, n,
-                           chunk, xq + (size_t)q0 * DX, qn, yg, k, qa, (const double*)(mq + q0),
-                           (const double*)mu, fpart, dpart);
+        const dim3 grid(qb, gb, nch);
+        const float* xs = xq + (size_t)q0 * DX;
+        const double* mqs = mq + q0;
+        if (gt == 4)
+            hipLaunchKernelGGL((k_query_mfma<DX, DY, 4>), grid, dim3(TILE), 0, stream, pts, n, chunk, xs,
+                               qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
+        else if (gt == 8)
+            hipLaunchKernelGGL((k_query_mfma<DX, DY, 8>), grid, dim3(TILE), 0, stream, pts, n, chunk, xs,
+                               qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
+        else
+            hipLaunchKernelGGL((k_query_mfma<DX, DY, 16>), grid, dim3(TILE), 0, stream, pts, n, chunk, xs,
+                               qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int64_t total = (int64_t)qn * k;
         hipLaunchKernelGGL(k_query_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,

@@ -289,6 +289,34 @@ def test_query_rows_independent_of_batch():
     assert np.all(err <= 1e-5 * ref + 1e-7 * peak)
 
 
+def test_query_grid_widths_and_many_chunks():
+    # n = 600,000 needs more than 256 training-point chunks (a chunk holds at
+    # most 8 tiles); k = 40, 100 and 700 use blocks of 64, 128 and 256 grid
+    # points (the last with a ragged third block); one query lies far from
+    # every training point (a large shift m_q).
+    say("case: query n=600000, k in (40, 100, 700)")
+    x, y = workloads.gmm(600_000, seed=17, dx=2)
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    h = [0.25, 0.3, 0.2]
+    rng = np.random.default_rng(9)
+    xq = (xo[rng.choice(600_000, 69)] + 0.05 * rng.normal(size=(69, 2))).astype(np.float32)
+    xq[68] = xo.max(axis=0) + 3.0
+    xq_d = P.to_dev(xq, torch.float32)
+    rows = [0, 33, 67, 68]
+    for k in (40, 100, 700):
+        yg = np.linspace(yo.min() - 1, yo.max() + 1, k).astype(np.float32)
+        yg_d = P.to_dev(yg, torch.float32)
+        f = m.query(xq_d, yg_d, h).cpu().numpy()
+        ref = oracle.density(xo, yo, h, xq[rows].astype(np.float64), yg.astype(np.float64),
+                             nthreads=NT)
+        peak = ref.max(axis=1, keepdims=True)
+        err = np.abs(f[rows] - ref)
+        assert np.all(err <= 1e-5 * ref + 1e-7 * peak), (k, float(np.max(err / (1e-5 * ref + 1e-7 * peak))))
+        part = m.query(xq_d[[33, 68]].contiguous(), yg_d, h).cpu().numpy()
+        assert np.array_equal(part, f[[33, 68]]), k
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_workspace_bytes_matches_model(dtype):
     # cde_workspace_bytes predicts what a model holds after one grid call
