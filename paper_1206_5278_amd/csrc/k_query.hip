@@ -13,21 +13,23 @@
 // Shifts: w' = 2^-(d2x(q,i) - m_q), k' = 2^-(d2y(g,i) - mu_g), with m_q the
 // smallest scaled x-distance of query q to the data and mu_g the smallest
 // scaled y-distance of grid point g (FP64 prepasses; exact minima, so the
-// nearest point has w' = 1 and den' >= 1).  Distances and the shifted
-// exponents are formed in FP64 and rounded to FP32 after the subtraction.
-// Kernel values and products are FP32 (see k_query_mfma for the sums).  A value of f more than ~2^-100 below
-// its query's peak is not carried to full relative precision (FP32 range);
-// such tail values are far below the accuracy floor of a density estimate.
+// nearest point has w' = 1 up to one rounding and den' >= 1).  The shifted
+// exponents are formed in FP64 (each sum starts from the negated shift) and
+// rounded once to FP32.  Kernel values and products are FP32 (see
+// k_query_mfma for the sums).  A value of f more than ~2^-100 below its
+// query's peak is not carried to full relative precision (FP32 range); such
+// tail values are far below the accuracy floor of a density estimate.
 //
-// Work decomposition: a 256-lane block owns 64 queries (16 per wave), a chunk
+// Work decomposition: a 512-lane block owns 128 queries (16 per wave), a chunk
 // of 64, 128 or 256 grid points (blockIdx.y) and a chunk of training points
 // (blockIdx.z).  The y-kernel values of a panel of 32 training points and
 // the block's grid points are formed once per block in LDS and read by all
-// four waves as MFMA B operands; the x-kernel values are formed per wave.
-// Chunk partial sums (FP64) are combined in a fixed order by k_query_reduce.  The training-point chunks depend on n alone and every
-// query row is accumulated on its own, so a query's result does not depend
-// on which other queries share its launch; large batches run in slices of
-// queries that bound the partial storage.
+// eight waves as MFMA B operands; the x-kernel values are formed per wave.
+// Chunk partial sums (FP32 numerators, FP64 denominators) are combined in
+// FP64 in a fixed order by k_query_reduce.  The training-point chunks depend
+// on n alone and every query row is accumulated on its own, so a query's
+// result does not depend on which other queries share its launch; large
+// batches run in slices of queries that bound the partial storage.
 #include <type_traits>
 
 #include "cde_device.h"
@@ -63,9 +65,7 @@ __global__ void k_fill_inf(double* p, int cnt)
 }  // namespace
 
 // Scaled squared distances in FP64 of a query's x (or a grid point's y) to
-// a training row staged as doubles.  The shift prepasses and the main kernel
-// use these same expressions, so the shifted exponent of every live pair is
-// >= 0 exactly.
+// a training row staged as doubles (the shift prepasses).
 template <int DX>
 __device__ __forceinline__ double xdist2(const double (&xo)[DX], const double* pj, const QueryArgs& qa)
 {
@@ -82,6 +82,35 @@ template <int DX, int DY>
 __device__ __forceinline__ double ydist2(const double (&yo)[DY], const double* pj, const QueryArgs& qa)
 {
     double e = 0.0;
+#pragma unroll
+    for (int l = 0; l < DY; ++l) {
+        const double d = yo[l] - pj[DX + l];
+        e = fma_(d * d, qa.cy[l], e);
+    }
+    return e;
+}
+
+// The same sums started from -shift: the shifted exponents of the main
+// kernel (one rounding fewer than subtracting afterwards; a live pair's
+// exponent can then fall a few ulps below 0, which the kernel tolerates).
+template <int DX>
+__device__ __forceinline__ double xdist2_shifted(const double (&xo)[DX], const double* pj,
+                                                 const QueryArgs& qa, double shift)
+{
+    double d2 = -shift;
+#pragma unroll
+    for (int kk = 0; kk < DX; ++kk) {
+        const double d = xo[kk] - pj[kk];
+        d2 = fma_(d * d, qa.cx[kk], d2);
+    }
+    return d2;
+}
+
+template <int DX, int DY>
+__device__ __forceinline__ double ydist2_shifted(const double (&yo)[DY], const double* pj,
+                                                 const QueryArgs& qa, double shift)
+{
+    double e = -shift;
 #pragma unroll
     for (int l = 0; l < DY; ++l) {
         const double d = yo[l] - pj[DX + l];
@@ -156,24 +185,28 @@ __global__ __launch_bounds__(TILE) void k_qshift_y(const float* __restrict__ pts
     if (e < k) atomic_min_nonneg(mu + e, best);
 }
 
-// Numerator and denominator partials of one chunk of training points for 64
-// queries (16 per wave) and GW = 16 GT grid points.  The training tile is
-// staged in LDS as doubles; for each panel of 32 of its points the block
+// Numerator and denominator partials of one chunk of training points for
+// 128 queries (8 waves of 16) and GW = 16 GT grid points.  The training tile
+// is staged in LDS as doubles; for each panel of 32 of its points the block
 // first writes the y-kernel values k'(i, g) of all GW grid points to LDS
-// (computed once per block, shared by the four waves), then each wave runs
+// (computed once per block, shared by the eight waves), then each wave runs
 // 4-point MFMA steps: A = the x-kernel values w'(q, i) of its 16 queries
 // (lane % 16 = query, lane / 16 = point), B = the y-kernel values read from
 // LDS (lane / 16 = point, lane % 16 = grid column).  Each panel's MFMA sums
 // (8 roundings) are added into FP32 chunk sums (at most 64 panels), so a
 // chunk partial carries a relative error of at most about 72 x 2^-24 of its
 // all-positive terms; chunks are combined in FP64.
+constexpr int QWAVES = 8;            // waves per query block
+constexpr int QNT = 64 * QWAVES;     // threads per query block
+constexpr int QPB = 16 * QWAVES;     // queries per query block
+
 template <int DX, int DY, int GT>
-__global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ pts, int n, int chunk,
+__global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pts, int n, int chunk,
                                                      const float* __restrict__ xq, int q,
                                                      const float* __restrict__ yg, int k,
                                                      QueryArgs qa, const double* __restrict__ mq,
                                                      const double* __restrict__ mu,
-                                                     double* __restrict__ fpart,
+                                                     float* __restrict__ fpart,
                                                      double* __restrict__ dpart)
 {
     constexpr int S = row_stride(DX, DY), SD = DX + DY;
@@ -182,13 +215,13 @@ __global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ p
     // the four 16-lane groups of a B read then fall in disjoint banks.
     constexpr int YS = (GW % 32 == 16) ? GW : GW + 16;
     constexpr int SUB = 32;
-    constexpr int PSTEP = TILE / GW;  // panel rows filled per pass of the block
+    constexpr int PSTEP = QNT / GW;   // panel rows filled per pass of the block
     constexpr int YPT = SUB / PSTEP;  // y-kernel values per thread per panel
-    static_assert(TILE % GW == 0 && SUB % PSTEP == 0, "grid width must divide the tile");
+    static_assert(QNT % GW == 0 && SUB % PSTEP == 0, "grid width must divide the block");
     __shared__ double tile[TILE * SD];
     __shared__ float ykv[SUB * YS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int q0 = blockIdx.x * 64 + wave * 16;
+    const int q0 = blockIdx.x * QPB + wave * 16;
     const int g0 = blockIdx.y * GW;
     const int c = blockIdx.z;
     const int kr = lane >> 4;
@@ -218,12 +251,15 @@ __global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ p
     double dtot = 0.0;
 
     const int j0 = c * chunk, j1 = min(n, j0 + chunk);
+    const bool stager = tid < TILE;  // the first TILE threads stage the rows
     float pre[S];
-    load_row<S>(pre, pts + ((size_t)j0 + tid) * S);
+    if (stager) load_row<S>(pre, pts + ((size_t)j0 + tid) * S);
     for (int t0 = j0; t0 < j1; t0 += TILE) {
         __syncthreads();
-        stage_tile_d<DX, DY>(tile, pre, tid);
-        if (t0 + TILE < j1) load_row<S>(pre, pts + ((size_t)t0 + TILE + tid) * S);
+        if (stager) {
+            stage_tile_d<DX, DY>(tile, pre, tid);
+            if (t0 + TILE < j1) load_row<S>(pre, pts + ((size_t)t0 + TILE + tid) * S);
+        }
         const int cnt = min(TILE, j1 - t0);
         float dp = 0.f;
         for (int s0 = 0; s0 < cnt; s0 += SUB) {
@@ -233,7 +269,7 @@ __global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ p
 #pragma unroll
             for (int r = 0; r < YPT; ++r) {
                 const int p = prow + PSTEP * r;
-                const float a = (float)(ydist2<DX, DY>(yo, tile + (s0 + p) * SD, qa) - mu_g);
+                const float a = (float)ydist2_shifted<DX, DY>(yo, tile + (s0 + p) * SD, qa, mu_g);
                 ykv[p * YS + gcol] = exp2_<float>(-fmaxf(a, 0.f));
             }
             __syncthreads();
@@ -241,8 +277,8 @@ __global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ p
 #pragma unroll
             for (int s = 0; s < SUB; s += 4) {
                 const int ii = s0 + s + kr;
-                const double d2 = xdist2<DX>(xo, tile + ii * SD, qa);
-                const float xa = ii < cnt ? (float)(d2 - m_q) : QEXCLUDED;
+                const double d2 = xdist2_shifted<DX>(xo, tile + ii * SD, qa, m_q);
+                const float xa = ii < cnt ? (float)d2 : QEXCLUDED;
                 const float w = exp2_<float>(-xa);
                 dp += w;
                 const float* brow = ykv + (s + kr) * YS + (lane & 15);
@@ -271,13 +307,13 @@ __global__ __launch_bounds__(TILE) void k_query_mfma(const float* __restrict__ p
 #pragma unroll
         for (int t = 0; t < GT; ++t) {
             const int g = g0 + 16 * t + (lane & 15);
-            if (qq < q && g < k) fpart[((size_t)c * q + qq) * k + g] = (double)tot[t][r];
+            if (qq < q && g < k) fpart[((size_t)c * q + qq) * k + g] = tot[t][r];
         }
     }
 }
 
 // f = c_y 2^-mu_g F'/D' with F' and D' summed over the point chunks in order.
-__global__ void k_query_reduce(const double* __restrict__ fpart, const double* __restrict__ dpart,
+__global__ void k_query_reduce(const float* __restrict__ fpart, const double* __restrict__ dpart,
                                const double* __restrict__ mu, int q, int k, int nchunks,
                                double log_cy, double* __restrict__ f)
 {
@@ -286,7 +322,7 @@ __global__ void k_query_reduce(const double* __restrict__ fpart, const double* _
     const int qq = (int)(e / k), g = (int)(e - (int64_t)qq * k);
     double num = 0.0, den = 0.0;
     for (int c = 0; c < nchunks; ++c) {
-        num += fpart[((size_t)c * q + qq) * k + g];
+        num += (double)fpart[((size_t)c * q + qq) * k + g];
         den += dpart[(size_t)c * q + qq];
     }
     f[e] = num > 0.0 ? exp(log_cy - mu[g] * LN2 + log(num / den)) : 0.0;
@@ -308,11 +344,12 @@ static int query_grid_tiles(int64_t k)
     return nt <= 4 ? 4 : nt <= 8 ? 8 : 16;
 }
 
-// Queries per slice: chunk partials of one slice within 2^26 doubles.
+// Queries per slice: chunk partials of one slice (k FP32 numerators and one
+// FP64 denominator per query and chunk) within 512 MiB.
 static int64_t query_slice(int64_t nch, int64_t q, int64_t k)
 {
-    int64_t s = ((int64_t(1) << 26) / (nch * (k + 1))) / 64 * 64;
-    return std::min(q, std::max<int64_t>(64, s));
+    int64_t s = ((int64_t(1) << 29) / (nch * (4 * k + 8))) / QPB * QPB;
+    return std::min(q, std::max<int64_t>(QPB, s));
 }
 
 size_t query_work_doubles(const cde_model* m, int64_t q, int64_t k)
@@ -320,7 +357,7 @@ size_t query_work_doubles(const cde_model* m, int64_t q, int64_t k)
     const int64_t chunk = query_chunk_points(m->n);
     const int64_t nch = (m->n + chunk - 1) / chunk;
     const int64_t qs = query_slice(nch, q, k);
-    return (size_t)(q + k + nch * qs * (k + 1) + 64);
+    return (size_t)(q + k + nch * qs + (nch * qs * k + 1) / 2 + 64);
 }
 
 template <int DX, int DY>
@@ -345,7 +382,7 @@ static hipError_t query_t(const cde_model* m, const float* xq, int q, const floa
     double* mq = work;
     double* mu = work + q;
     double* dpart = mu + k;
-    double* fpart = dpart + (size_t)nch * qs;
+    float* fpart = (float*)(dpart + (size_t)nch * qs);
     // shifts: exact minima over point chunks
     const int sch = 16 * TILE;
     const int nsch = (n + sch - 1) / sch;
@@ -359,23 +396,23 @@ static hipError_t query_t(const cde_model* m, const float* xq, int q, const floa
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int q0 = 0; q0 < q; q0 += qs) {
         const int qn = std::min(qs, q - q0);
-        const int qb = (qn + 63) / 64;
+        const int qb = (qn + QPB - 1) / QPB;
         const dim3 grid(qb, gb, nch);
         const float* xs = xq + (size_t)q0 * DX;
         const double* mqs = mq + q0;
         if (gt == 4)
-            hipLaunchKernelGGL((k_query_mfma<DX, DY, 4>), grid, dim3(TILE), 0, stream, pts, n, chunk, xs,
+            hipLaunchKernelGGL((k_query_mfma<DX, DY, 4>), grid, dim3(QNT), 0, stream, pts, n, chunk, xs,
                                qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
         else if (gt == 8)
-            hipLaunchKernelGGL((k_query_mfma<DX, DY, 8>), grid, dim3(TILE), 0, stream, pts, n, chunk, xs,
+            hipLaunchKernelGGL((k_query_mfma<DX, DY, 8>), grid, dim3(QNT), 0, stream, pts, n, chunk, xs,
                                qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
         else
-            hipLaunchKernelGGL((k_query_mfma<DX, DY, 16>), grid, dim3(TILE), 0, stream, pts, n, chunk, xs,
+            hipLaunchKernelGGL((k_query_mfma<DX, DY, 16>), grid, dim3(QNT), 0, stream, pts, n, chunk, xs,
                                qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int64_t total = (int64_t)qn * k;
         hipLaunchKernelGGL(k_query_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
-                           (const double*)fpart, (const double*)dpart, (const double*)mu, qn, k, nch,
+                           (const float*)fpart, (const double*)dpart, (const double*)mu, qn, k, nch,
                            lcy, f + (size_t)q0 * k);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
