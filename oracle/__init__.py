@@ -11,7 +11,8 @@ blocking or factorisation); this module only marshals numpy arrays.
 Definitions followed (Holmes, Gray & Isbell): Section 2 (scaled kernel,
 eq. 1), Section 3 eq. (3) and the A_i expansion of Section 3.2; the Gaussian
 kernel, and the Epanechnikov kernel of Section 4 (``loo_epan``,
-``density_epan``).
+``density_epan``); the cross-validated ISE of Section 3, eq. (2)
+(``cv_ise``).
 """
 from __future__ import annotations
 
@@ -71,6 +72,9 @@ def load_library(path: str):
     lib.oracle_cond_mean.restype = ctypes.c_int
     lib.oracle_density_summary.argtypes = [dp, dp, ctypes.c_long, ctypes.c_long, ctypes.c_double, dp]
     lib.oracle_density_summary.restype = ctypes.c_int
+    lib.oracle_cv_ise.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, dp, lp,
+                                  ctypes.c_long, dp, dp, ctypes.c_int]
+    lib.oracle_cv_ise.restype = ctypes.c_int
     return lib
 
 
@@ -247,3 +251,29 @@ def density_summary(f, yg, alpha=0.05, lib=None):
     if s:
         raise ValueError(f"oracle_density_summary failed with status {s}")
     return out
+
+
+def cv_ise(x, y, h, idx=None, nthreads=1, lib=None):
+    """Per-point terms of the cross-validated ISE (Section 3, eq. 2; Gaussian
+    kernels): returns (t1, t2) with t1[t] = integral of f^{-i}(y|x_i)^2 dy and
+    t2[t] = f^{-i}(y_i|x_i) for i = idx[t] (all points when idx is None)."""
+    lib = _load(lib)
+    x, y = _f64(x), _f64(y)
+    n, dx = x.shape
+    dy = y.shape[1]
+    h = _bw(h, dx, dy)
+    idx, m = _idx(idx, n)
+    t1, t2 = np.empty(m), np.empty(m)
+    s = lib.oracle_cv_ise(_ptr(x), _ptr(y), n, dx, dy, _ptr(h),
+                          None if idx is None else _ptr(idx, ctypes.c_long), m, _ptr(t1), _ptr(t2),
+                          int(nthreads))
+    if s:
+        raise ValueError(f"oracle_cv_ise failed with status {s}")
+    return t1, t2
+
+
+def ise_total(t1, t2):
+    """ISE = (1/n) sum_i T1_i - (2/n) sum_i T2_i over all n points (index-order
+    compensated sums)."""
+    n = len(t1)
+    return total(t1) / n - 2.0 * total(t2) / n

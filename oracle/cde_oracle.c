@@ -72,6 +72,19 @@
  *     only when narrower by more than 1e-12 of the grid's span, so ties do
  *     not depend on rounding).
  *
+ * Cross-validated integrated squared error (Section 3, eq. (2) and the
+ * cross-validated estimate that follows it, taken from Fan & Yim), Gaussian
+ * product kernels: per point i
+ *   T1_i = integral over y of f^{-i}(y|x_i)^2
+ *        = sum_{j!=i} sum_{l!=i} w_j w_l G(y_j - y_l) / (sum_{j!=i} w_j)^2,
+ *   T2_i = f^{-i}(y_i|x_i),
+ * with w_j the x-kernel weights of eq. (1) and G the integral of the product
+ * of two y-kernels centred at y_j and y_l, i.e. the Gaussian of standard
+ * deviation sqrt(2) hy_l in each dimension:
+ *   G(t) = prod_l exp(-(t_l / hy_l)^2 / 4) / (2 sqrt(pi) hy_l).
+ * The estimate is ISE = (1/n) sum_i T1_i - (2/n) sum_i T2_i.  The double sum
+ * over (j, l) makes the cost O(n^2) per point, O(n^3) in all.
+ *
  * Threads: points i are split into contiguous ranges, one per thread; each
  * l_i is computed by exactly the same code whatever the split, so results are
  * bitwise independent of the thread count.  Totals are formed by the caller
@@ -273,7 +286,7 @@ static int check_args(const double* x, const double* y, long n, int dx, int dy,
     return 0;
 }
 
-static int run_jobs(loo_job* base, long m, int nthreads)
+static int run_jobs_with(loo_job* base, long m, int nthreads, void* (*worker)(void*))
 {
     if (nthreads < 1) nthreads = 1;
     if (nthreads > m) nthreads = (int)(m > 0 ? m : 1);
@@ -292,10 +305,10 @@ static int run_jobs(loo_job* base, long m, int nthreads)
     }
     int status = 0;
     if (nthreads == 1) {
-        loo_worker(&jobs[0]);
+        worker(&jobs[0]);
         status = jobs[0].status;
     } else {
-        for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, loo_worker, &jobs[t]);
+        for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, worker, &jobs[t]);
         for (int t = 0; t < nthreads; ++t) {
             pthread_join(th[t], NULL);
             if (jobs[t].status) status = jobs[t].status;
@@ -304,6 +317,114 @@ static int run_jobs(loo_job* base, long m, int nthreads)
     free(jobs);
     free(th);
     return status;
+}
+
+static int run_jobs(loo_job* base, long m, int nthreads)
+{
+    return run_jobs_with(base, m, nthreads, loo_worker);
+}
+
+/* One point i of the cross-validated ISE: *t1 = T1_i, *t2 = T2_i (see the
+ * file header).  w[] is scratch of n doubles. */
+static void ise_point(const loo_job* J, long i, double* w, double* t1, double* t2)
+{
+    const long n = J->n;
+    const int dx = J->dx, dy = J->dy;
+    const double* hx = J->h;
+    const double* hy = J->h + dx;
+    const double* xi = J->x + (size_t)i * dx;
+    const double* yi = J->y + (size_t)i * dy;
+    /* x-kernel exponents, shifted by their maximum (cancels in both ratios) */
+    double Mx = -INFINITY;
+    for (long j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const double* xj = J->x + (size_t)j * dx;
+        double sx = 0.0;
+        for (int k = 0; k < dx; ++k) {
+            double t = (xi[k] - xj[k]) / hx[k];
+            sx += t * t;
+        }
+        w[j] = -0.5 * sx;
+        if (w[j] > Mx) Mx = w[j];
+    }
+    double W = 0.0;
+    for (long j = 0; j < n; ++j) {
+        if (j == i) continue;
+        w[j] = exp(w[j] - Mx);
+        W += w[j];
+    }
+    /* T2: the LOO conditional density at the point itself */
+    const double cy = exp(log_norm(hy, dy));
+    double num = 0.0;
+    for (long j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const double* yj = J->y + (size_t)j * dy;
+        double sy = 0.0;
+        for (int l = 0; l < dy; ++l) {
+            double t = (yi[l] - yj[l]) / hy[l];
+            sy += t * t;
+        }
+        num += w[j] * exp(-0.5 * sy);
+    }
+    *t2 = cy * num / W;
+    /* T1: the double sum over j != i and l != i */
+    double cg = 1.0;
+    for (int l = 0; l < dy; ++l) cg /= 2.0 * sqrt(PI) * hy[l];
+    double Q = 0.0;
+    for (long j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const double* yj = J->y + (size_t)j * dy;
+        double inner = 0.0;
+        for (long l = 0; l < n; ++l) {
+            if (l == i) continue;
+            const double* yl = J->y + (size_t)l * dy;
+            double s = 0.0;
+            for (int d = 0; d < dy; ++d) {
+                double t = (yj[d] - yl[d]) / hy[d];
+                s += t * t;
+            }
+            inner += w[l] * exp(-0.25 * s);
+        }
+        Q += w[j] * inner;
+    }
+    *t1 = cg * Q / (W * W);
+}
+
+static void* ise_worker(void* arg)
+{
+    loo_job* J = (loo_job*)arg;
+    double* w = (double*)malloc(sizeof(double) * (size_t)J->n);
+    if (!w) {
+        J->status = 2;
+        return NULL;
+    }
+    for (long t = J->lo; t < J->hi; ++t) {
+        long i = J->idx ? J->idx[t] : t;
+        ise_point(J, i, w, &J->ell[t], &J->dell[t]);
+    }
+    free(w);
+    J->status = 0;
+    return NULL;
+}
+
+/* Per-point terms of the cross-validated ISE for one diagonal setting
+ * h[dx+dy] (Gaussian kernels): t1[t] = T1_i, t2[t] = T2_i for i = idx[t]
+ * (idx == NULL: i = 0..m-1, m == n).  Returns 0 on success, 1 on invalid
+ * arguments, 2 on allocation failure. */
+int oracle_cv_ise(const double* x, const double* y, long n, int dx, int dy,
+                  const double* h, const long* idx, long m, double* t1, double* t2,
+                  int nthreads)
+{
+    if (check_args(x, y, n, dx, dy, h) || !t1 || !t2 || m < 0) return 1;
+    if (!idx && m != n) return 1;
+    if (idx)
+        for (long t = 0; t < m; ++t)
+            if (idx[t] < 0 || idx[t] >= n) return 1;
+    loo_job J;
+    memset(&J, 0, sizeof J);
+    J.x = x; J.y = y; J.n = n; J.dx = dx; J.dy = dy; J.h = h;
+    J.idx = idx; J.m = m; J.ell = t1; J.dell = t2;
+    return run_jobs_with(&J, m, nthreads, ise_worker);
 }
 
 /* Per-point LOO log-likelihood (and optionally its bandwidth gradient) for

@@ -135,3 +135,18 @@ def cond_mean(x, y, hx, xq):
         num += k * Y[i]
         den += k
     return float(num / den)
+
+
+def loo_density_curve(x, y, hx, hy, i, ypts):
+    """f^{-i}(y | x_i) of eq. (1) with point i left out, at each row of ypts
+    [m, dy], in float64 with scipy's normal density (an independent
+    evaluation for quadrature pins)."""
+    import numpy as np
+    from scipy.stats import norm
+    x, y = np.asarray(x, float), np.asarray(y, float)
+    hx, hy = np.asarray(hx, float), np.asarray(hy, float)
+    keep = np.arange(len(x)) != i
+    w = np.prod(norm.pdf((x[i] - x[keep]) / hx) / hx, axis=1)
+    ky = np.prod(norm.pdf((np.asarray(ypts, float)[:, None, :] - y[keep][None, :, :]) / hy) / hy,
+                 axis=2)
+    return ky @ w / w.sum()

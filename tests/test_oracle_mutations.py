@@ -115,6 +115,37 @@ def battery_products(lib) -> list:
     return failed
 
 
+# Mistakes planted in the cross-validated ISE.
+ISE_MUTATIONS = {
+    "ise_convolution_width_h": ("inner += w[l] * exp(-0.25 * s);", "inner += w[l] * exp(-0.5 * s);"),
+    "ise_convolution_norm_sqrt2pi": ("cg /= 2.0 * sqrt(PI) * hy[l];", "cg /= sqrt(2.0 * PI) * hy[l];"),
+    "ise_l_equal_i_kept": ("            if (l == i) continue;\n", ""),
+    "ise_den_not_squared": ("*t1 = cg * Q / (W * W);", "*t1 = cg * Q / W;"),
+    "ise_t2_missing_cy": ("*t2 = cy * num / W;", "*t2 = num / W;"),
+    "ise_pair_uses_point_y": ("double t = (yj[d] - yl[d]) / hy[d];", "double t = (yi[d] - yl[d]) / hy[d];"),
+    "ise_inner_unweighted": ("inner += w[l] * exp(-0.25 * s);", "inner += exp(-0.25 * s);"),
+}
+
+
+def battery_ise(lib) -> list:
+    """Independent checks of the cross-validated ISE terms (quadrature of the
+    squared LOO density, the LOO density at the point)."""
+    failed = []
+    rng = np.random.default_rng(14)
+    x, y = rng.normal(size=(6, 2)), rng.normal(size=(6, 1))
+    hx, hy = np.array([0.9, 0.6]), np.array([0.5])
+    t1, t2 = oracle.cv_ise(x, y, np.concatenate([hx, hy]), lib=lib)
+    for i in range(6):
+        yy = np.linspace(y.min() - 10 * hy[0], y.max() + 10 * hy[0], 20001)
+        f = brute.loo_density_curve(x, y, hx, hy, i, yy[:, None])
+        if not math.isclose(t1[i], np.trapezoid(f * f, yy), rel_tol=1e-8):
+            failed.append(f"t1_quadrature_{i}")
+        if not math.isclose(t2[i], brute.loo_density_curve(x, y, hx, hy, i, y[i:i + 1])[0],
+                            rel_tol=1e-12):
+            failed.append(f"t2_point_{i}")
+    return failed
+
+
 def battery(lib) -> list:
     """Independent checks; returns the names of those that fail."""
     failed = []
@@ -207,3 +238,19 @@ def test_planted_product_mistake_is_caught(name, tmp_path):
     so = oracle.build(str(mutated), str(tmp_path / "libmut.so"))
     lib = oracle.load_library(so)
     assert battery_products(lib), f"mutation {name} was not detected by any pin"
+
+
+def test_unmutated_oracle_passes_ise_battery():
+    assert battery_ise(None) == []
+
+
+@pytest.mark.parametrize("name", sorted(ISE_MUTATIONS))
+def test_planted_ise_mistake_is_caught(name, tmp_path):
+    old, new = ISE_MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not unique: {old!r}"
+    mutated = tmp_path / "mut.c"
+    mutated.write_text(src.replace(old, new))
+    so = oracle.build(str(mutated), str(tmp_path / "libmut.so"))
+    lib = oracle.load_library(so)
+    assert battery_ise(lib), f"mutation {name} was not detected by any pin"
