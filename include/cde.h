@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define CDE_ABI_VERSION 2
+#define CDE_ABI_VERSION 3
 
 typedef struct cde_model cde_model; /* opaque handle */
 
@@ -189,6 +189,18 @@ cde_status cde_conditional_mean(cde_model* m, const void* xq_dev, int64_t q, con
  *   Limits: q >= 0, 2 <= k <= 4096, 0 < alpha < 1.  */
 cde_status cde_density_summary(const double* f_dev, const double* ygrid_dev, int64_t q, int64_t k,
                                double alpha, double* out_dev, void* stream);
+
+/* Cross-validated integrated squared error of Section 3 (eq. (2) and the
+ * cross-validated estimate that follows it), Gaussian product kernels, one
+ * diagonal setting h (host [dx+dy]):
+ *   ISE = (1/n) sum_i T1_i - (2/n) sum_i T2_i,
+ *   T1_i = integral over y of f^{-i}(y|x_i)^2   (a double sum over j, l != i:
+ *          O(n^2) per point, O(n^3) in all, on the matrix cores),
+ *   T2_i = f^{-i}(y_i|x_i)                      (exp of cde_loo_loglik's l_i).
+ *   out_dev: [3] doubles {ISE, (1/n) sum T1, (1/n) sum T2}.
+ *   terms_dev: optional [n][2] doubles {T1_i, T2_i}, or NULL.
+ * FP32 models only (CDE_EUNSUPPORTED otherwise); n <= 262144.  */
+cde_status cde_cv_ise(cde_model* m, const double* h, double* out_dev, double* terms_dev, void* stream);
 
 #ifdef __cplusplus
 }

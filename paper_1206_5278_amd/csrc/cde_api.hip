@@ -464,6 +464,39 @@ cde_status cde_loo_grad(cde_model* m, const double* h, cde_criterion criterion, 
     }
 }
 
+cde_status cde_cv_ise(cde_model* m, const double* h, double* out_dev, double* terms_dev, void* stream)
+{
+    try {
+        if (!m) return fail(CDE_EINVAL, "cde_cv_ise: model is NULL");
+        if (!out_dev) return fail(CDE_EINVAL, "cde_cv_ise: output pointer is NULL");
+        if (!valid_bandwidths(h, m->dx + m->dy))
+            return fail(CDE_EINVAL, "cde_cv_ise: bandwidths must be finite and > 0");
+        if (m->prec != CDE_F32) return fail(CDE_EUNSUPPORTED, "cde_cv_ise: FP32 models only");
+        if (m->n > CDE_ISE_MAX_N) return fail(CDE_EUNSUPPORTED, "cde_cv_ise: n > 262144");
+        DeviceGuard guard(m->device);
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t n = m->n;
+        // scratch: the LOO pass's own scratch, then l_i [n], the LOO total,
+        // the terms (unless the caller takes them) and the ISE work area
+        const size_t diag = round_scratch(diag_list_scratch<float>(m, 1, false, nullptr));
+        const size_t extra = sizeof(double) * ((size_t)n + 8 + (terms_dev ? 0 : 2 * (size_t)n) +
+                                               ise_work_doubles(m)) + 256;
+        cde_status st = ensure_scratch(m, diag + extra);
+        if (st != CDE_OK) return st;
+        double* ell = (double*)((char*)m->scratch + diag);
+        double* loo_total = ell + n;
+        double* terms = terms_dev ? terms_dev : loo_total + 8;
+        double* work = terms_dev ? loo_total + 8 : terms + 2 * n;
+        st = run_diag_list<float>(m, h, 1, CDE_COND, false, loo_total, nullptr, ell, nullptr, s);
+        if (st != CDE_OK) return st;
+        hipError_t e = launch_cv_ise(m, h, ell, out_dev, terms, work, s);
+        if (e != hipSuccess) return hip_fail(e, "launch k_ise");
+        return CDE_OK;
+    } catch (...) {
+        return fail(CDE_EDEVICE, "cde_cv_ise: unexpected exception");
+    }
+}
+
 cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const void* ygrid_dev,
                              int64_t k, const double* h, double* f_dev, void* stream)
 {

@@ -15,6 +15,7 @@ constexpr int MAXP = 18;            // dx + dy for the largest instantiated shap
 constexpr double LOG2E = 1.4426950408889634073599246810019;
 constexpr double LN2 = 0.69314718055994530941723212145818;
 constexpr double HALF_LOG_2PI = 0.91893853320467274178032973640562;
+constexpr int64_t CDE_ISE_MAX_N = 262144;  // largest n of the cross-validated ISE
 
 // Points are stored array-of-structures, x then y then zero padding, with a
 // row stride rounded up to 4 values so that a whole point is one or more

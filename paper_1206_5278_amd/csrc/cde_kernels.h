@@ -64,6 +64,12 @@ hipError_t launch_query_mfma(const cde_model* m, const float* xq, int q, const f
                              const double* h, double* f, double* work, hipStream_t stream);
 size_t query_work_doubles(const cde_model* m, int64_t q, int64_t k);
 
+// Cross-validated ISE (k_ise.hip): FP32 models; ell = the conditional LOO
+// log-likelihood per point; out[3] = {ISE, mean T1, mean T2}; terms [n][2].
+size_t ise_work_doubles(const cde_model* m);
+hipError_t launch_cv_ise(const cde_model* m, const double* h, const double* ell, double* out,
+                         double* terms, double* work, hipStream_t stream);
+
 // Scalar-bandwidth grid on FP32 models: per-point neighbour shifts (first
 // call only), the MFMA grid pass, FP64 finalisation, exact fixup of extreme
 // entries and the fixed-order row sums.  `work` must hold grid_work_bytes();

@@ -152,6 +152,18 @@ class Model:
         B.check(st, "cde_conditional_mean")
         return out
 
+    def cv_ise(self, h, terms: bool = False, stream=None):
+        """Cross-validated ISE of Section 3 (eq. 2) for one diagonal setting h
+        (Gaussian kernels, FP32 models): returns a float64 device tensor
+        [ISE, mean T1, mean T2] and, when ``terms``, the per-point [n, 2]
+        tensor (T1_i, T2_i) as well.  O(n^3) work."""
+        out = torch.empty(3, dtype=torch.float64, device=self.device)
+        tm = torch.empty((self.n, 2), dtype=torch.float64, device=self.device) if terms else None
+        st = self._lib.cde_cv_ise(self._h, B.doubles(self._bw(h)), out.data_ptr(),
+                                  tm.data_ptr() if tm is not None else None, _stream_ptr(stream))
+        B.check(st, "cde_cv_ise")
+        return (out, tm) if terms else out
+
     def query(self, xq: torch.Tensor, ygrid: torch.Tensor, h, stream=None, out=None):
         """f(ygrid[g] | xq[q]) of eq. (1) over all training points: [q, k] float64."""
         xq = xq.reshape(-1, self.dx).to(self.dtype).contiguous()

@@ -27,7 +27,8 @@ def lib():
 def test_header_declares_expected_calls():
     names = declared_functions()
     for n in ("cde_create", "cde_destroy", "cde_loo_loglik", "cde_loo_grad", "cde_density_query",
-              "cde_loo_loglik_list", "cde_last_error", "cde_abi_version"):
+              "cde_loo_loglik_list", "cde_last_error", "cde_abi_version", "cde_conditional_mean",
+              "cde_density_summary", "cde_cv_ise"):
         assert n in names
 
 
@@ -43,7 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.cde_abi_version() == 2
+    assert lib.cde_abi_version() == 3
 
 
 def test_invalid_arguments_return_status(lib):
@@ -61,6 +62,7 @@ def test_invalid_arguments_return_status(lib):
     assert lib.cde_loo_loglik(None, hv, 1, hv, 1, 0, 0, 0, 8, None, None, None) == B.CDE_EINVAL
     assert lib.cde_loo_loglik_list(None, hv, 1, 0, 0, 8, None, None) == B.CDE_EINVAL
     assert lib.cde_density_query(None, 8, 1, 8, 1, hv, 8, None) == B.CDE_EINVAL
+    assert lib.cde_cv_ise(None, hv, 8, None, None) == B.CDE_EINVAL
     assert lib.cde_destroy(None) == B.CDE_OK
     assert lib.cde_model_device_bytes(None) == 0
 
