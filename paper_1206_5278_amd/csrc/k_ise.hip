@@ -218,19 +218,25 @@ __global__ __launch_bounds__(INT) void k_ise_mfma(const float* __restrict__ pts,
             }
             __syncthreads();
             v4f acc[IGT];
-#pragma unroll
-            for (int s = 0; s < SUB; s += 4) {
-                const int jj = s0 + s + kr;
+            // x-kernel value of a 4-point step; the next step's is formed
+            // before the current step's MFMAs are issued
+            auto weight = [&](int jj) {
                 const int j = t0 + jj;
                 const double d2 = xdist2_shifted<DX>(xo, tile + jj * SD, a, m_q);
                 const float xa = (jj < cnt && j != qi) ? (float)d2 : IEXCL;
-                const float w = exp2_<float>(-xa);
+                return exp2_<float>(-xa);
+            };
+            float w = weight(s0 + kr);
+#pragma unroll
+            for (int s = 0; s < SUB; s += 4) {
+                const float wn = s + 4 < SUB ? weight(s0 + s + 4 + kr) : 0.f;
                 dp += w;
                 const float* brow = ykv + (s + kr) * YS + (lane & 15);
 #pragma unroll
                 for (int t = 0; t < IGT; ++t)
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                         w, brow[16 * t], s == 0 ? v4f{0.f, 0.f, 0.f, 0.f} : acc[t], 0, 0, 0);
+                w = wn;
             }
 #pragma unroll
             for (int t = 0; t < IGT; ++t)

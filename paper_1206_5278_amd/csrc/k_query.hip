@@ -274,18 +274,24 @@ __global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pt
             }
             __syncthreads();
             v4f acc[GT];
-#pragma unroll
-            for (int s = 0; s < SUB; s += 4) {
-                const int ii = s0 + s + kr;
+            // x-kernel value of a 4-point step; the next step's is formed
+            // before the current step's MFMAs are issued
+            auto weight = [&](int ii) {
                 const double d2 = xdist2_shifted<DX>(xo, tile + ii * SD, qa, m_q);
                 const float xa = ii < cnt ? (float)d2 : QEXCLUDED;
-                const float w = exp2_<float>(-xa);
+                return exp2_<float>(-xa);
+            };
+            float w = weight(s0 + kr);
+#pragma unroll
+            for (int s = 0; s < SUB; s += 4) {
+                const float wn = s + 4 < SUB ? weight(s0 + s + 4 + kr) : 0.f;
                 dp += w;
                 const float* brow = ykv + (s + kr) * YS + (lane & 15);
 #pragma unroll
                 for (int t = 0; t < GT; ++t)
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                         w, brow[16 * t], s == 0 ? v4f{0.f, 0.f, 0.f, 0.f} : acc[t], 0, 0, 0);
+                w = wn;
             }
 #pragma unroll
             for (int t = 0; t < GT; ++t)
