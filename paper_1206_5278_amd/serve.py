@@ -32,6 +32,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import sys
 import time
 from typing import Callable
 
@@ -216,11 +217,22 @@ class Scheduler:
             self._launch(admitted)
         return bool(self.pending or self.waiting or self.inflight or self.ready_q)
 
-    def run(self, idle_sleep: float = 2e-4, deadline: float | None = None) -> None:
+    def run(self, idle_sleep: float = 2e-4, deadline: float | None = None,
+            progress: float | None = None, log=None) -> None:
+        """Drive ticks until every request has finished (or the deadline
+        passes).  With ``progress`` (seconds), ``log`` (default: stderr) gets
+        a status line at that interval."""
         self.t0 = self.clock()
+        next_log = progress
         while self.tick():
-            if deadline is not None and self.now() > deadline:
+            now = self.now()
+            if deadline is not None and now > deadline:
                 break
+            if progress is not None and now >= next_log:
+                line = (f"serve: t={now:.0f} s completed={len(self.completed)} "
+                        f"waiting={len(self.waiting)} in_flight={sum(len(q) for _, q, _ in self.inflight)}")
+                (log or (lambda m: print(m, file=sys.stderr, flush=True)))(line)
+                next_log += progress
             if not self.waiting or self.active >= self.max_active:
                 time.sleep(idle_sleep)
         self.ex.wait_all()
