@@ -159,10 +159,14 @@ cde_status cde_loo_grad(cde_model* m, const double* h, cde_criterion criterion,
 /* Conditional density queries, eq. (1) over all n training points (no point
  * left out): f_dev[qq][g] = f(ygrid[g] | xq[qq]).
  *   xq_dev: [q][dx], ygrid_dev: [k][dy], device memory of the model's
- *   precision type.  h: host [dx+dy].  f_dev: [q][k] doubles.
- *   Gaussian kernel.  Limits: q >= 0, 0 <= k <= 4096. */
+ *   precision type.  h: host [dx+dy].  kernel: CDE_GAUSSIAN, or
+ *   CDE_EPANECHNIKOV (the kernel of Section 4, radial over the scaled
+ *   coordinates; FP32 models only; f = 0 where no training x lies inside the
+ *   query's x window, where eq. (1) is 0/0).  f_dev: [q][k] doubles.
+ *   Limits: q >= 0, 0 <= k <= 4096. */
 cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const void* ygrid_dev,
-                             int64_t k, const double* h, double* f_dev, void* stream);
+                             int64_t k, const double* h, cde_kernel kernel, double* f_dev,
+                             void* stream);
 
 /* Conditional mean E[y | x_q] = sum_i K_hx(x_q - x_i) y_i / sum_i K_hx(x_q - x_i),
  * the mean of eq. (1)'s density (each y-kernel component has mean y_i): the

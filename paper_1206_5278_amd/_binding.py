@@ -36,7 +36,7 @@ SIGNATURES = {
     "cde_loo_loglik_list": (ctypes.c_int, [_vp, _dp, _i32, ctypes.c_int, ctypes.c_int, _vp, _vp,
                                            _vp]),
     "cde_loo_grad": (ctypes.c_int, [_vp, _dp, ctypes.c_int, _vp, _vp, _vp, _vp]),
-    "cde_density_query": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _dp, _vp, _vp]),
+    "cde_density_query": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _dp, ctypes.c_int, _vp, _vp]),
     "cde_conditional_mean": (ctypes.c_int, [_vp, _vp, _i64, _dp, _vp, _vp]),
     "cde_density_summary": (ctypes.c_int, [_vp, _vp, _i64, _i64, ctypes.c_double, _vp, _vp]),
     "cde_cv_ise": (ctypes.c_int, [_vp, _dp, _vp, _vp, _vp]),

@@ -13,6 +13,16 @@
 
 using namespace cde;
 
+// Radial Epanechnikov setting (Section 4's kernel in the scaled form of
+// Section 2): K_h(t) = c_d / prod h * max(0, 1 - |t/h|^2), c_d = (d+2)/(2 V_d).
+double cde::log_epan_norm(const double* h, int d)
+{
+    const double log_vd = 0.5 * d * std::log(3.14159265358979323846) - std::lgamma(0.5 * d + 1.0);
+    double s = std::log((d + 2.0) / 2.0) - log_vd;
+    for (int k = 0; k < d; ++k) s -= std::log(h[k]);
+    return s;
+}
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -152,16 +162,6 @@ cde_status run_diag_list(cde_model* m, const double* h, int g, int crit, bool gr
                                        counts, nonfinite, stream);
     if (e != hipSuccess) return hip_fail(e, "launch k_reduce_parts");
     return CDE_OK;
-}
-
-// Radial Epanechnikov setting (Section 4's kernel in the scaled form of
-// Section 2): K_h(t) = c_d / prod h * max(0, 1 - |t/h|^2), c_d = (d+2)/(2 V_d).
-double log_epan_norm(const double* h, int d)
-{
-    const double log_vd = 0.5 * d * std::log(3.14159265358979323846) - std::lgamma(0.5 * d + 1.0);
-    double s = std::log((d + 2.0) / 2.0) - log_vd;
-    for (int k = 0; k < d; ++k) s -= std::log(h[k]);
-    return s;
 }
 
 void fill_epan(EpanSet& s, const double* h, int dx, int dy)
@@ -498,10 +498,12 @@ cde_status cde_cv_ise(cde_model* m, const double* h, double* out_dev, double* te
 }
 
 cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const void* ygrid_dev,
-                             int64_t k, const double* h, double* f_dev, void* stream)
+                             int64_t k, const double* h, cde_kernel kernel, double* f_dev, void* stream)
 {
     try {
         if (!m) return fail(CDE_EINVAL, "cde_density_query: model is NULL");
+        if (kernel != CDE_GAUSSIAN && kernel != CDE_EPANECHNIKOV)
+            return fail(CDE_EINVAL, "cde_density_query: unknown kernel");
         if (q < 0 || k < 0 || k > 4096) return fail(CDE_EINVAL, "cde_density_query: need q >= 0, 0 <= k <= 4096");
         if (q > 0 && k > 0 && (!xq_dev || !ygrid_dev || !f_dev))
             return fail(CDE_EINVAL, "cde_density_query: NULL device pointer");
@@ -513,6 +515,8 @@ cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const 
         hipStream_t s = (hipStream_t)stream;
         hipError_t e;
         if (m->prec == CDE_F64) {
+            if (kernel != CDE_GAUSSIAN)
+                return fail(CDE_EUNSUPPORTED, "cde_density_query: Epanechnikov queries need an FP32 model");
             DiagSets<double> sets;
             std::memset(&sets, 0, sizeof sets);
             fill_set(sets.s[0], h, m->dx, m->dy);
@@ -523,7 +527,7 @@ cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const 
             cde_status st = ensure_scratch(m, sizeof(double) * query_work_doubles(m, q, k) + 256);
             if (st != CDE_OK) return st;
             e = launch_query_mfma(m, (const float*)xq_dev, (int)q, (const float*)ygrid_dev, (int)k, h,
-                                  f_dev, (double*)m->scratch, s);
+                                  kernel == CDE_EPANECHNIKOV, f_dev, (double*)m->scratch, s);
         }
         if (e != hipSuccess) return hip_fail(e, "launch k_query");
         return CDE_OK;

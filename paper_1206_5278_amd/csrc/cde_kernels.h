@@ -61,7 +61,9 @@ hipError_t launch_query(const cde_model* m, const T* xq, int64_t q, const T* yg,
 // Density queries on FP32 models, on the matrix cores: f [q][k]; `work`
 // holds query_work_doubles(m, q, k) doubles (shifts and chunk partials).
 hipError_t launch_query_mfma(const cde_model* m, const float* xq, int q, const float* yg, int k,
-                             const double* h, double* f, double* work, hipStream_t stream);
+                             const double* h, bool epan, double* f, double* work, hipStream_t stream);
+// log of the radial Epanechnikov normalisation c_d / prod h_k (cde_api.hip)
+double log_epan_norm(const double* h, int d);
 size_t query_work_doubles(const cde_model* m, int64_t q, int64_t k);
 
 // Cross-validated ISE (k_ise.hip): FP32 models; ell = the conditional LOO

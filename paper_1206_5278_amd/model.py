@@ -164,14 +164,17 @@ class Model:
         B.check(st, "cde_cv_ise")
         return (out, tm) if terms else out
 
-    def query(self, xq: torch.Tensor, ygrid: torch.Tensor, h, stream=None, out=None):
-        """f(ygrid[g] | xq[q]) of eq. (1) over all training points: [q, k] float64."""
+    def query(self, xq: torch.Tensor, ygrid: torch.Tensor, h, stream=None, out=None,
+              kernel: str = "gaussian"):
+        """f(ygrid[g] | xq[q]) of eq. (1) over all training points: [q, k] float64
+        (``kernel``: "gaussian", or "epanechnikov" for FP32 models)."""
         xq = xq.reshape(-1, self.dx).to(self.dtype).contiguous()
         ygrid = ygrid.reshape(-1, self.dy).to(self.dtype).contiguous()
         q, k = int(xq.shape[0]), int(ygrid.shape[0])
         f = out if out is not None else torch.empty((q, k), dtype=torch.float64, device=self.device)
         st = self._lib.cde_density_query(self._h, xq.data_ptr(), q, ygrid.data_ptr(), k,
-                                         B.doubles(self._bw(h)), f.data_ptr(), _stream_ptr(stream))
+                                         B.doubles(self._bw(h)), KERNELS[kernel], f.data_ptr(),
+                                         _stream_ptr(stream))
         B.check(st, "cde_density_query")
         return f
 

@@ -61,7 +61,7 @@ def test_invalid_arguments_return_status(lib):
     assert lib.cde_loo_grad(None, hv, 0, 8, 8, None, None) == B.CDE_EINVAL
     assert lib.cde_loo_loglik(None, hv, 1, hv, 1, 0, 0, 0, 8, None, None, None) == B.CDE_EINVAL
     assert lib.cde_loo_loglik_list(None, hv, 1, 0, 0, 8, None, None) == B.CDE_EINVAL
-    assert lib.cde_density_query(None, 8, 1, 8, 1, hv, 8, None) == B.CDE_EINVAL
+    assert lib.cde_density_query(None, 8, 1, 8, 1, hv, 0, 8, None) == B.CDE_EINVAL
     assert lib.cde_cv_ise(None, hv, 8, None, None) == B.CDE_EINVAL
     assert lib.cde_destroy(None) == B.CDE_OK
     assert lib.cde_model_device_bytes(None) == 0

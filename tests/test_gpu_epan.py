@@ -170,3 +170,59 @@ def test_epan_deterministic_and_model_order_independent():
     _, p3 = m2.loo_list(hs, per_point=True, kernel="epanechnikov")
     torch.cuda.synchronize()
     np.testing.assert_allclose(p3.cpu().numpy(), p1.cpu().numpy()[:, perm], rtol=1e-12, atol=1e-12)
+
+
+def check_density(f, ref):
+    # query tolerance; rows with no training x inside the window are 0 on both
+    peak = ref.max(axis=1, keepdims=True)
+    err = np.abs(f - ref)
+    assert np.all(err <= 1e-5 * ref + 1e-7 * peak), float(np.max(err / (1e-5 * ref + 1e-7 * peak + 1e-300)))
+    assert np.array_equal(f == 0.0, ref == 0.0), int(np.sum((f == 0.0) != (ref == 0.0)))
+
+
+@pytest.mark.parametrize("dx,dy,k", [(3, 1, 150), (1, 1, 40), (2, 2, 100), (5, 1, 256), (16, 2, 70)])
+def test_epan_query_parity(dx, dy, k):
+    # 200 queries (two blocks, ragged), grid widths 64/128/256 per block; a
+    # narrow and a wide window (the narrow one leaves some queries with no
+    # training x inside, f = 0 there, and most grid points outside every window)
+    say(f"case: epan query dx={dx} dy={dy} k={k}")
+    v = workloads.gmm_general(3000, dx + dy, seed=600 + 10 * dx + dy)
+    x, y = v[:, :dx], v[:, dx:]
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    rng = np.random.default_rng(dx + 7 * dy)
+    xq = (xo[rng.choice(3000, 200)] + 0.3 * rng.normal(size=(200, dx))).astype(np.float32).astype(np.float64)
+    xq[0] = xo.max(axis=0) + 50.0  # far outside the data: D = 0
+    yg = (np.linspace(-1, 1, k)[:, None] * np.ones((1, dy)) * 6.0).astype(np.float32).astype(np.float64)
+    sd = np.std(np.concatenate([xo, yo], axis=1), axis=0)
+    for f_h in (0.15, 0.8):
+        h = list(f_h * sd)
+        f = m.query(P.to_dev(xq), P.to_dev(yg), h, kernel="epanechnikov").cpu().numpy()
+        ref = oracle.density_epan(xo, yo, h, xq, yg)
+        check_density(f, ref)
+        assert np.all(f[0] == 0.0)
+
+
+def test_epan_query_rows_independent_of_batch_and_fp64_rejected():
+    say("case: epan query rows alone vs batch")
+    from paper_1206_5278_amd import _binding as B
+    x, y = workloads.photoz(40_000, seed=3)
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    sd = np.std(np.concatenate([xo, yo], axis=1), axis=0)
+    h = list(0.2 * sd)
+    rng = np.random.default_rng(4)
+    xq = (xo[rng.choice(40_000, 1000)] + 0.01).astype(np.float32)
+    yg = np.linspace(-0.1, 0.7, 256).astype(np.float32)
+    xq_d, yg_d = P.to_dev(xq, torch.float32), P.to_dev(yg, torch.float32)
+    full = m.query(xq_d, yg_d, h, kernel="epanechnikov").cpu().numpy()
+    for rows in ([0], [999], [5, 500, 998]):
+        part = m.query(xq_d[rows].contiguous(), yg_d, h, kernel="epanechnikov").cpu().numpy()
+        assert np.array_equal(part, full[rows]), rows
+    ref = oracle.density_epan(xo, yo, h, xq[[0, 999]].astype(np.float64), yg.astype(np.float64))
+    check_density(full[[0, 999]], ref)
+    m64 = cde().Model(P.to_dev(x, torch.float64), P.to_dev(y, torch.float64))
+    with pytest.raises(B.CdeError) as e:
+        m64.query(P.to_dev(xq[:4].astype(np.float64), torch.float64), P.to_dev(yg.astype(np.float64), torch.float64),
+                  h, kernel="epanechnikov")
+    assert e.value.status == B.CDE_EUNSUPPORTED
