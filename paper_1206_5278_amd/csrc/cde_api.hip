@@ -524,10 +524,19 @@ cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const 
                                      f_dev, s);
         } else {
             if (q >= (int64_t(1) << 31) - 64) return fail(CDE_EUNSUPPORTED, "cde_density_query: q >= 2^31");
-            cde_status st = ensure_scratch(m, sizeof(double) * query_work_doubles(m, q, k) + 256);
-            if (st != CDE_OK) return st;
-            e = launch_query_mfma(m, (const float*)xq_dev, (int)q, (const float*)ygrid_dev, (int)k, h,
-                                  kernel == CDE_EPANECHNIKOV, f_dev, (double*)m->scratch, s);
+            if (kernel == CDE_EPANECHNIKOV) {
+                cde_status st = ensure_index(m, s);
+                if (st != CDE_OK) return st;
+                st = ensure_scratch(m, query_epan_work_bytes(m, q, k) + 256);
+                if (st != CDE_OK) return st;
+                e = launch_query_epan(m, (const float*)xq_dev, (int)q, (const float*)ygrid_dev, (int)k, h,
+                                      f_dev, (char*)m->scratch, s);
+            } else {
+                cde_status st = ensure_scratch(m, sizeof(double) * query_work_doubles(m, q, k) + 256);
+                if (st != CDE_OK) return st;
+                e = launch_query_mfma(m, (const float*)xq_dev, (int)q, (const float*)ygrid_dev, (int)k, h,
+                                      f_dev, (double*)m->scratch, s);
+            }
         }
         if (e != hipSuccess) return hip_fail(e, "launch k_query");
         return CDE_OK;

@@ -61,7 +61,18 @@ hipError_t launch_query(const cde_model* m, const T* xq, int64_t q, const T* yg,
 // Density queries on FP32 models, on the matrix cores: f [q][k]; `work`
 // holds query_work_doubles(m, q, k) doubles (shifts and chunk partials).
 hipError_t launch_query_mfma(const cde_model* m, const float* xq, int q, const float* yg, int k,
-                             const double* h, bool epan, double* f, double* work, hipStream_t stream);
+                             const double* h, double* f, double* work, hipStream_t stream);
+// Query decomposition shared by the Gaussian and Epanechnikov query kernels
+// (functions of n and k only): training-point chunk size, grid tiles of 16
+// per block, queries per slice.
+int64_t query_chunk_points(int64_t n);
+int query_grid_tiles(int64_t k);
+int64_t query_slice(int64_t nch, int64_t q, int64_t k);
+// Epanechnikov queries (k_query_epan.hip): FP32 models with the spatial
+// index built; work = query_epan_work_bytes of device scratch.
+size_t query_epan_work_bytes(const cde_model* m, int64_t q, int64_t k);
+hipError_t launch_query_epan(const cde_model* m, const float* xq, int q, const float* yg, int k,
+                             const double* h, double* f, char* work, hipStream_t stream);
 // log of the radial Epanechnikov normalisation c_d / prod h_k (cde_api.hip)
 double log_epan_norm(const double* h, int d);
 size_t query_work_doubles(const cde_model* m, int64_t q, int64_t k);

@@ -10,13 +10,6 @@
 // one y-kernel value per grid point are formed on the VALU (not one product
 // kernel per (q, g)).
 //
-// The Epanechnikov kernel of the paper's experiments (Section 4, radial over
-// the bandwidth-scaled coordinates) runs through the same kernel with
-// w = (1 - |(x_q - x_i) / hx|^2)_+ and k = (1 - |(y_g - y_i) / hy|^2)_+, each
-// formed in FP64 and rounded once to FP32 (no shifts: the values lie in
-// [0, 1] and the nearest point does not bound the sum away from 0); a query
-// with no training x inside its window gets f = 0 (eq. (1) is 0/0 there).
-//
 // Shifts: w' = 2^-(d2x(q,i) - m_q), k' = 2^-(d2y(g,i) - mu_g), with m_q the
 // smallest scaled x-distance of query q to the data and mu_g the smallest
 // scaled y-distance of grid point g (FP64 prepasses; exact minima, so the
@@ -51,8 +44,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr float QEXCLUDED = 1e20f;
 
 struct QueryArgs {
-    double cx[16];   // Gaussian: log2(e) / (2 hx_k^2); Epanechnikov: 1 / hx_k^2
-    double cy[4];    // Gaussian: log2(e) / (2 hy_l^2); Epanechnikov: 1 / hy_l^2
+    double cx[16];   // log2(e) / (2 hx_k^2)
+    double cy[4];    // log2(e) / (2 hy_l^2)
     double log_cy;
 };
 
@@ -207,7 +200,7 @@ constexpr int QWAVES = 8;            // waves per query block
 constexpr int QNT = 64 * QWAVES;     // threads per query block
 constexpr int QPB = 16 * QWAVES;     // queries per query block
 
-template <int DX, int DY, int GT, bool EPAN>
+template <int DX, int DY, int GT>
 __global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pts, int n, int chunk,
                                                      const float* __restrict__ xq, int q,
                                                      const float* __restrict__ yg, int k,
@@ -238,15 +231,14 @@ __global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pt
     double xo[DX];
 #pragma unroll
     for (int kk = 0; kk < DX; ++kk) xo[kk] = (double)xq[(size_t)qi * DX + kk];
-    // Epanechnikov: the sums start from -1, so -sum = 1 - |u|^2
-    const double m_q = EPAN ? 1.0 : mq[qi];
+    const double m_q = mq[qi];
     // y-kernel role: grid column tid % GW, panel rows tid / GW + PSTEP r
     const int gcol = tid % GW;
     const int gy = min(g0 + gcol, k - 1);
     double yo[DY];
 #pragma unroll
     for (int l = 0; l < DY; ++l) yo[l] = (double)yg[(size_t)gy * DY + l];
-    const double mu_g = EPAN ? 1.0 : mu[gy];
+    const double mu_g = mu[gy];
     const int prow = tid / GW;
 
     // Panel sums (MFMA, 32 points) are added into FP32 chunk sums; a chunk
@@ -277,8 +269,8 @@ __global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pt
 #pragma unroll
             for (int r = 0; r < YPT; ++r) {
                 const int p = prow + PSTEP * r;
-                const double a = ydist2_shifted<DX, DY>(yo, tile + (s0 + p) * SD, qa, mu_g);
-                ykv[p * YS + gcol] = EPAN ? (float)fmax(-a, 0.0) : exp2_<float>(-fmaxf((float)a, 0.f));
+                const float a = (float)ydist2_shifted<DX, DY>(yo, tile + (s0 + p) * SD, qa, mu_g);
+                ykv[p * YS + gcol] = exp2_<float>(-fmaxf(a, 0.f));
             }
             __syncthreads();
             v4f acc[GT];
@@ -286,7 +278,6 @@ __global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pt
             // before the current step's MFMAs are issued
             auto weight = [&](int ii) {
                 const double d2 = xdist2_shifted<DX>(xo, tile + ii * SD, qa, m_q);
-                if (EPAN) return ii < cnt ? (float)fmax(-d2, 0.0) : 0.f;
                 const float xa = ii < cnt ? (float)d2 : QEXCLUDED;
                 return exp2_<float>(-xa);
             };
@@ -327,9 +318,7 @@ __global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pt
     }
 }
 
-// f = c_y 2^-mu_g F'/D' with F' and D' summed over the point chunks in order
-// (Epanechnikov: f = c_y F/D, 0 where D = 0).
-template <bool EPAN>
+// f = c_y 2^-mu_g F'/D' with F' and D' summed over the point chunks in order.
 __global__ void k_query_reduce(const float* __restrict__ fpart, const double* __restrict__ dpart,
                                const double* __restrict__ mu, int q, int k, int nchunks,
                                double log_cy, double* __restrict__ f)
@@ -342,23 +331,20 @@ __global__ void k_query_reduce(const float* __restrict__ fpart, const double* __
         num += (double)fpart[((size_t)c * q + qq) * k + g];
         den += dpart[(size_t)c * q + qq];
     }
-    if (EPAN)
-        f[e] = den > 0.0 ? exp(log_cy) * num / den : 0.0;
-    else
-        f[e] = num > 0.0 ? exp(log_cy - mu[g] * LN2 + log(num / den)) : 0.0;
+    f[e] = num > 0.0 ? exp(log_cy - mu[g] * LN2 + log(num / den)) : 0.0;
 }
 
 // Training-point chunks: whole tiles, at most 256 chunks while that keeps a
 // chunk within 8 tiles (the FP32 chunk sums above), a function of n only
 // (never of the batch).
-static int64_t query_chunk_points(int64_t n)
+int64_t query_chunk_points(int64_t n)
 {
     const int64_t ntiles = (n + TILE - 1) / TILE;
     return std::min<int64_t>(8, (ntiles + 255) / 256) * TILE;
 }
 
 // Grid tiles of 16 points per block: 4, 8 or 16 (a function of k only).
-static int query_grid_tiles(int64_t k)
+int query_grid_tiles(int64_t k)
 {
     const int64_t nt = (k + 15) / 16;
     return nt <= 4 ? 4 : nt <= 8 ? 8 : 16;
@@ -366,7 +352,7 @@ static int query_grid_tiles(int64_t k)
 
 // Queries per slice: chunk partials of one slice (k FP32 numerators and one
 // FP64 denominator per query and chunk) within 512 MiB.
-static int64_t query_slice(int64_t nch, int64_t q, int64_t k)
+int64_t query_slice(int64_t nch, int64_t q, int64_t k)
 {
     int64_t s = ((int64_t(1) << 29) / (nch * (4 * k + 8))) / QPB * QPB;
     return std::min(q, std::max<int64_t>(QPB, s));
@@ -380,21 +366,17 @@ size_t query_work_doubles(const cde_model* m, int64_t q, int64_t k)
     return (size_t)(q + k + nch * qs + (nch * qs * k + 1) / 2 + 64);
 }
 
-template <int DX, int DY, bool EPAN>
+template <int DX, int DY>
 static hipError_t query_t(const cde_model* m, const float* xq, int q, const float* yg, int k,
                           const double* h, double* f, double* work, hipStream_t stream)
 {
     QueryArgs qa;
-    for (int kk = 0; kk < 16; ++kk)
-        qa.cx[kk] = kk >= DX ? 0.0 : EPAN ? 1.0 / (h[kk] * h[kk]) : LOG2E / (2.0 * h[kk] * h[kk]);
+    for (int kk = 0; kk < 16; ++kk) qa.cx[kk] = kk < DX ? LOG2E / (2.0 * h[kk] * h[kk]) : 0.0;
     double lcy = 0.0;
     for (int l = 0; l < 4; ++l) {
-        qa.cy[l] = l >= DY ? 0.0
-                   : EPAN  ? 1.0 / (h[DX + l] * h[DX + l])
-                           : LOG2E / (2.0 * h[DX + l] * h[DX + l]);
-        if (!EPAN && l < DY) lcy -= log(h[DX + l]) + HALF_LOG_2PI;
+        qa.cy[l] = l < DY ? LOG2E / (2.0 * h[DX + l] * h[DX + l]) : 0.0;
+        if (l < DY) lcy -= log(h[DX + l]) + HALF_LOG_2PI;
     }
-    if (EPAN) lcy = log_epan_norm(h + DX, DY);
     qa.log_cy = lcy;
     const int n = (int)m->n;
     const float* pts = (const float*)m->pts;
@@ -407,19 +389,17 @@ static hipError_t query_t(const cde_model* m, const float* xq, int q, const floa
     double* mu = work + q;
     double* dpart = mu + k;
     float* fpart = (float*)(dpart + (size_t)nch * qs);
-    hipError_t e;
-    if (!EPAN) {
-        // shifts: exact minima over point chunks
-        const int sch = 16 * TILE;
-        const int nsch = (n + sch - 1) / sch;
-        hipLaunchKernelGGL(k_fill_inf, dim3((q + k + 255) / 256), dim3(256), 0, stream, mq, q + k);
-        hipLaunchKernelGGL((k_qshift_x<DX, DY>), dim3((q + TILE - 1) / TILE, nsch), dim3(TILE), 0, stream,
-                           pts, n, sch, xq, q, qa, mq);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_qshift_y<DX, DY>), dim3((k + TILE - 1) / TILE, nsch), dim3(TILE), 0, stream,
-                           pts, n, sch, yg, k, qa, mu);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    // shifts: exact minima over point chunks
+    const int sch = 16 * TILE;
+    const int nsch = (n + sch - 1) / sch;
+    hipLaunchKernelGGL(k_fill_inf, dim3((q + k + 255) / 256), dim3(256), 0, stream, mq, q + k);
+    hipLaunchKernelGGL((k_qshift_x<DX, DY>), dim3((q + TILE - 1) / TILE, nsch), dim3(TILE), 0, stream,
+                       pts, n, sch, xq, q, qa, mq);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_qshift_y<DX, DY>), dim3((k + TILE - 1) / TILE, nsch), dim3(TILE), 0, stream,
+                       pts, n, sch, yg, k, qa, mu);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int q0 = 0; q0 < q; q0 += qs) {
         const int qn = std::min(qs, q - q0);
         const int qb = (qn + QPB - 1) / QPB;
@@ -427,17 +407,17 @@ static hipError_t query_t(const cde_model* m, const float* xq, int q, const floa
         const float* xs = xq + (size_t)q0 * DX;
         const double* mqs = mq + q0;
         if (gt == 4)
-            hipLaunchKernelGGL((k_query_mfma<DX, DY, 4, EPAN>), grid, dim3(QNT), 0, stream, pts, n, chunk,
-                               xs, qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
+            hipLaunchKernelGGL((k_query_mfma<DX, DY, 4>), grid, dim3(QNT), 0, stream, pts, n, chunk, xs,
+                               qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
         else if (gt == 8)
-            hipLaunchKernelGGL((k_query_mfma<DX, DY, 8, EPAN>), grid, dim3(QNT), 0, stream, pts, n, chunk,
-                               xs, qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
+            hipLaunchKernelGGL((k_query_mfma<DX, DY, 8>), grid, dim3(QNT), 0, stream, pts, n, chunk, xs,
+                               qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
         else
-            hipLaunchKernelGGL((k_query_mfma<DX, DY, 16, EPAN>), grid, dim3(QNT), 0, stream, pts, n, chunk,
-                               xs, qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
+            hipLaunchKernelGGL((k_query_mfma<DX, DY, 16>), grid, dim3(QNT), 0, stream, pts, n, chunk, xs,
+                               qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int64_t total = (int64_t)qn * k;
-        hipLaunchKernelGGL(k_query_reduce<EPAN>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
+        hipLaunchKernelGGL(k_query_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
                            (const float*)fpart, (const double*)dpart, (const double*)mu, qn, k, nch,
                            lcy, f + (size_t)q0 * k);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -445,13 +425,11 @@ static hipError_t query_t(const cde_model* m, const float* xq, int q, const floa
     return hipSuccess;
 }
 
-#define CDE_QM_CASE(DX_, DY_)                                                                   \
-    case (DX_) * 8 + (DY_):                                                                     \
-        return epan ? query_t<DX_, DY_, true>(m, xq, q, yg, k, h, f, work, stream)              \
-                    : query_t<DX_, DY_, false>(m, xq, q, yg, k, h, f, work, stream);
+#define CDE_QM_CASE(DX_, DY_) \
+    case (DX_) * 8 + (DY_): return query_t<DX_, DY_>(m, xq, q, yg, k, h, f, work, stream);
 
 hipError_t launch_query_mfma(const cde_model* m, const float* xq, int q, const float* yg, int k,
-                             const double* h, bool epan, double* f, double* work, hipStream_t stream)
+                             const double* h, double* f, double* work, hipStream_t stream)
 {
     switch (m->dx * 8 + m->dy) {
         CDE_QM_CASE(1, 1) CDE_QM_CASE(1, 2) CDE_QM_CASE(2, 1) CDE_QM_CASE(2, 2)

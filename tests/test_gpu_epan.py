@@ -226,3 +226,27 @@ def test_epan_query_rows_independent_of_batch_and_fp64_rejected():
         m64.query(P.to_dev(xq[:4].astype(np.float64), torch.float64), P.to_dev(yg.astype(np.float64), torch.float64),
                   h, kernel="epanechnikov")
     assert e.value.status == B.CDE_EUNSUPPORTED
+
+
+def test_epan_query_narrow_window_skipping():
+    # n = 120,000 and h = 0.03 sd: almost every (query block, tile) pair is
+    # skipped; some queries lie in empty windows.  Rows alone vs in the batch,
+    # and sampled rows against the oracle (zeros exactly where it has zeros).
+    say("case: epan query n=120000 h=0.03 sd")
+    x, y = workloads.photoz(120_000, seed=5)
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    sd = np.std(np.concatenate([xo, yo], axis=1), axis=0)
+    h = list(0.03 * sd)
+    rng = np.random.default_rng(6)
+    xq = (xo[rng.choice(120_000, 2500)] + 0.02 * rng.normal(size=(2500, 5))).astype(np.float32)
+    yg = np.linspace(-0.1, 0.7, 200).astype(np.float32)
+    xq_d, yg_d = P.to_dev(xq, torch.float32), P.to_dev(yg, torch.float32)
+    full = m.query(xq_d, yg_d, h, kernel="epanechnikov").cpu().numpy()
+    rows = [0, 1234, 2499]
+    part = m.query(xq_d[rows].contiguous(), yg_d, h, kernel="epanechnikov").cpu().numpy()
+    assert np.array_equal(part, full[rows])
+    ref = oracle.density_epan(xo, yo, h, xq[rows].astype(np.float64), yg.astype(np.float64))
+    check_density(full[rows], ref)
+    assert np.any(full.max(axis=1) == 0.0) and np.any(full.max(axis=1) > 0.0)
+
