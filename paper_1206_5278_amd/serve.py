@@ -90,6 +90,11 @@ class Executor:
     def idle(self) -> None:
         """Called when nothing is in flight (a safe point for deferred frees)."""
 
+    def resident_bytes(self) -> int:
+        """Device memory held outside any request (resident sets and their
+        scratch); the scheduler admits requests against what remains."""
+        return 0
+
 
 class Scheduler:
     """Admission, batching and completion tracking (device-agnostic)."""
@@ -101,7 +106,9 @@ class Scheduler:
         self.max_query_rows = int(max_query_rows)
         self.ready_q = collections.OrderedDict()  # set_id -> admitted queries not launched
         self.q_busy = set()                       # sets with a query launch in flight
-        self.budget = int(hbm_budget)
+        self.budget = int(hbm_budget) - int(executor.resident_bytes())
+        if self.budget <= 0:
+            raise ValueError("the resident sets alone exceed the HBM budget")
         self.max_active = int(max_active)
         self.batched = batched
         self.clock = clock or time.perf_counter
@@ -262,7 +269,7 @@ class Scheduler:
 class GpuExecutor(Executor):
     """Runs requests through the C ABI on HIP streams."""
 
-    def __init__(self, sets, n_streams: int = 4, grid_points: int = 256):
+    def __init__(self, sets, n_streams: int = 4, grid_points: int = 256, max_query_rows: int = 1 << 16):
         import torch
 
         from . import _binding
@@ -293,12 +300,25 @@ class GpuExecutor(Executor):
             yg64 = torch.from_numpy(yg.astype(np.float32).astype(np.float64)).to(self.dev)
             self.sets.append({"model": m, "h": h, "ygrid": ygd, "ygrid64": yg64, "k": grid_points,
                               "dx": x32.shape[1]})
+            # One fused batch of the largest size the scheduler forms grows
+            # the set's scratch to its final size now: later queries then
+            # never reallocate (a device-wide synchronisation), and the
+            # memory is counted in resident_bytes.
+            xw = torch.from_numpy(np.repeat(x32[:1], max_query_rows, axis=0)).to(self.dev)
+            f = m.query(xw, ygd, h)
+            m.conditional_mean(xw, h)
+            density_summary(f, yg64, self.alpha)
+            del xw, f
         torch.cuda.synchronize()
+        self._resident = sum(st["model"].device_bytes for st in self.sets)
 
     def _stream(self):
         s = self.streams[self.rr % len(self.streams)]
         self.rr += 1
         return s
+
+    def resident_bytes(self) -> int:
+        return self._resident
 
     def footprint(self, r):
         if r.kind == "query":

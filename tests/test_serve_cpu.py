@@ -3,6 +3,8 @@ admission by memory footprint and slots, FIFO order, fused query launches,
 the one-request-per-launch baseline, and failure isolation."""
 import numpy as np
 
+import pytest
+
 from paper_1206_5278_amd.serve import Executor, Scheduler, ServeRequest
 
 
@@ -99,6 +101,22 @@ def test_admission_by_footprint_and_late_arrivals():
     assert start[2] >= 2.0 and start[3] >= 2.0  # admitted as memory frees up
     assert start[9] >= 2.0
     assert s.used == 0 and s.active == 0
+
+
+def test_resident_memory_is_taken_from_the_budget():
+    # resident sets hold 100 of 250 bytes: only one 100-byte job fits at a time
+    clock = FakeClock()
+    ex = FakeExecutor(clock, latency=2.0)
+    ex.resident_bytes = lambda: 100
+    s = Scheduler(ex, hbm_budget=250, max_active=64, batched=True, clock=clock)
+    assert s.budget == 150
+    s.submit_all([ServeRequest(i, "job", 0.0) for i in range(2)])
+    drive(s, clock)
+    start = {l[1][0]: l[2] for l in ex.launches}
+    assert start[0] == 0.0 and start[1] >= 2.0
+    ex.resident_bytes = lambda: 300
+    with pytest.raises(ValueError):
+        Scheduler(ex, hbm_budget=250, batched=True, clock=clock)
 
 
 def test_slot_limit_and_rejection():
