@@ -360,16 +360,26 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
 
 // FP32 fast pass: the same decomposition with FP32 kernel values (plain
 // v_exp_f32), v_mfma_f32_16x16x4f32 products and sums, partial sums over a
-// 256-point j-tile folded into Kahan-compensated FP32 totals.  FP32 cannot
-// carry a cell whose shifted num' falls far below 1; k_grid_finalize flags
-// the points that have such a cell (num' < 2^-80) and those points are
-// recomputed by the FP64 kernel above.
+// 256-point j-tile folded into Kahan-compensated FP32 totals.  Every kernel
+// value carries an exact factor 2^GRID_BIAS (the exponent is biased by
+// +GRID_BIAS), removed when the totals are written: v_exp_f32 flushes
+// results below 2^-126 to zero while the MFMA keeps denormal products, so
+// the bias moves the smallest kept kernel value from 2^-126 to
+// 2^-(149 + GRID_BIAS) (the cost: the biased exponent is rounded at
+// magnitude ~GRID_BIAS, a relative error below 2^-20 per kernel value).
+// FP32 cannot carry a cell whose shifted num' falls far below 1;
+// k_grid_finalize flags the points that have such a cell (num' < 2^-130:
+// the terms lost, each below 2^-181, then sum to at most n 2^-181, under
+// 1e-9 of the cell for n <= 2^20) and those points are recomputed by the
+// FP64 kernel above.
 // Points per wave of the FP32 pass (4 or 8): fewer points per wave means
 // fewer accumulator registers and more resident waves to hide the latency of
 // each exponential feeding an MFMA.
 #ifndef CDE_GRID32_POINTS_PER_WAVE
 #define CDE_GRID32_POINTS_PER_WAVE 4
 #endif
+
+constexpr float GRID_BIAS = 32.f;
 
 template <int DX, int DY, int PW>
 __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ pts,
@@ -397,6 +407,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
     const double m_i = nn[di], my_i = nn[npad + di];
     const float ca = ga.cx[ab * 16 + (lane & 15)];
     const float cb = ga.cy[bb * 16 + (lane & 15)];
+    const float bias = vreg(GRID_BIAS);  // in a VGPR: the subtraction stays VOP2
 
     v4f acc[PW];
     Kahan<float> tot[PW][4], dtot[PW];
@@ -433,10 +444,11 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
             }
             const int xai = __float_as_int(xa), yai = __float_as_int(ya);
             Unroll<16>::run([&](auto c) {
+#pragma clang fp contract(off)  // DPP-fed v_mul_f32, then a VGPR-only v_sub_f32
                 constexpr int idx = decltype(c)::value;  // idx = PW s + q
                 constexpr int q = idx % PW;
-                const float ex = exp2_<float>(-(row_bcast<idx>(xai) * ca));
-                const float ey = exp2_<float>(-(row_bcast<idx>(yai) * cb));
+                const float ex = exp2_<float>(bias - row_bcast<idx>(xai) * ca);
+                const float ey = exp2_<float>(bias - row_bcast<idx>(yai) * cb);
                 acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ex, ey, acc[q], 0, 0, 0);
                 dpart[q] += ex;
             });
@@ -457,7 +469,8 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
         for (int r = 0; r < 4; ++r) {
             const int a = ab * 16 + 4 * (lane >> 4) + r;
             const int b = bb * 16 + (lane & 15);
-            if (a < ga.gx && b < ga.gy) numbuf[((size_t)a * ga.gy + b) * npad + i0 + q] = tot[q][r].value();
+            if (a < ga.gx && b < ga.gy)
+                numbuf[((size_t)a * ga.gy + b) * npad + i0 + q] = (double)tot[q][r].value() * 0x1p-64;
         }
     }
     if (do_den) {
@@ -467,7 +480,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
             v += __shfl_xor(v, 16, 64);
             v += __shfl_xor(v, 32, 64);
             const int a = ab * 16 + (lane & 15);
-            if (lane < 16 && a < ga.gx) denbuf[(size_t)a * npad + i0 + q] = v;
+            if (lane < 16 && a < ga.gx) denbuf[(size_t)a * npad + i0 + q] = v * 0x1p-32;
         }
     }
 }
@@ -483,7 +496,7 @@ struct GridFin {
 // Per (setting, point) finalisation in FP64; entries whose shifted num' is
 // too small for FP32 to have carried it are queued for the exact fixup.
 // flag_points != NULL (after the FP32 pass): mark points with a cell below
-// 2^-80; otherwise queue entries below 2^-1000 for the per-entry fixup.
+// 2^-130; otherwise queue entries below 2^-1000 for the per-entry fixup.
 __global__ void k_grid_finalize(const double* __restrict__ numbuf, const double* __restrict__ denbuf,
                                 const double* __restrict__ nn, int n, int npad, GridFin gf, int crit,
                                 double* __restrict__ ell, int* __restrict__ fix_count,
@@ -505,7 +518,7 @@ __global__ void k_grid_finalize(const double* __restrict__ numbuf, const double*
             log((double)(n - 1));
     ell[(size_t)g * npad + i] = v;
     if (flag_points) {
-        if (!(num >= 0x1p-80)) flag_points[i] = 1;
+        if (!(num >= 0x1p-130)) flag_points[i] = 1;
     } else if (!(num >= 0x1p-1000)) {
         const int slot = atomicAdd(fix_count, 1);
         if (slot < fix_cap) fix_list[slot] = make_int2(g, i);
