@@ -164,6 +164,7 @@ struct GridArgs {
     float cy[64];
     int gx, gy;    // real grid sizes
     int gxp, gyp;  // padded to multiples of 16
+    int tile_of[16];  // FP32 pass: grid tile (ab * gyp/16 + bb) of each blockIdx.y
 };
 
 typedef short v4s __attribute__((ext_vector_type(4)));
@@ -360,18 +361,20 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
 
 // FP32 fast pass: the same decomposition with FP32 kernel values (plain
 // v_exp_f32), v_mfma_f32_16x16x4f32 products and sums, partial sums over a
-// 256-point j-tile folded into Kahan-compensated FP32 totals.  Every kernel
-// value carries an exact factor 2^GRID_BIAS (the exponent is biased by
-// +GRID_BIAS), removed when the totals are written: v_exp_f32 flushes
+// 256-point j-tile folded into Kahan-compensated FP32 totals.  FP32 cannot
+// carry a cell whose shifted num' falls far below 1; k_grid_finalize flags
+// the points that have such a cell and those points are recomputed by the
+// FP64 kernel above.  Such cells need both bandwidths small, so the grid
+// tile holding the smallest hx and hy runs with BIAS: every kernel value
+// carries an exact factor 2^GRID_BIAS (the exponent is biased by
+// +GRID_BIAS), removed when the totals are written.  v_exp_f32 flushes
 // results below 2^-126 to zero while the MFMA keeps denormal products, so
 // the bias moves the smallest kept kernel value from 2^-126 to
-// 2^-(149 + GRID_BIAS) (the cost: the biased exponent is rounded at
-// magnitude ~GRID_BIAS, a relative error below 2^-20 per kernel value).
-// FP32 cannot carry a cell whose shifted num' falls far below 1;
-// k_grid_finalize flags the points that have such a cell (num' < 2^-130:
-// the terms lost, each below 2^-181, then sum to at most n 2^-181, under
-// 1e-9 of the cell for n <= 2^20) and those points are recomputed by the
-// FP64 kernel above.
+// 2^-(149 + GRID_BIAS), at the cost of one subtraction per value and a
+// biased exponent rounded at magnitude ~GRID_BIAS (below 2^-20 relative
+// error per kernel value).  Flag thresholds: num' < 2^-130 in a biased tile
+// (the terms lost, each below 2^-181, sum to at most n 2^-181, under 1e-9 of
+// the cell for n <= 2^20), num' < 2^-80 elsewhere (n 2^-126 / 2^-80).
 // Points per wave of the FP32 pass (4 or 8): fewer points per wave means
 // fewer accumulator registers and more resident waves to hide the latency of
 // each exponential feeding an MFMA.
@@ -381,7 +384,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
 
 constexpr float GRID_BIAS = 32.f;
 
-template <int DX, int DY, int PW>
+template <int DX, int DY, int PW, bool BIAS>
 __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ pts,
                                                      const double* __restrict__ nn, int n, int npad,
                                                      GridArgs ga, double* __restrict__ numbuf,
@@ -394,7 +397,8 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i0 = blockIdx.x * (4 * PW) + wave * PW;
     const int tb = ga.gyp / 16;
-    const int ab = blockIdx.y / tb, bb = blockIdx.y % tb;
+    const int tile_id = ga.tile_of[blockIdx.y];
+    const int ab = tile_id / tb, bb = tile_id % tb;
     const bool do_den = (bb == 0);
     // distance role: lane = 16 r + PW s + q forms point i0 + q against row
     // group*JG + 4 s + r; a row broadcast of position PW s + q then gives
@@ -407,7 +411,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
     const double m_i = nn[di], my_i = nn[npad + di];
     const float ca = ga.cx[ab * 16 + (lane & 15)];
     const float cb = ga.cy[bb * 16 + (lane & 15)];
-    const float bias = vreg(GRID_BIAS);  // in a VGPR: the subtraction stays VOP2
+    const float bias = vreg(BIAS ? GRID_BIAS : 0.f);  // in a VGPR: the subtraction stays VOP2
 
     v4f acc[PW];
     Kahan<float> tot[PW][4], dtot[PW];
@@ -447,8 +451,14 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
 #pragma clang fp contract(off)  // DPP-fed v_mul_f32, then a VGPR-only v_sub_f32
                 constexpr int idx = decltype(c)::value;  // idx = PW s + q
                 constexpr int q = idx % PW;
-                const float ex = exp2_<float>(bias - row_bcast<idx>(xai) * ca);
-                const float ey = exp2_<float>(bias - row_bcast<idx>(yai) * cb);
+                float ex, ey;
+                if constexpr (BIAS) {
+                    ex = exp2_<float>(bias - row_bcast<idx>(xai) * ca);
+                    ey = exp2_<float>(bias - row_bcast<idx>(yai) * cb);
+                } else {
+                    ex = exp2_<float>(-(row_bcast<idx>(xai) * ca));
+                    ey = exp2_<float>(-(row_bcast<idx>(yai) * cb));
+                }
                 acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ex, ey, acc[q], 0, 0, 0);
                 dpart[q] += ex;
             });
@@ -470,7 +480,8 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
             const int a = ab * 16 + 4 * (lane >> 4) + r;
             const int b = bb * 16 + (lane & 15);
             if (a < ga.gx && b < ga.gy)
-                numbuf[((size_t)a * ga.gy + b) * npad + i0 + q] = (double)tot[q][r].value() * 0x1p-64;
+                numbuf[((size_t)a * ga.gy + b) * npad + i0 + q] =
+                    (double)tot[q][r].value() * (BIAS ? 0x1p-64 : 1.0);
         }
     }
     if (do_den) {
@@ -480,7 +491,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
             v += __shfl_xor(v, 16, 64);
             v += __shfl_xor(v, 32, 64);
             const int a = ab * 16 + (lane & 15);
-            if (lane < 16 && a < ga.gx) denbuf[(size_t)a * npad + i0 + q] = v * 0x1p-32;
+            if (lane < 16 && a < ga.gx) denbuf[(size_t)a * npad + i0 + q] = v * (BIAS ? 0x1p-32 : 1.0);
         }
     }
 }
@@ -491,12 +502,15 @@ struct GridFin {
     double log_cx[64];
     double log_cy[64];
     int gx, gy;
+    int tb;             // grid tiles per row (gyp / 16)
+    unsigned biased;    // bit t: tile t ran the FP32 pass with biased exponents
 };
 
 // Per (setting, point) finalisation in FP64; entries whose shifted num' is
 // too small for FP32 to have carried it are queued for the exact fixup.
 // flag_points != NULL (after the FP32 pass): mark points with a cell below
-// 2^-130; otherwise queue entries below 2^-1000 for the per-entry fixup.
+// its tile's threshold (2^-130 biased, 2^-80 otherwise); otherwise queue
+// entries below 2^-1000 for the per-entry fixup.
 __global__ void k_grid_finalize(const double* __restrict__ numbuf, const double* __restrict__ denbuf,
                                 const double* __restrict__ nn, int n, int npad, GridFin gf, int crit,
                                 double* __restrict__ ell, int* __restrict__ fix_count,
@@ -518,7 +532,9 @@ __global__ void k_grid_finalize(const double* __restrict__ numbuf, const double*
             log((double)(n - 1));
     ell[(size_t)g * npad + i] = v;
     if (flag_points) {
-        if (!(num >= 0x1p-130)) flag_points[i] = 1;
+        const int t = (a / 16) * gf.tb + b / 16;
+        const double lim = (gf.biased >> t) & 1u ? 0x1p-130 : 0x1p-80;
+        if (!(num >= lim)) flag_points[i] = 1;
     } else if (!(num >= 0x1p-1000)) {
         const int slot = atomicAdd(fix_count, 1);
         if (slot < fix_cap) fix_list[slot] = make_int2(g, i);
@@ -681,10 +697,25 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
         hipLaunchKernelGGL(k_zero_int, dim3((npad + 255) / 256), dim3(256), 0, stream, w.flags, npad);
         hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, w.pcount, 1);
         constexpr int PW = CDE_GRID32_POINTS_PER_WAVE;
-        const dim3 grid32((unsigned)(npad / (4 * PW)), (unsigned)tiles);
-        hipLaunchKernelGGL((k_loo_grid32<DX, DY, PW>), grid32, dim3(TILE), 0, stream, pts, nn, n, npad,
-                           ga, w.numbuf, w.denbuf);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // the biased tile, then the others (GridFin::biased marks which)
+        GridArgs gb = ga, gu = ga;
+        int nb_ = 0, nu_ = 0;
+        for (int t = 0; t < tiles; ++t) {
+            if ((gf.biased >> t) & 1u)
+                gb.tile_of[nb_++] = t;
+            else
+                gu.tile_of[nu_++] = t;
+        }
+        if (nb_ > 0) {
+            hipLaunchKernelGGL((k_loo_grid32<DX, DY, PW, true>), dim3((unsigned)(npad / (4 * PW)), (unsigned)nb_),
+                               dim3(TILE), 0, stream, pts, nn, n, npad, gb, w.numbuf, w.denbuf);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        if (nu_ > 0) {
+            hipLaunchKernelGGL((k_loo_grid32<DX, DY, PW, false>), dim3((unsigned)(npad / (4 * PW)), (unsigned)nu_),
+                               dim3(TILE), 0, stream, pts, nn, n, npad, gu, w.numbuf, w.denbuf);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         hipLaunchKernelGGL(k_grid_finalize, fgrid, dim3(256), 0, stream, (const double*)w.numbuf,
                            (const double*)w.denbuf, nn, n, npad, gf, crit, w.ell, w.fix_count,
                            w.fix_list, w.fix_cap, w.flags);
@@ -751,6 +782,18 @@ hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* h
         ga.cy[b] = (float)(LOG2E / (2.0 * h * h));
         gf.cyb[b] = (double)ga.cy[b];
         gf.log_cy[b] = -m->dy * (log(h) + HALF_LOG_2PI);
+    }
+    // The FP32 pass biases the grid tile that holds the smallest hx and the
+    // smallest hy (the only cells that can fall far below 1 need both small).
+    gf.tb = ga.gyp / 16;
+    {
+        int amin = 0, bmin = 0;
+        for (int a = 1; a < n_hx; ++a)
+            if (hx[a] < hx[amin]) amin = a;
+        for (int b = 1; b < n_hy; ++b)
+            if (hy[b] < hy[bmin]) bmin = b;
+        gf.biased = 1u << ((amin / 16) * gf.tb + bmin / 16);
+        for (int t = 0; t < 16; ++t) ga.tile_of[t] = t;
     }
     const size_t G = (size_t)n_hx * n_hy;
     // work layout: numbuf [G][npad] | denbuf [gx][npad] | ell [G][npad] |
