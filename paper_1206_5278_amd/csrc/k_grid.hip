@@ -122,7 +122,18 @@ __device__ __forceinline__ void own_f64(double (&dst)[S], const float* src)
     for (int q = 0; q < S; ++q) dst[q] = (double)t[q];
 }
 
-// Per point: nearest-neighbour squared distances in x and in y, j != i.
+// Per point: nearest-neighbour squared distances in x and in y, j != i,
+// exactly as the FP64 formula of dist2 gives them.  Every pair is screened
+// in FP32 against the running FP32 minimum; only candidates within a factor
+// NN_TOL of it (or tiny ones, where FP32 loses relative accuracy) take the
+// FP64 formula.  The FP32 distance of any pair is within a relative
+// (1 +- eps), eps < 2^-18 for 18 dimensions, of its FP64 value, so the FP64
+// nearest neighbour j* satisfies d32(j*) <= (1+eps)/(1-eps) min_j d32(j)
+// <= NN_TOL times the running minimum when it is reached: it is always a
+// candidate, and the result equals the plain FP64 minimum.
+constexpr float NN_TOL = 1.0f + 0x1p-10f;
+constexpr float NN_TINY = 0x1p-100f;
+
 template <int DX, int DY>
 __global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int n,
                                              double* __restrict__ nn, int npad)
@@ -131,8 +142,12 @@ __global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int 
     __shared__ float tile[TILE * S];
     const int tid = threadIdx.x;
     const int i = blockIdx.x * TILE + tid;
+    float own32[S];
+    load_row<S>(own32, pts + (size_t)i * S);
     double own[S];
-    own_f64<S>(own, pts + (size_t)i * S);
+#pragma unroll
+    for (int q = 0; q < S; ++q) own[q] = (double)own32[q];
+    float sx = inf_<float>(), sy = inf_<float>();
     double mx = inf_<double>(), my = inf_<double>();
     const int ntiles = (n + TILE - 1) / TILE;
     for (int t = 0; t < ntiles; ++t) {
@@ -144,13 +159,30 @@ __global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int 
         const int cnt = min(TILE, n - t * TILE);
         const int self = (t == (int)blockIdx.x) ? tid : -1;
         for (int q = 0; q < cnt; ++q) {
+            if (q == self) continue;
             float pj[S];
             load_row<S>(pj, tile + q * S);
-            double a, b;
-            dist2<DX, DY>(own, pj, a, b);
-            if (q == self) continue;
-            mx = min_(mx, a);
-            my = min_(my, b);
+            float ex = 0.f, ey = 0.f;
+#pragma unroll
+            for (int k = 0; k < DX; ++k) {
+                const float d = own32[k] - pj[k];
+                ex = fma_(d, d, ex);
+            }
+#pragma unroll
+            for (int l = 0; l < DY; ++l) {
+                const float d = own32[DX + l] - pj[DX + l];
+                ey = fma_(d, d, ey);
+            }
+            const bool cx = ex <= sx * NN_TOL || ex < NN_TINY;
+            const bool cy = ey <= sy * NN_TOL || ey < NN_TINY;
+            sx = min_(sx, ex);
+            sy = min_(sy, ey);
+            if (cx || cy) {
+                double a, b;
+                dist2<DX, DY>(own, pj, a, b);
+                if (cx) mx = min_(mx, a);
+                if (cy) my = min_(my, b);
+            }
         }
     }
     nn[i] = mx;
