@@ -141,4 +141,23 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* [4][NV
     }
 }
 
+// Exact FP64 minimum of a squared distance over a stream of points, with an
+// FP32 screen: a point is a candidate (its FP64 distance is taken) when its
+// FP32 distance is within a factor 1 + 2^-10 of the running FP32 minimum, or
+// tiny.  An FP32 distance formed from the same FP32 inputs (differences,
+// squares and weights rounded to FP32) lies within a relative 2^-18 of the
+// FP64 value for up to 18 dimensions, so the FP64 minimiser j* satisfies
+// d32(j*) <= (1 + 2^-18) / (1 - 2^-18) min_j d32(j), below the factor times
+// any running minimum: it is always a candidate, and the minimum over the
+// candidates equals the plain FP64 minimum.
+struct ScreenedMin {
+    float s = __builtin_inff();
+    __device__ __forceinline__ bool candidate(float d32)
+    {
+        const bool c = d32 <= s * (1.0f + 0x1p-10f) || d32 < 0x1p-100f;
+        s = __builtin_fminf(s, d32);
+        return c;
+    }
+};
+
 }  // namespace cde

@@ -124,15 +124,9 @@ __device__ __forceinline__ void own_f64(double (&dst)[S], const float* src)
 
 // Per point: nearest-neighbour squared distances in x and in y, j != i,
 // exactly as the FP64 formula of dist2 gives them.  Every pair is screened
-// in FP32 against the running FP32 minimum; only candidates within a factor
-// NN_TOL of it (or tiny ones, where FP32 loses relative accuracy) take the
-// FP64 formula.  The FP32 distance of any pair is within a relative
-// (1 +- eps), eps < 2^-18 for 18 dimensions, of its FP64 value, so the FP64
-// nearest neighbour j* satisfies d32(j*) <= (1+eps)/(1-eps) min_j d32(j)
-// <= NN_TOL times the running minimum when it is reached: it is always a
-// candidate, and the result equals the plain FP64 minimum.
-constexpr float NN_TOL = 1.0f + 0x1p-10f;
-constexpr float NN_TINY = 0x1p-100f;
+// in FP32 (ScreenedMin, cde_device.h): only candidates near the running
+// FP32 minimum take the FP64 formula, and the FP64 nearest neighbour is
+// always one of them, so the result equals the plain FP64 minimum.
 
 template <int DX, int DY>
 __global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int n,
@@ -147,7 +141,7 @@ __global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int 
     double own[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) own[q] = (double)own32[q];
-    float sx = inf_<float>(), sy = inf_<float>();
+    ScreenedMin sx, sy;
     double mx = inf_<double>(), my = inf_<double>();
     const int ntiles = (n + TILE - 1) / TILE;
     for (int t = 0; t < ntiles; ++t) {
@@ -173,10 +167,8 @@ __global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int 
                 const float d = own32[DX + l] - pj[DX + l];
                 ey = fma_(d, d, ey);
             }
-            const bool cx = ex <= sx * NN_TOL || ex < NN_TINY;
-            const bool cy = ey <= sy * NN_TOL || ey < NN_TINY;
-            sx = min_(sx, ex);
-            sy = min_(sy, ey);
+            const bool cx = sx.candidate(ex);
+            const bool cy = sy.candidate(ey);
             if (cx || cy) {
                 double a, b;
                 dist2<DX, DY>(own, pj, a, b);

@@ -22,6 +22,7 @@
 //     inverse of G is found with a pointer that only moves forward, since the
 //     targets increase along each scan.
 #include <algorithm>
+#include <type_traits>
 
 #include "cde_device.h"
 #include "cde_kernels.h"
@@ -71,8 +72,14 @@ __global__ __launch_bounds__(TILE) void k_cmean_shift(const T* __restrict__ pts,
     const int e = blockIdx.x * TILE + tid;
     const int ec = e < q ? e : q - 1;
     double xo[DX];
+    float xo32[DX], c32[DX];
 #pragma unroll
-    for (int k = 0; k < DX; ++k) xo[k] = (double)xq[(size_t)ec * DX + k];
+    for (int k = 0; k < DX; ++k) {
+        xo[k] = (double)xq[(size_t)ec * DX + k];
+        xo32[k] = (float)xq[(size_t)ec * DX + k];
+        c32[k] = (float)a.cx[k];
+    }
+    ScreenedMin screen;
     double best = __builtin_inf();
     const int j0 = blockIdx.y * chunk, j1 = min(n, j0 + chunk);
     for (int t0 = j0; t0 < j1; t0 += TILE) {
@@ -82,7 +89,23 @@ __global__ __launch_bounds__(TILE) void k_cmean_shift(const T* __restrict__ pts,
         store_row<S>(tile + tid * S, pre);
         __syncthreads();
         const int cnt = min(TILE, j1 - t0);
-        for (int j = 0; j < cnt; ++j) best = fmin(best, xdist<T, DX>(xo, tile + j * S, a));
+        if constexpr (std::is_same<T, float>::value) {
+            // FP32 screening against the running FP32 minimum; the FP64
+            // distance is taken for every candidate, so best is exactly the
+            // FP64 minimum (ScreenedMin, cde_device.h)
+            for (int j = 0; j < cnt; ++j) {
+                const float* pj = tile + j * S;
+                float e32 = 0.f;
+#pragma unroll
+                for (int k = 0; k < DX; ++k) {
+                    const float d = xo32[k] - pj[k];
+                    e32 = fmaf(d * d, c32[k], e32);
+                }
+                if (screen.candidate(e32)) best = fmin(best, xdist<T, DX>(xo, pj, a));
+            }
+        } else {
+            for (int j = 0; j < cnt; ++j) best = fmin(best, xdist<T, DX>(xo, tile + j * S, a));
+        }
     }
     if (e < q) atomic_min_nonneg_d(mq + e, best);
 }

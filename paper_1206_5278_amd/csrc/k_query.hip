@@ -135,24 +135,47 @@ __global__ __launch_bounds__(TILE) void k_qshift_x(const float* __restrict__ pts
                                                    const float* __restrict__ xq, int q,
                                                    QueryArgs qa, double* __restrict__ mq)
 {
-    constexpr int S = row_stride(DX, DY), SD = DX + DY;
-    __shared__ double tile[TILE * SD];
+    constexpr int S = row_stride(DX, DY);
+    __shared__ float tile[TILE * S];
     const int tid = threadIdx.x;
     const int e = blockIdx.x * TILE + tid;
     const int ec = e < q ? e : q - 1;
     double xo[DX];
+    float xo32[DX], c32[DX];
 #pragma unroll
-    for (int k = 0; k < DX; ++k) xo[k] = (double)xq[(size_t)ec * DX + k];
+    for (int k = 0; k < DX; ++k) {
+        xo32[k] = xq[(size_t)ec * DX + k];
+        xo[k] = (double)xo32[k];
+        c32[k] = (float)qa.cx[k];
+    }
+    ScreenedMin screen;  // FP32 screen, exact FP64 minimum (cde_device.h)
     double best = inf_<double>();
     const int j0 = blockIdx.y * chunk, j1 = min(n, j0 + chunk);
     for (int t0 = j0; t0 < j1; t0 += TILE) {
         __syncthreads();
         float pre[S];
         load_row<S>(pre, pts + ((size_t)t0 + tid) * S);
-        stage_tile_d<DX, DY>(tile, pre, tid);
+        store_row<S>(tile + tid * S, pre);
         __syncthreads();
         const int cnt = min(TILE, j1 - t0);
-        for (int j = 0; j < cnt; ++j) best = min_(best, xdist2<DX>(xo, tile + j * SD, qa));
+        for (int j = 0; j < cnt; ++j) {
+            const float* pj = tile + j * S;
+            float e32 = 0.f;
+#pragma unroll
+            for (int k = 0; k < DX; ++k) {
+                const float d = xo32[k] - pj[k];
+                e32 = fmaf(d * d, c32[k], e32);
+            }
+            if (screen.candidate(e32)) {
+                double d2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < DX; ++k) {
+                    const double d = xo[k] - (double)pj[k];
+                    d2 = fma_(d * d, qa.cx[k], d2);
+                }
+                best = min_(best, d2);
+            }
+        }
     }
     if (e < q) atomic_min_nonneg(mq + e, best);
 }
