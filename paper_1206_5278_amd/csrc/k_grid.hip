@@ -123,10 +123,12 @@ __device__ __forceinline__ void own_f64(double (&dst)[S], const float* src)
 }
 
 // Per point: nearest-neighbour squared distances in x and in y, j != i,
-// exactly as the FP64 formula of dist2 gives them.  Every pair is screened
-// in FP32 (ScreenedMin, cde_device.h): only candidates near the running
-// FP32 minimum take the FP64 formula, and the FP64 nearest neighbour is
-// always one of them, so the result equals the plain FP64 minimum.
+// exactly as the FP64 formula of dist2 gives them.  From 10 dimensions on,
+// every pair is first screened in FP32 (ScreenedMin, cde_device.h): only
+// candidates near the running FP32 minimum take the FP64 formula, and the
+// FP64 nearest neighbour is always one of them, so the result equals the
+// plain FP64 minimum.  (In fewer dimensions the screen's compares, minima
+// and branch cost more than the FP64 formula it saves.)
 
 template <int DX, int DY>
 __global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int n,
@@ -156,6 +158,13 @@ __global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int 
             if (q == self) continue;
             float pj[S];
             load_row<S>(pj, tile + q * S);
+            if constexpr (DX + DY < 10) {
+                double a, b;
+                dist2<DX, DY>(own, pj, a, b);
+                mx = min_(mx, a);
+                my = min_(my, b);
+                continue;
+            }
             float ex = 0.f, ey = 0.f;
 #pragma unroll
             for (int k = 0; k < DX; ++k) {
@@ -189,6 +198,7 @@ struct GridArgs {
     int gx, gy;    // real grid sizes
     int gxp, gyp;  // padded to multiples of 16
     int tile_of[16];  // FP32 pass: grid tile (ab * gyp/16 + bb) of each blockIdx.y
+    int bias_ta, bias_tb;  // FP32 pass: the biased tile's a-tile and b-tile indices
 };
 
 typedef short v4s __attribute__((ext_vector_type(4)));
@@ -520,6 +530,151 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
     }
 }
 
+// The FP32 pass for grids of at least 32 x 32 cells (both padded sides
+// multiples of 32): a block owns a 2 x 2 quad of 16 x 16 grid tiles.  Per
+// 4-point MFMA step a lane forms ex for its two a-tiles and ey for its two
+// b-tiles (4 exponentials) and issues the 4 tile products, where one tile
+// per block would form 2 exponentials per product; the FP64 distances are
+// formed once per quad instead of once per tile.  Exponent biases are per
+// a-tile and per b-tile (32 for the tile of the smallest hx, resp. hy, else
+// 0); each tile's totals are unscaled by its own factor, and the flag
+// thresholds of k_grid_finalize (2^-130 for the tile biased on both sides,
+// 2^-80 elsewhere) hold as for k_loo_grid32.
+template <int DX, int DY, int PW>
+__global__ __launch_bounds__(TILE) void k_loo_grid32q(const float* __restrict__ pts,
+                                                      const double* __restrict__ nn, int n, int npad,
+                                                      GridArgs ga, double* __restrict__ numbuf,
+                                                      double* __restrict__ denbuf)
+{
+    static_assert(PW == 2 || PW == 4, "2 or 4 points per wave");
+    constexpr int S = row_stride(DX, DY);
+    constexpr int JG = 64 / PW;  // tile rows per distance group
+    __shared__ float tile[TILE * S];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i0 = blockIdx.x * (4 * PW) + wave * PW;
+    const int tqb = ga.gyp / 32;
+    const int qa = blockIdx.y / tqb, qb = blockIdx.y % tqb;
+    const bool do_den = (qb == 0);
+    const int pos = lane & 15;
+    const int di = i0 + (pos % PW);
+    const int jo = 4 * (pos / PW) + (lane >> 4);
+    double own[S];
+    own_f64<S>(own, pts + (size_t)di * S);
+    const double m_i = nn[di], my_i = nn[npad + di];
+    float ca[2], cb[2], bx[2], by[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        ca[t] = ga.cx[(2 * qa + t) * 16 + (lane & 15)];
+        cb[t] = ga.cy[(2 * qb + t) * 16 + (lane & 15)];
+        bx[t] = vreg(2 * qa + t == ga.bias_ta ? GRID_BIAS : 0.f);
+        by[t] = vreg(2 * qb + t == ga.bias_tb ? GRID_BIAS : 0.f);
+    }
+
+    v4f acc[PW][4];  // tile (ta, tb) at 2 ta + tb
+    Kahan<float> tot[PW][4][4], dtot[PW][2];
+    float dpart[PW][2];
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            acc[q][t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tot[q][t][r].zero();
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            dpart[q][t] = 0.f;
+            dtot[q][t].zero();
+        }
+    }
+    const int ntiles = (n + TILE - 1) / TILE;
+    float pre[S];
+    load_row<S>(pre, pts + (size_t)tid * S);
+    for (int t = 0; t < ntiles; ++t) {
+        __syncthreads();
+        store_row<S>(tile + tid * S, pre);
+        __syncthreads();
+        if (t + 1 < ntiles) load_row<S>(pre, pts + ((size_t)(t + 1) * TILE + tid) * S);
+        const int base = t * TILE;
+        const int cnt = min(TILE, n - base);
+        const int ngroups = (cnt + JG - 1) / JG;
+        for (int g = 0; g < ngroups; ++g) {
+            const int jj = g * JG + jo;
+            float pj[S];
+            load_row<S>(pj, tile + jj * S);  // jj < 256: rows >= cnt are packed padding
+            double d2x, d2y;
+            dist2<DX, DY>(own, pj, d2x, d2y);
+            float xa = (float)(d2x - m_i), ya = (float)(d2y - my_i);
+            if (jj >= cnt || base + jj == di) {
+                xa = EXCLUDED;
+                ya = EXCLUDED;
+            }
+            const int xai = __float_as_int(xa), yai = __float_as_int(ya);
+            Unroll<16>::run([&](auto c) {
+#pragma clang fp contract(off)  // v_mul_f32, then a VGPR-only v_sub_f32
+                constexpr int idx = decltype(c)::value;  // idx = PW s + q
+                constexpr int q = idx % PW;
+                const float xb = row_bcast<idx>(xai), yb = row_bcast<idx>(yai);
+                const float ex0 = exp2_<float>(bx[0] - xb * ca[0]);
+                const float ex1 = exp2_<float>(bx[1] - xb * ca[1]);
+                const float ey0 = exp2_<float>(by[0] - yb * cb[0]);
+                const float ey1 = exp2_<float>(by[1] - yb * cb[1]);
+                acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ex0, ey0, acc[q][0], 0, 0, 0);
+                acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ex0, ey1, acc[q][1], 0, 0, 0);
+                acc[q][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(ex1, ey0, acc[q][2], 0, 0, 0);
+                acc[q][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(ex1, ey1, acc[q][3], 0, 0, 0);
+                dpart[q][0] += ex0;
+                dpart[q][1] += ex1;
+            });
+        }
+#pragma unroll
+        for (int q = 0; q < PW; ++q) {
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) tot[q][tt][r].add(acc[q][tt][r]);
+                acc[q][tt] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int ta = 0; ta < 2; ++ta) {
+                dtot[q][ta].add(dpart[q][ta]);
+                dpart[q][ta] = 0.f;
+            }
+        }
+    }
+    // f32 16x16x4 result layout: register r holds row 4*(lane/16) + r; each
+    // tile's factor 2^(bx + by) (den: 2^bx) removed exactly
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            const int ta = tt >> 1, tb = tt & 1;
+            const double sc = ldexp(1.0, -(int)(bx[ta] + by[tb]));
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int a = (2 * qa + ta) * 16 + 4 * (lane >> 4) + r;
+                const int b = (2 * qb + tb) * 16 + (lane & 15);
+                if (a < ga.gx && b < ga.gy)
+                    numbuf[((size_t)a * ga.gy + b) * npad + i0 + q] = (double)tot[q][tt][r].value() * sc;
+            }
+        }
+    }
+    if (do_den) {
+#pragma unroll
+        for (int q = 0; q < PW; ++q) {
+#pragma unroll
+            for (int ta = 0; ta < 2; ++ta) {
+                double v = dtot[q][ta].value();
+                v += __shfl_xor(v, 16, 64);
+                v += __shfl_xor(v, 32, 64);
+                const int a = (2 * qa + ta) * 16 + (lane & 15);
+                if (lane < 16 && a < ga.gx)
+                    denbuf[(size_t)a * npad + i0 + q] = v * ldexp(1.0, -(int)bx[ta]);
+            }
+        }
+    }
+}
+
 struct GridFin {
     double cxa[64];   // c_a in FP64 (the same FP32 values the kernel used)
     double cyb[64];
@@ -721,6 +876,13 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
         hipLaunchKernelGGL(k_zero_int, dim3((npad + 255) / 256), dim3(256), 0, stream, w.flags, npad);
         hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, w.pcount, 1);
         constexpr int PW = CDE_GRID32_POINTS_PER_WAVE;
+        if (ga.gxp % 32 == 0 && ga.gyp % 32 == 0) {
+            constexpr int PWQ = 2;
+            const int quads = (ga.gxp / 32) * (ga.gyp / 32);
+            hipLaunchKernelGGL((k_loo_grid32q<DX, DY, PWQ>), dim3((unsigned)(npad / (4 * PWQ)), (unsigned)quads),
+                               dim3(TILE), 0, stream, pts, nn, n, npad, ga, w.numbuf, w.denbuf);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        } else {
         // the biased tile, then the others (GridFin::biased marks which)
         GridArgs gb = ga, gu = ga;
         int nb_ = 0, nu_ = 0;
@@ -739,6 +901,7 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
             hipLaunchKernelGGL((k_loo_grid32<DX, DY, PW, false>), dim3((unsigned)(npad / (4 * PW)), (unsigned)nu_),
                                dim3(TILE), 0, stream, pts, nn, n, npad, gu, w.numbuf, w.denbuf);
             if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         }
         hipLaunchKernelGGL(k_grid_finalize, fgrid, dim3(256), 0, stream, (const double*)w.numbuf,
                            (const double*)w.denbuf, nn, n, npad, gf, crit, w.ell, w.fix_count,
@@ -817,6 +980,8 @@ hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* h
         for (int b = 1; b < n_hy; ++b)
             if (hy[b] < hy[bmin]) bmin = b;
         gf.biased = 1u << ((amin / 16) * gf.tb + bmin / 16);
+        ga.bias_ta = amin / 16;
+        ga.bias_tb = bmin / 16;
         for (int t = 0; t < 16; ++t) ga.tile_of[t] = t;
     }
     const size_t G = (size_t)n_hx * n_hy;

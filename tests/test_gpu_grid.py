@@ -72,6 +72,34 @@ def test_grid_32x32_small_n():
     check(tot, pp, ref)
 
 
+@pytest.mark.parametrize("gx,gy,descending", [(17, 64, False), (64, 20, True), (33, 40, False)])
+def test_grid_quad_tiles_ragged_and_bias_placement(gx, gy, descending):
+    # grids whose padded sides are multiples of 32 run on 2 x 2 tile quads
+    # (17 x 64, 64 x 20); 33 x 40 pads to 48 x 48 and runs one tile per
+    # block.  A descending hx list puts the smallest hx (the biased a-tile)
+    # in the last tile of its quad.
+    print(f"case: grid quads n=800 {gx}x{gy} descending={descending}", flush=True)
+    x, y = workloads.gmm(800, seed=23, dx=2)
+    hx = workloads.geomspace(0.03, 4.0, gx)
+    hy = workloads.geomspace(0.03, 3.0, gy)
+    if descending:
+        hx = hx[::-1].copy()
+    _, tot, pp, nonfin, ref = run_grid(x, y, hx, hy)
+    assert nonfin == 0
+    check(tot, pp, ref)
+
+
+@pytest.mark.parametrize("dx,dy", [(1, 1), (3, 2), (8, 2), (16, 2)])
+def test_grid_quad_tiles_shapes(dx, dy):
+    print(f"case: grid quads dx={dx} dy={dy} n=300 32x32", flush=True)
+    v = workloads.gmm_general(300, dx + dy, seed=150 + dx * 10 + dy)
+    hx = workloads.geomspace(0.1, 4.0, 32)
+    hy = workloads.geomspace(0.05, 2.0, 32)
+    _, tot, pp, nonfin, ref = run_grid(v[:, :dx], v[:, dx:], hx, hy)
+    assert nonfin == 0
+    check(tot, pp, ref)
+
+
 def test_grid_tiny_bandwidths_wide_range_and_fixup():
     # Largest terms hundreds to thousands of binary orders below the
     # neighbour shifts: exercises the wide-range kernel values and the exact
