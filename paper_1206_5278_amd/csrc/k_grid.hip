@@ -154,17 +154,22 @@ __global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int 
         __syncthreads();
         const int cnt = min(TILE, n - t * TILE);
         const int self = (t == (int)blockIdx.x) ? tid : -1;
+        if constexpr (DX + DY < 10) {
+            for (int q = 0; q < cnt; ++q) {
+                float pj[S];
+                load_row<S>(pj, tile + q * S);
+                double a, b;
+                dist2<DX, DY>(own, pj, a, b);
+                if (q == self) continue;
+                mx = min_(mx, a);
+                my = min_(my, b);
+            }
+            continue;
+        }
         for (int q = 0; q < cnt; ++q) {
             if (q == self) continue;
             float pj[S];
             load_row<S>(pj, tile + q * S);
-            if constexpr (DX + DY < 10) {
-                double a, b;
-                dist2<DX, DY>(own, pj, a, b);
-                mx = min_(mx, a);
-                my = min_(my, b);
-                continue;
-            }
             float ex = 0.f, ey = 0.f;
 #pragma unroll
             for (int k = 0; k < DX; ++k) {
