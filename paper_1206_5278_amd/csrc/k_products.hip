@@ -17,10 +17,11 @@
 //     holding 1 - alpha of the grid's piecewise-linear CDF G, over candidates
 //     with one end on a grid node (lower ends first, then upper ends), the
 //     first of least width (a later one replaces it only when narrower by
-//     more than 1e-12 of the span).  One thread per row runs the scan
-//     sequentially, so the result does not depend on any reduction order; the
-//     inverse of G is found with a pointer that only moves forward, since the
-//     targets increase along each scan.
+//     more than 1e-12 of the span).  One wave per row: the running sums and
+//     the tie rule's scan over the candidates stay sequential (lane 0, in the
+//     scalar order), the candidates are evaluated by all lanes, and the
+//     inverse of the (non-decreasing) grid CDF is a binary search that finds
+//     the node the scalar definition's forward-moving pointer finds.
 #include <algorithm>
 #include <type_traits>
 
@@ -169,69 +170,170 @@ __global__ void k_cmean_reduce(const double* __restrict__ part, int q, int dy, i
     for (int l = 0; l < dy; ++l) mean[(size_t)e * dy + l] = Sy[l] / D;
 }
 
-// Density summary, one thread per row (see the file header).
-__global__ void k_density_summary(const double* __restrict__ f, const double* __restrict__ yg, int q,
-                                  int k, double alpha, double* __restrict__ out)
+// Density summary, one wave per row (see the file header).  Rows are
+// densities (f >= 0), so the grid CDF C[g] / mass is non-decreasing: the
+// inverse the scalar definition finds with a pointer that only moves
+// forward is the first node g with C[g] / mass >= target (at most k - 1),
+// found here by a binary search over the same values.  What decides bits
+// stays sequential: lane 0 forms the running sums C[g] in the scalar order
+// (the same additions as the mass), and lane 0 scans the candidate widths
+// in candidate order for the tie rule.  The mode is a first-index argmax
+// over the wave (exact).  Candidate evaluation runs on all 64 lanes.
+// LDS per block: yg [k], then per row C [k] and the candidate widths [2k].
+__device__ __forceinline__ int first_at_least(const double* G, int k, double target)
+{
+    // smallest g in [0, k-1) with G[g] >= target, else k - 1
+    int lo = 0, hi = k - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (G[mid] < target)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Interval of candidate c (c < k: lower end on node c; else upper end on
+// node c - k) on the grid CDF G[g] = C[g] / mass (the quotients the scalar
+// definition forms); returns false when the candidate is not admitted.
+__device__ __forceinline__ bool summary_candidate(const double* G, const double* yg, int k, double cover,
+                                                  int c, double& lo, double& hi)
+{
+#pragma clang fp contract(off)
+    const int pass = c >= k, a = pass ? c - k : c;
+    const double Ga = G[a];
+    const double target = pass == 0 ? Ga + cover : Ga - cover;
+    if (pass == 0 && target > 1.0) return false;
+    if (pass == 1 && target < 0.0) return false;
+    const int ptr = first_at_least(G, k, target);
+    const double Gp = G[ptr], Gpm = ptr > 0 ? G[ptr - 1] : 0.0;
+    double y;
+    if (ptr == 0 || Gp <= Gpm)
+        y = yg[ptr];
+    else
+        y = yg[ptr - 1] + (target - Gpm) / (Gp - Gpm) * (yg[ptr] - yg[ptr - 1]);
+    lo = pass == 0 ? yg[a] : y;
+    hi = pass == 0 ? y : yg[a];
+    return true;
+}
+
+// LDS of the summary kernel (doubles, sized per launch): the y grid [k]
+// when YLDS (k <= 2048; larger grids are read from global memory), then per
+// row the running sums C [k] and one chunk of candidate widths [SUMMARY_WCH].
+constexpr int SUMMARY_WCH = 256;
+
+// Within one wave: LDS writes of some lanes are visible to the reads that
+// follow them in program order.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool YLDS>
+__global__ __launch_bounds__(256) void k_density_summary(const double* __restrict__ f,
+                                                         const double* __restrict__ yg, int q, int k,
+                                                         int rows_per_block, double alpha,
+                                                         double* __restrict__ out)
 {
 #pragma clang fp contract(off)  // the same roundings as the plain scalar definition
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    extern __shared__ double sm[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double* ysh = yg;
+    if (YLDS) {
+        for (int g = tid; g < k; g += blockDim.x) sm[g] = yg[g];
+        ysh = sm;
+    }
+    __syncthreads();  // the only block-wide barrier: everything below is per wave
+    const int row = blockIdx.x * rows_per_block + wave;
     if (row >= q) return;
+    double* C = sm + (YLDS ? k : 0) + (size_t)wave * (k + SUMMARY_WCH);
+    double* wid = C + k;
     const double* r = f + (size_t)row * k;
     double* o = out + (size_t)row * 4;
-    // mass and mode
-    double c = 0.0;
-    int imax = 0;
-    double fmax_ = r[0];
-    for (int g = 0; g + 1 < k; ++g) {
-        c += (r[g] + r[g + 1]) * 0.5 * (yg[g + 1] - yg[g]);
-        if (r[g + 1] > fmax_) {
-            fmax_ = r[g + 1];
-            imax = g + 1;
+    // stage the row (coalesced)
+    for (int g = lane; g < k; g += 64) C[g] = r[g];
+    wave_sync();
+    // mode: first index of the maximum, as the scalar scan from r[0] finds it
+    double bv = -__builtin_inf();
+    int bi = 0;
+    for (int g = lane; g < k; g += 64) {
+        const double v = C[g];
+        if (v > bv) {
+            bv = v;
+            bi = g;
         }
     }
-    const double mass = c;
-    o[0] = mass;
-    o[1] = yg[imax];
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    const double r0 = C[0];
+    // the scalar scan starts at r[0] and moves only on a strictly larger value
+    const int imax = (r0 != r0 || !(bv > r0)) ? 0 : bi;
+    wave_sync();
+    // running sums in the scalar order, in place (lane 0)
+    if (lane == 0) {
+        double c = 0.0, prev = C[0];
+        C[0] = 0.0;
+#pragma unroll 8
+        for (int g = 0; g + 1 < k; ++g) {
+            const double cur = C[g + 1];
+            c += (prev + cur) * 0.5 * (ysh[g + 1] - ysh[g]);
+            C[g + 1] = c;
+            prev = cur;
+        }
+    }
+    wave_sync();
+    const double mass = C[k - 1];
+    if (lane == 0) {
+        o[0] = mass;
+        o[1] = ysh[imax];
+    }
     if (!(mass > 0.0)) {
-        o[2] = o[3] = __builtin_nan("");
+        if (lane == 0) o[2] = o[3] = __builtin_nan("");
         return;
     }
+    wave_sync();  // every lane holds mass before C becomes G
+    for (int g = lane; g < k; g += 64) C[g] = C[g] / mass;
+    wave_sync();
     const double cover = 1.0 - alpha;
-    const double tie = 1e-12 * (yg[k - 1] - yg[0]);
-    double best = __builtin_inf(), blo = __builtin_nan(""), bhi = __builtin_nan("");
-    // running cumulative sums (the same sequence of additions as the mass)
-    // at the scan position a and at the inverse pointer p (and p - 1)
-    for (int pass = 0; pass < 2; ++pass) {
-        double ca = 0.0, cp = 0.0, cpm = 0.0;
-        int ptr = 0;
-        for (int a = 0; a < k; ++a) {
-            if (a > 0) ca += (r[a - 1] + r[a]) * 0.5 * (yg[a] - yg[a - 1]);
-            const double Ga = ca / mass;
-            const double target = pass == 0 ? Ga + cover : Ga - cover;
-            if (pass == 0 && target > 1.0) break;
-            if (pass == 1 && target < 0.0) continue;
-            // first index g with G_g >= target (g < k - 1 bound, as a scan from 0)
-            while (ptr < k - 1 && cp / mass < target) {
-                cpm = cp;
-                cp += (r[ptr] + r[ptr + 1]) * 0.5 * (yg[ptr + 1] - yg[ptr]);
-                ++ptr;
-            }
-            const double Gp = cp / mass, Gpm = cpm / mass;
-            double y;
-            if (ptr == 0 || Gp <= Gpm)
-                y = yg[ptr];
-            else
-                y = yg[ptr - 1] + (target - Gpm) / (Gp - Gpm) * (yg[ptr] - yg[ptr - 1]);
-            const double lo = pass == 0 ? yg[a] : y, hi = pass == 0 ? y : yg[a];
-            if (hi - lo < best - tie) {
-                best = hi - lo;
-                blo = lo;
-                bhi = hi;
+    const double tie = 1e-12 * (ysh[k - 1] - ysh[0]);
+    double best = __builtin_inf();
+    int win = -1;
+    for (int c0 = 0; c0 < 2 * k; c0 += SUMMARY_WCH) {
+        const int cn = min(SUMMARY_WCH, 2 * k - c0);
+        for (int e = lane; e < cn; e += 64) {
+            double lo, hi;
+            wid[e] = summary_candidate(C, ysh, k, cover, c0 + e, lo, hi) ? hi - lo : __builtin_nan("");
+        }
+        wave_sync();
+        if (lane == 0) {
+            // candidate order: the first of least width; a later one only
+            // when narrower by more than tie
+#pragma unroll 8
+            for (int e = 0; e < cn; ++e) {
+                const double w = wid[e];
+                if (w == w && w < best - tie) {
+                    best = w;
+                    win = c0 + e;
+                }
             }
         }
+        wave_sync();
     }
-    o[2] = blo;
-    o[3] = bhi;
+    if (lane == 0) {
+        double lo = __builtin_nan(""), hi = __builtin_nan("");
+        if (win >= 0) summary_candidate(C, ysh, k, cover, win, lo, hi);
+        o[2] = lo;
+        o[3] = hi;
+    }
 }
 
 MeanArgs mean_args(const double* h, int dx)
@@ -309,8 +411,20 @@ hipError_t launch_cond_mean(const cde_model* m, const void* xq, int64_t q, const
 hipError_t launch_density_summary(const double* f, const double* yg, int64_t q, int64_t k, double alpha,
                                   double* out, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_density_summary, dim3((unsigned)((q + 63) / 64)), dim3(64), 0, stream, f, yg, (int)q,
-                       (int)k, alpha, out);
+    if (q == 0) return hipSuccess;
+    // rows per block (one wave each): 4, 2 or 1, within 64 KiB of LDS
+    const bool ylds = k <= 2048;
+    const int64_t base = ylds ? k : 0, per_row = k + SUMMARY_WCH;
+    int rpb = 4;
+    while (rpb > 1 && (base + rpb * per_row) * (int64_t)sizeof(double) > 65536) rpb /= 2;
+    const size_t lds = (size_t)(base + rpb * per_row) * sizeof(double);
+    const dim3 grid((unsigned)((q + rpb - 1) / rpb)), block(64 * rpb);
+    if (ylds)
+        hipLaunchKernelGGL(k_density_summary<true>, grid, block, lds, stream, f, yg, (int)q, (int)k, rpb, alpha,
+                           out);
+    else
+        hipLaunchKernelGGL(k_density_summary<false>, grid, block, lds, stream, f, yg, (int)q, (int)k, rpb,
+                           alpha, out);
     return hipGetLastError();
 }
 

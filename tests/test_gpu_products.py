@@ -88,6 +88,25 @@ def test_density_summary_bit_equal_to_oracle():
         assert np.array_equal(got, ref, equal_nan=True), np.nanmax(np.abs(got - ref))
 
 
+@pytest.mark.parametrize("k,q", [(2, 5), (3, 9), (256, 4099), (2048, 7), (4096, 3)])
+def test_density_summary_sizes(k, q):
+    # grid sizes that give 4, 2 and 1 rows per block, ragged last blocks, and
+    # rows with ties (flat stretches) and zero mass
+    say(f"case: density summary k={k} q={q}")
+    rng = np.random.default_rng(k + q)
+    yg = np.sort(rng.uniform(-4.0, 4.0, k))
+    yg[0], yg[-1] = -4.0, 4.0
+    centres = rng.uniform(-2.0, 2.0, (q, 1))
+    f = np.exp(-0.5 * ((yg[None, :] - centres) / 0.7) ** 2)
+    f[::3] = np.round(f[::3], 2)  # flat stretches: ties in the mode and the widths
+    if q > 1:
+        f[1] = 0.0
+    for alpha in (0.05, 0.3):
+        ref = oracle.density_summary(f, yg, alpha)
+        got = cde().density_summary(P.to_dev(f, torch.float64), yg, alpha).cpu().numpy()
+        assert np.array_equal(got, ref, equal_nan=True), np.nanmax(np.abs(got - ref))
+
+
 def test_density_summary_of_gpu_query_rows():
     # the GPU query feeds the GPU summary; the summary of the oracle's density
     # at the same queries agrees within the query tolerance's effect
