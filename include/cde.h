@@ -26,8 +26,12 @@
  *     Host pointers (bandwidth arrays) are read during the call only.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Calls only enqueue work on `stream`; outputs are valid once the stream
- *     has passed the call.  A model may be used from several streams only for
- *     calls whose outputs do not overlap; calls on one stream are ordered.
+ *     has passed the call.  Calls on one model share that model's device
+ *     scratch, so they must not overlap in time: issue them on one stream (or
+ *     order them across streams with events).  Different models may run
+ *     concurrently on different streams.  A call that needs more scratch
+ *     than the model holds frees and reallocates it, which synchronises the
+ *     device.
  *   - Outputs are caller-owned device buffers.
  *   - Errors are reported by status code only; no exception crosses the ABI.
  *     After a non-OK status, cde_last_error() returns a message (per thread).
