@@ -248,7 +248,9 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
     const int i0 = blockIdx.x * 32 + wave * 8;
     int cnt_list = 0;
     if (plist) {
-        cnt_list = *pcount;
+        // the list of this grid tile (blockIdx.y)
+        plist += (size_t)blockIdx.y * npad;
+        cnt_list = pcount[blockIdx.y];
         if ((int)blockIdx.x * 32 >= cnt_list) return;  // whole block past the list (uniform)
     }
     auto point = [&](int q) -> int {
@@ -692,9 +694,10 @@ struct GridFin {
 
 // Per (setting, point) finalisation in FP64; entries whose shifted num' is
 // too small for FP32 to have carried it are queued for the exact fixup.
-// flag_points != NULL (after the FP32 pass): mark points with a cell below
-// its tile's threshold (2^-130 biased, 2^-80 otherwise); otherwise queue
-// entries below 2^-1000 for the per-entry fixup.
+// flag_points != NULL (after the FP32 pass): mark (tile, point) pairs with a
+// cell below the tile's threshold (2^-130 biased, 2^-80 otherwise), in
+// flag_points[tile][npad]; otherwise queue entries below 2^-1000 for the
+// per-entry fixup.
 __global__ void k_grid_finalize(const double* __restrict__ numbuf, const double* __restrict__ denbuf,
                                 const double* __restrict__ nn, int n, int npad, GridFin gf, int crit,
                                 double* __restrict__ ell, int* __restrict__ fix_count,
@@ -718,7 +721,7 @@ __global__ void k_grid_finalize(const double* __restrict__ numbuf, const double*
     if (flag_points) {
         const int t = (a / 16) * gf.tb + b / 16;
         const double lim = (gf.biased >> t) & 1u ? 0x1p-130 : 0x1p-80;
-        if (!(num >= lim)) flag_points[i] = 1;
+        if (!(num >= lim)) flag_points[(size_t)t * npad + i] = 1;
     } else if (!(num >= 0x1p-1000)) {
         const int slot = atomicAdd(fix_count, 1);
         if (slot < fix_cap) fix_list[slot] = make_int2(g, i);
@@ -726,11 +729,13 @@ __global__ void k_grid_finalize(const double* __restrict__ numbuf, const double*
 }
 
 // List of flagged points (order of the list does not affect any result).
-__global__ void k_compact_points(const int* __restrict__ flag, int n, int* __restrict__ count,
+__global__ void k_compact_points(const int* __restrict__ flag, int n, int npad, int* __restrict__ count,
                                  int* __restrict__ list)
 {
+    // one list per grid tile (blockIdx.y): flag[tile][npad] -> list[tile][npad]
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && flag[i]) list[atomicAdd(count, 1)] = i;
+    const size_t t = blockIdx.y;
+    if (i < n && flag[t * npad + i]) list[t * npad + atomicAdd(count + t, 1)] = i;
 }
 
 // Exact recomputation of queued (setting, point) entries: one wave per entry,
@@ -839,9 +844,9 @@ struct GridWork {
     double* denbuf;  // [gx][npad]
     double* ell;     // [G][npad]
     int* fix_count;  // [1]
-    int* flags;      // [npad] points needing the FP64 pass
-    int* plist;      // [npad] list of those points
-    int* pcount;     // [1]
+    int* flags;      // [tiles][npad] (tile, point) pairs needing the FP64 pass
+    int* plist;      // [tiles][npad] per tile: the list of those points
+    int* pcount;     // [tiles] list lengths
     int2* fix_list;  // [fix_cap] entries needing the per-entry recomputation
     int fix_cap;
 };
@@ -876,10 +881,12 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {
-        // FP32 pass over all points, flag points with a cell FP32 cannot carry,
-        // recompute those points on the FP64 path.
-        hipLaunchKernelGGL(k_zero_int, dim3((npad + 255) / 256), dim3(256), 0, stream, w.flags, npad);
-        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, w.pcount, 1);
+        // FP32 pass over all points; flag (tile, point) pairs with a cell FP32
+        // cannot carry and recompute those tiles of those points on the FP64
+        // path (the FP32 denominators stand where b-tile 0 is not recomputed).
+        hipLaunchKernelGGL(k_zero_int, dim3((unsigned)(((size_t)tiles * npad + 255) / 256)), dim3(256), 0, stream,
+                           w.flags, tiles * npad);
+        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, w.pcount, tiles);
         constexpr int PW = CDE_GRID32_POINTS_PER_WAVE;
         if (ga.gxp % 32 == 0 && ga.gyp % 32 == 0) {
             constexpr int PWQ = 2;
@@ -911,8 +918,8 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
         hipLaunchKernelGGL(k_grid_finalize, fgrid, dim3(256), 0, stream, (const double*)w.numbuf,
                            (const double*)w.denbuf, nn, n, npad, gf, crit, w.ell, w.fix_count,
                            w.fix_list, w.fix_cap, w.flags);
-        hipLaunchKernelGGL(k_compact_points, dim3((n + 255) / 256), dim3(256), 0, stream,
-                           (const int*)w.flags, n, w.pcount, w.plist);
+        hipLaunchKernelGGL(k_compact_points, dim3((n + 255) / 256, (unsigned)tiles), dim3(256), 0, stream,
+                           (const int*)w.flags, n, npad, w.pcount, w.plist);
         hipLaunchKernelGGL((k_loo_grid<DX, DY, false>), grid, dim3(TILE), 0, stream, pts, nn, n, npad,
                            ga, xmean, w.numbuf, w.denbuf, (const int*)w.plist, (const int*)w.pcount);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -991,15 +998,16 @@ hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* h
     }
     const size_t G = (size_t)n_hx * n_hy;
     // work layout: numbuf [G][npad] | denbuf [gx][npad] | ell [G][npad] |
-    // fix_count [64] | flags [npad] | plist [npad] | pcount [64] | fix_list
+    // fix_count [64] | flags [tiles][npad] | plist [tiles][npad] | pcount [64] | fix_list
     GridWork w;
     w.numbuf = (double*)work;
     w.denbuf = w.numbuf + G * m->npad;
     w.ell = w.denbuf + (size_t)n_hx * m->npad;
     w.fix_count = (int*)(w.ell + G * m->npad);
     w.flags = w.fix_count + 64;
-    w.plist = w.flags + m->npad;
-    w.pcount = w.plist + m->npad;
+    const size_t ntl = (size_t)(ga.gxp / 16) * (ga.gyp / 16);  // grid tiles
+    w.plist = w.flags + ntl * m->npad;
+    w.pcount = w.plist + ntl * m->npad;
     w.fix_list = (int2*)(w.pcount + 64);
     const size_t used = (size_t)((char*)w.fix_list - (char*)work);
     if (used >= work_bytes) return hipErrorInvalidValue;
@@ -1021,7 +1029,8 @@ size_t grid_work_bytes(const cde_model* m, int n_hx, int n_hy)
 {
     const size_t G = (size_t)n_hx * n_hy;
     const size_t fix_cap = std::max<size_t>(G * m->npad / 8, 1 << 20);  // 1/8 of all entries
-    return sizeof(double) * (2 * G + n_hx) * m->npad + (2 * m->npad + 128) * sizeof(int) +
+    const size_t ntl = (size_t)((n_hx + 15) / 16) * ((n_hy + 15) / 16);  // grid tiles
+    return sizeof(double) * (2 * G + n_hx) * m->npad + (2 * ntl * m->npad + 128) * sizeof(int) +
            fix_cap * sizeof(int2) + 64;
 }
 
