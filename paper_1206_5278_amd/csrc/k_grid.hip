@@ -208,6 +208,7 @@ struct GridArgs {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ short bf16_bits(float v)
 {
@@ -226,7 +227,14 @@ __device__ __forceinline__ void split4(const float* x, const float* mean, v4s& h
     }
 }
 
-template <int DX, int DY, bool XT>
+// The FP64 grid kernel: one 16 x 16 grid tile per blockIdx.y, PWF points per
+// wave (4 PWF per block) on v_mfma_f64_16x16x4f64.  In a distance group a
+// lane forms the pair of point q = (lane % 16) % PWF with tile row
+// 4 ((lane % 16) / PWF) + lane / 16, so the row broadcast of lane idx of
+// each 16-lane row hands MFMA step idx its four rows of point idx % PWF.
+// With a point list (the rerun of flagged points), fewer points per wave
+// spread a short list over more blocks; the work per pair is the same.
+template <int DX, int DY, bool XT, int PWF>
 __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts,
                                                    const double* __restrict__ nn, int n, int npad,
                                                    GridArgs ga, const float* __restrict__ xmean,
@@ -237,6 +245,9 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
 {
     constexpr int S = row_stride(DX, DY);
     static_assert(!XT || DX == 16, "the MFMA cross term is built for dx = 16");
+    static_assert(PWF == 2 || PWF == 4 || PWF == 8, "2, 4 or 8 points per wave");
+    static_assert(!XT || PWF == 8, "the cross-term layout holds 8 points per wave");
+    constexpr int JG = 64 / PWF;  // tile rows per distance group
     __shared__ float tile[TILE * S];
     __shared__ float jnorm[XT ? TILE : 1];
     __shared__ float xcross[XT ? 4 * 8 * TILE : 1];
@@ -244,14 +255,14 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    // this wave's 8 points: i0 .. i0+7, or list entries i0 .. i0+7 of plist
-    const int i0 = blockIdx.x * 32 + wave * 8;
+    // this wave's PWF points: i0 .. i0+PWF-1, or those list entries of plist
+    const int i0 = blockIdx.x * (4 * PWF) + wave * PWF;
     int cnt_list = 0;
     if (plist) {
         // the list of this grid tile (blockIdx.y)
         plist += (size_t)blockIdx.y * npad;
         cnt_list = pcount[blockIdx.y];
-        if ((int)blockIdx.x * 32 >= cnt_list) return;  // whole block past the list (uniform)
+        if ((int)blockIdx.x * (4 * PWF) >= cnt_list) return;  // whole block past the list (uniform)
     }
     auto point = [&](int q) -> int {
         if (!plist) return i0 + q;
@@ -262,9 +273,9 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
     const int ab = blockIdx.y / tb, bb = blockIdx.y % tb;
     const bool do_den = (bb == 0);
 
-    // distance role: point i0 + lane%8 against tile row group*8 + jo
-    const int di = point(lane & 7);
-    const int jo = 4 * ((lane & 15) >> 3) + (lane >> 4);
+    // distance role: point i0 + (lane%16)%PWF against tile row group*JG + jo
+    const int di = point((lane & 15) % PWF);
+    const int jo = 4 * ((lane & 15) / PWF) + (lane >> 4);
     double own[S];
     own_f64<S>(own, pts + (size_t)di * S);
     const double m_i = nn[di], my_i = nn[npad + di];
@@ -289,10 +300,10 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
     const float ca = ga.cx[ab * 16 + (lane & 15)];
     const float cb = ga.cy[bb * 16 + (lane & 15)];
 
-    v4d acc[8];
-    double dsum[8];
+    v4d acc[PWF];
+    double dsum[PWF];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < PWF; ++t) {
         acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
         dsum[t] = 0.0;
     }
@@ -307,7 +318,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
         if (t + 1 < ntiles) load_row<S>(pre, pts + ((size_t)(t + 1) * TILE + tid) * S);
         const int base = t * TILE;
         const int cnt = min(TILE, n - base);
-        const int ngroups = (cnt + 7) >> 3;
+        const int ngroups = (cnt + JG - 1) / JG;
         if constexpr (XT) {
             // norms of the tile's centred points (one per thread)
             float nj = 0.f;
@@ -337,7 +348,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
             __syncthreads();
         }
         for (int g = 0; g < ngroups; ++g) {
-            const int jj = g * 8 + jo;
+            const int jj = g * JG + jo;
             float pj[S];
             load_row<S>(pj, tile + jj * S);  // rows >= cnt hold packed padding (in bounds)
             double d2x, d2y;
@@ -361,10 +372,10 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
                 ya = EXCLUDED;
             }
             const int xai = __float_as_int(xa), yai = __float_as_int(ya);
-            // step idx = 8 s + q: point i0 + q against rows 4 s + k (k = lane/16)
+            // step idx = PWF s + q: point i0 + q against rows 4 s + k (k = lane/16)
             Unroll<16>::run([&](auto c) {
                 constexpr int idx = decltype(c)::value;
-                constexpr int q = idx & 7;
+                constexpr int q = idx % PWF;
                 const double ex = exp2_neg_wide(row_bcast<idx>(xai) * ca);
                 const double ey = exp2_neg_wide(row_bcast<idx>(yai) * cb);
                 acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, ey, acc[q], 0, 0, 0);
@@ -376,7 +387,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
     // num' for (i0+q, a, b): the f64 16x16x4 result puts row (lane/16) + 4r,
     // column lane%16 in register r of each lane.
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < PWF; ++q) {
         const int i = point(q);
         const bool ok = point_valid(q);
 #pragma unroll
@@ -390,7 +401,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
         // den' partials: lane (a = lane%16, k = lane/16) summed its k-rows;
         // combine the four k-rows in a fixed order.
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < PWF; ++q) {
             double v = dsum[q];
             v += __shfl_xor(v, 16, 64);
             v += __shfl_xor(v, 32, 64);
@@ -538,15 +549,18 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
 }
 
 // The FP32 pass for grids of at least 32 x 32 cells (both padded sides
-// multiples of 32): a block owns a 2 x 2 quad of 16 x 16 grid tiles.  Per
-// 4-point MFMA step a lane forms ex for its two a-tiles and ey for its two
-// b-tiles (4 exponentials) and issues the 4 tile products, where one tile
-// per block would form 2 exponentials per product; the FP64 distances are
-// formed once per quad instead of once per tile.  Exponent biases are per
-// a-tile and per b-tile (32 for the tile of the smallest hx, resp. hy, else
-// 0); each tile's totals are unscaled by its own factor, and the flag
-// thresholds of k_grid_finalize (2^-130 for the tile biased on both sides,
-// 2^-80 elsewhere) hold as for k_loo_grid32.
+// multiples of 32): a block owns a 32 x 32 quad of the grid (a-tiles 2 qa and
+// 2 qa + 1, b-tiles 2 qb and 2 qb + 1) and accumulates it with
+// v_mfma_f32_32x32x2f32, which moves more products per cycle than four
+// 16 x 16 x 4 tiles.  Operand layout of that instruction: lane 32 k + m holds
+// A[m][k] and B[k][m]; register r of lane l holds the result row
+// 8 (r / 4) + 4 (l / 32) + r % 4 of column l % 32.  So a lane forms ex for
+// a = 32 qa + lane % 32 and ey for b = 32 qb + lane % 32 of the j its half
+// of the wave carries: one exponential per operand, two per 2-point step.
+// Exponent biases are per a-tile and per b-tile (32 for the tile of the
+// smallest hx, resp. hy, else 0); each cell is unscaled by its own factor,
+// and the flag thresholds of k_grid_finalize (2^-130 for the tile biased on
+// both sides, 2^-80 elsewhere) hold as for k_loo_grid32.
 template <int DX, int DY, int PW>
 __global__ __launch_bounds__(TILE) void k_loo_grid32q(const float* __restrict__ pts,
                                                       const double* __restrict__ nn, int n, int npad,
@@ -562,37 +576,35 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32q(const float* __restrict__ 
     const int tqb = ga.gyp / 32;
     const int qa = blockIdx.y / tqb, qb = blockIdx.y % tqb;
     const bool do_den = (qb == 0);
-    const int pos = lane & 15;
-    const int di = i0 + (pos % PW);
-    const int jo = 4 * (pos / PW) + (lane >> 4);
+    // The pair this lane forms in a distance group of JG rows: lane row
+    // r = lane / 16 gives the k-half h = r / 2 and the step set r % 2; step
+    // c = 16 (r % 2) + lane % 16 is point q = c % PW against rows 2 (c / PW)
+    // and 2 (c / PW) + 1, of which this lane takes row 2 (c / PW) + h.
+    const int lrow = lane >> 4;
+    const int c = 16 * (lrow & 1) + (lane & 15);
+    const int di = i0 + c % PW;
+    const int jo = 2 * (c / PW) + (lrow >> 1);
     double own[S];
     own_f64<S>(own, pts + (size_t)di * S);
     const double m_i = nn[di], my_i = nn[npad + di];
-    float ca[2], cb[2], bx[2], by[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        ca[t] = ga.cx[(2 * qa + t) * 16 + (lane & 15)];
-        cb[t] = ga.cy[(2 * qb + t) * 16 + (lane & 15)];
-        bx[t] = vreg(2 * qa + t == ga.bias_ta ? GRID_BIAS : 0.f);
-        by[t] = vreg(2 * qb + t == ga.bias_tb ? GRID_BIAS : 0.f);
-    }
+    const int am = lane & 31;  // A row and B column of this lane
+    const float ca = ga.cx[32 * qa + am];
+    const float cb = ga.cy[32 * qb + am];
+    const float bx = vreg(2 * qa + am / 16 == ga.bias_ta ? GRID_BIAS : 0.f);
+    const float by = vreg(2 * qb + am / 16 == ga.bias_tb ? GRID_BIAS : 0.f);
 
-    v4f acc[PW][4];  // tile (ta, tb) at 2 ta + tb
-    Kahan<float> tot[PW][4][4], dtot[PW][2];
-    float dpart[PW][2];
+    v16f acc[PW];
+    Kahan<float> tot[PW][16], dtot[PW];
+    float dpart[PW];
 #pragma unroll
     for (int q = 0; q < PW; ++q) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            acc[q][t] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int r = 0; r < 4; ++r) tot[q][t][r].zero();
+        for (int r = 0; r < 16; ++r) {
+            acc[q][r] = 0.f;
+            tot[q][r].zero();
         }
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            dpart[q][t] = 0.f;
-            dtot[q][t].zero();
-        }
+        dpart[q] = 0.f;
+        dtot[q].zero();
     }
     const int ntiles = (n + TILE - 1) / TILE;
     float pre[S];
@@ -616,68 +628,56 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32q(const float* __restrict__ 
                 xa = EXCLUDED;
                 ya = EXCLUDED;
             }
-            const int xai = __float_as_int(xa), yai = __float_as_int(ya);
-            Unroll<16>::run([&](auto c) {
+            // lane rows duplicated pairwise: x0 holds rows (0, 0, 2, 2) of xa,
+            // x1 rows (1, 1, 3, 3); a row broadcast of lane c % 16 then hands
+            // each half of the wave its own row of step c
+            const auto xs = __builtin_amdgcn_permlane16_swap(__float_as_uint(xa), __float_as_uint(xa), false, false);
+            const auto ys = __builtin_amdgcn_permlane16_swap(__float_as_uint(ya), __float_as_uint(ya), false, false);
+            const int x0 = (int)xs[0], x1 = (int)xs[1], y0 = (int)ys[0], y1 = (int)ys[1];
+            Unroll<32>::run([&](auto cc) {
 #pragma clang fp contract(off)  // v_mul_f32, then a VGPR-only v_sub_f32
-                constexpr int idx = decltype(c)::value;  // idx = PW s + q
-                constexpr int q = idx % PW;
-                const float xb = row_bcast<idx>(xai), yb = row_bcast<idx>(yai);
-                const float ex0 = exp2_<float>(bx[0] - xb * ca[0]);
-                const float ex1 = exp2_<float>(bx[1] - xb * ca[1]);
-                const float ey0 = exp2_<float>(by[0] - yb * cb[0]);
-                const float ey1 = exp2_<float>(by[1] - yb * cb[1]);
-                acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ex0, ey0, acc[q][0], 0, 0, 0);
-                acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ex0, ey1, acc[q][1], 0, 0, 0);
-                acc[q][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(ex1, ey0, acc[q][2], 0, 0, 0);
-                acc[q][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(ex1, ey1, acc[q][3], 0, 0, 0);
-                dpart[q][0] += ex0;
-                dpart[q][1] += ex1;
+                constexpr int st = decltype(cc)::value;
+                constexpr int q = st % PW;
+                const float xb = row_bcast<st % 16>(st < 16 ? x0 : x1);
+                const float yb = row_bcast<st % 16>(st < 16 ? y0 : y1);
+                const float ex = exp2_<float>(bx - xb * ca);
+                const float ey = exp2_<float>(by - yb * cb);
+                acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(ex, ey, acc[q], 0, 0, 0);
+                dpart[q] += ex;
             });
         }
 #pragma unroll
         for (int q = 0; q < PW; ++q) {
 #pragma unroll
-            for (int tt = 0; tt < 4; ++tt) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) tot[q][tt][r].add(acc[q][tt][r]);
-                acc[q][tt] = v4f{0.f, 0.f, 0.f, 0.f};
+            for (int r = 0; r < 16; ++r) {
+                tot[q][r].add(acc[q][r]);
+                acc[q][r] = 0.f;
             }
-#pragma unroll
-            for (int ta = 0; ta < 2; ++ta) {
-                dtot[q][ta].add(dpart[q][ta]);
-                dpart[q][ta] = 0.f;
-            }
+            dtot[q].add(dpart[q]);
+            dpart[q] = 0.f;
         }
     }
-    // f32 16x16x4 result layout: register r holds row 4*(lane/16) + r; each
-    // tile's factor 2^(bx + by) (den: 2^bx) removed exactly
+    // each cell's factor 2^(bias of its a-tile + bias of its b-tile) (den:
+    // 2^(bias of its a-tile)) removed exactly
 #pragma unroll
     for (int q = 0; q < PW; ++q) {
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-            const int ta = tt >> 1, tb = tt & 1;
-            const double sc = ldexp(1.0, -(int)(bx[ta] + by[tb]));
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int a = (2 * qa + ta) * 16 + 4 * (lane >> 4) + r;
-                const int b = (2 * qb + tb) * 16 + (lane & 15);
-                if (a < ga.gx && b < ga.gy)
-                    numbuf[((size_t)a * ga.gy + b) * npad + i0 + q] = (double)tot[q][tt][r].value() * sc;
-            }
+        for (int r = 0; r < 16; ++r) {
+            const int ar = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+            const int a = 32 * qa + ar, b = 32 * qb + am;
+            const int ea = (2 * qa + ar / 16 == ga.bias_ta) ? (int)GRID_BIAS : 0;
+            const double sc = ldexp(1.0, -(ea + (int)by));
+            if (a < ga.gx && b < ga.gy)
+                numbuf[((size_t)a * ga.gy + b) * npad + i0 + q] = (double)tot[q][r].value() * sc;
         }
     }
     if (do_den) {
 #pragma unroll
         for (int q = 0; q < PW; ++q) {
-#pragma unroll
-            for (int ta = 0; ta < 2; ++ta) {
-                double v = dtot[q][ta].value();
-                v += __shfl_xor(v, 16, 64);
-                v += __shfl_xor(v, 32, 64);
-                const int a = (2 * qa + ta) * 16 + (lane & 15);
-                if (lane < 16 && a < ga.gx)
-                    denbuf[(size_t)a * npad + i0 + q] = v * ldexp(1.0, -(int)bx[ta]);
-            }
+            double v = dtot[q].value();
+            v += __shfl_xor(v, 32, 64);
+            const int a = 32 * qa + am;
+            if (lane < 32 && a < ga.gx) denbuf[(size_t)a * npad + i0 + q] = v * ldexp(1.0, -(int)bx);
         }
     }
 }
@@ -873,7 +873,7 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
     const float* xmean = (const float*)m->xmean;
     if (xt) {
         if constexpr (DX == 16) {
-            hipLaunchKernelGGL((k_loo_grid<DX, DY, true>), grid, dim3(TILE), 0, stream, pts, nn, n,
+            hipLaunchKernelGGL((k_loo_grid<DX, DY, true, 8>), grid, dim3(TILE), 0, stream, pts, nn, n,
                                npad, ga, xmean, w.numbuf, w.denbuf, (const int*)nullptr,
                                (const int*)nullptr);
         } else {
@@ -920,8 +920,20 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
                            w.fix_list, w.fix_cap, w.flags);
         hipLaunchKernelGGL(k_compact_points, dim3((n + 255) / 256, (unsigned)tiles), dim3(256), 0, stream,
                            (const int*)w.flags, n, npad, w.pcount, w.plist);
-        hipLaunchKernelGGL((k_loo_grid<DX, DY, false>), grid, dim3(TILE), 0, stream, pts, nn, n, npad,
-                           ga, xmean, w.numbuf, w.denbuf, (const int*)w.plist, (const int*)w.pcount);
+        // Points per wave of the rerun.  Each block streams all n points, so
+        // 8 per wave keeps that traffic low; up to 2^18 points the flagged
+        // lists are short (a few thousand points: ~100 blocks of 32) and 2
+        // per wave spreads them over 4x the blocks.
+        if (npad <= (1 << 18)) {
+            const dim3 rgrid((unsigned)(npad / 8), (unsigned)tiles);
+            hipLaunchKernelGGL((k_loo_grid<DX, DY, false, 2>), rgrid, dim3(TILE), 0, stream, pts, nn, n,
+                               npad, ga, xmean, w.numbuf, w.denbuf, (const int*)w.plist,
+                               (const int*)w.pcount);
+        } else {
+            hipLaunchKernelGGL((k_loo_grid<DX, DY, false, 8>), grid, dim3(TILE), 0, stream, pts, nn, n,
+                               npad, ga, xmean, w.numbuf, w.denbuf, (const int*)w.plist,
+                               (const int*)w.pcount);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_grid_finalize, fgrid, dim3(256), 0, stream, (const double*)w.numbuf,
