@@ -44,6 +44,14 @@ PAIR_F, PAIR_E = 31.0, 2.0
 # reading for a 256 MiB copy (profiles/k_loo_diag_f32_5x1_grad_photoz500k.md).
 # Set to None whenever that kernel changes, until the counters are re-taken.
 DIAG_TRAFFIC_BYTES = 958_886_000
+# Shader-clock cycles of one such launch: rocprofv3 --pmc GRBM_COUNT over the
+# launch (3 launches), divided by the 8 XCDs the counter sums over.  Over the
+# launch's duration that is the clock the chip really ran (2.20 GHz in that
+# run, against the 2.4 GHz the peak assumes); the ideal cycle count over it
+# is the roofline fraction at the measured clock.  None whenever that kernel
+# changes, until the counter is re-taken.
+DIAG_CYCLES = 399_617_000
+DIAG_CYCLES_GHZ = 2.20
 
 
 def parse():
@@ -156,6 +164,10 @@ def main():
                 "frac": achieved / peak,
                 "traffic": DIAG_TRAFFIC_BYTES if n == 500_000 else None,
                 "kernel": "k_loo_diag<float,5,1,grad>", "kernel_ms": kern_ms,
+                "measured_clock": ({"frac": slots / (VALU_PEAK_SLOTS / 2.4e9) / DIAG_CYCLES,
+                                    "cycles_per_launch": DIAG_CYCLES, "ghz": DIAG_CYCLES_GHZ,
+                                    "source": "rocprofv3 --pmc GRBM_COUNT / 8 XCDs over the launch"}
+                                   if n == 500_000 and DIAG_CYCLES else None),
                 "work_per_pair": f"F={PAIR_F:g} VALU ops + E={PAIR_E:g} v_exp_f32 x {EXP_SLOTS:g} slots"}
 
     # Secondary: value-only evaluation (no gradient moments) at the final h.
