@@ -109,6 +109,26 @@ def test_gmm_50k_32x32_grid_sampled_points():
     np.testing.assert_allclose(t, pp.sum(axis=1), rtol=1e-10)
 
 
+def test_gmm_300k_16x16_grid_sampled_points():
+    # Above 2^18 points the FP64 rerun of flagged points runs 8 points per
+    # wave (2 below): 48 sampled points, of which a few are expected to have
+    # a flagged cell, each checked against all other 299,999 points.
+    print("case: gmm n=300000 16x16 grid, 48 sampled points", flush=True)
+    x, y = workloads.gmm(300_000, seed=4, dx=5)
+    hx = workloads.geomspace(0.05, 5.0, 16)
+    hy = workloads.geomspace(0.05, 5.0, 16)
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    tot, pp, nonfin = m.loo_grid(hx, hy, per_point=True)
+    assert int(nonfin.item()) == 0
+    pp = pp.cpu().numpy()
+    idx = np.sort(np.random.default_rng(11).choice(300_000, 48, replace=False))
+    ref = oracle.loo_grid(xo, yo, hx, hy, idx=idx, nthreads=NT)
+    P.assert_points(pp[:, idx], ref)
+    np.testing.assert_allclose(tot.cpu().numpy(), pp.sum(axis=1), rtol=1e-10)
+    m.close()
+
+
 def test_ascend_checkpoint_resume_is_exact(tmp_path):
     print("case: ascend checkpoint/resume", flush=True)
     x, y = workloads.photoz(3000, seed=9)
