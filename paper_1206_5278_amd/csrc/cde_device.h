@@ -144,19 +144,27 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* [4][NV
 // Exact FP64 minimum of a squared distance over a stream of points, with an
 // FP32 screen: a point is a candidate (its FP64 distance is taken) when its
 // FP32 distance is within a factor 1 + 2^-10 of the running FP32 minimum, or
-// tiny.  An FP32 distance formed from the same FP32 inputs (differences,
-// squares and weights rounded to FP32) lies within a relative 2^-18 of the
-// FP64 value for up to 18 dimensions, so the FP64 minimiser j* satisfies
-// d32(j*) <= (1 + 2^-18) / (1 - 2^-18) min_j d32(j), below the factor times
-// any running minimum: it is always a candidate, and the minimum over the
-// candidates equals the plain FP64 minimum.
+// at most 2^-100.  An FP32 distance formed from the same FP32 inputs
+// (differences, squares and weights rounded to FP32) lies within a relative
+// 2^-18 of the FP64 value for up to 18 dimensions, so the FP64 minimiser j*
+// satisfies d32(j*) <= (1 + 2^-18) / (1 - 2^-18) min_j d32(j), below the
+// factor times any running minimum: it is always a candidate, and the
+// minimum over the candidates equals the plain FP64 minimum.  A point that
+// is not a candidate lies above the running minimum and would not lower it,
+// so the minimum and the threshold change only on candidates and the common
+// case costs one compare.
 struct ScreenedMin {
-    float s = __builtin_inff();
+    float s = __builtin_inff();  // FP32 minimum so far
+    float t = __builtin_inff();  // max(s (1 + 2^-10), 2^-100)
+    // the screen alone, without updating the minimum: the smallest of a
+    // group of distances passes exactly when one of them is a candidate
+    __device__ __forceinline__ bool passes(float d32) const { return d32 <= t; }
     __device__ __forceinline__ bool candidate(float d32)
     {
-        const bool c = d32 <= s * (1.0f + 0x1p-10f) || d32 < 0x1p-100f;
+        if (!(d32 <= t)) return false;
         s = __builtin_fminf(s, d32);
-        return c;
+        t = __builtin_fmaxf(s * (1.0f + 0x1p-10f), 0x1p-100f);
+        return true;
     }
 };
 

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(TILE) void k_cmean_shift(const T* __restrict__ pts,
     for (int k = 0; k < DX; ++k) {
         xo[k] = (double)xq[(size_t)ec * DX + k];
         xo32[k] = (float)xq[(size_t)ec * DX + k];
-        c32[k] = (float)a.cx[k];
+        c32[k] = vreg((float)a.cx[k]);  // vector operands: the FMAs dual-issue
     }
     ScreenedMin screen;
     double best = __builtin_inf();
@@ -94,15 +94,29 @@ __global__ __launch_bounds__(TILE) void k_cmean_shift(const T* __restrict__ pts,
             // FP32 screening against the running FP32 minimum; the FP64
             // distance is taken for every candidate, so best is exactly the
             // FP64 minimum (ScreenedMin, cde_device.h)
-            for (int j = 0; j < cnt; ++j) {
-                const float* pj = tile + j * S;
-                float e32 = 0.f;
+            auto d32 = [&](const float* pj) {
+                float e32 = (xo32[0] - pj[0]) * (xo32[0] - pj[0]) * c32[0];
 #pragma unroll
-                for (int k = 0; k < DX; ++k) {
+                for (int k = 1; k < DX; ++k) {
                     const float d = xo32[k] - pj[k];
                     e32 = fmaf(d * d, c32[k], e32);
                 }
-                if (screen.candidate(e32)) best = fmin(best, xdist<T, DX>(xo, pj, a));
+                return e32;
+            };
+            // four rows per branch, screened in order inside (as one at a time)
+            int j = 0;
+            for (; j + 4 <= cnt; j += 4) {
+                float e4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) e4[u] = d32(tile + (j + u) * S);
+                if (screen.passes(fminf(fminf(e4[0], e4[1]), fminf(e4[2], e4[3])))) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (screen.candidate(e4[u])) best = fmin(best, xdist<T, DX>(xo, tile + (j + u) * S, a));
+                }
+            }
+            for (; j < cnt; ++j) {
+                if (screen.candidate(d32(tile + j * S))) best = fmin(best, xdist<T, DX>(xo, tile + j * S, a));
             }
         } else {
             for (int j = 0; j < cnt; ++j) best = fmin(best, xdist<T, DX>(xo, tile + j * S, a));

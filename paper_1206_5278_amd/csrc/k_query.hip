@@ -146,7 +146,7 @@ __global__ __launch_bounds__(TILE) void k_qshift_x(const float* __restrict__ pts
     for (int k = 0; k < DX; ++k) {
         xo32[k] = xq[(size_t)ec * DX + k];
         xo[k] = (double)xo32[k];
-        c32[k] = (float)qa.cx[k];
+        c32[k] = vreg((float)qa.cx[k]);  // vector operands: the FMAs dual-issue
     }
     ScreenedMin screen;  // FP32 screen, exact FP64 minimum (cde_device.h)
     double best = inf_<double>();
@@ -158,23 +158,39 @@ __global__ __launch_bounds__(TILE) void k_qshift_x(const float* __restrict__ pts
         store_row<S>(tile + tid * S, pre);
         __syncthreads();
         const int cnt = min(TILE, j1 - t0);
-        for (int j = 0; j < cnt; ++j) {
-            const float* pj = tile + j * S;
-            float e32 = 0.f;
+        auto d32 = [&](const float* pj) {
+            float e32 = (xo32[0] - pj[0]) * (xo32[0] - pj[0]) * c32[0];
 #pragma unroll
-            for (int k = 0; k < DX; ++k) {
+            for (int k = 1; k < DX; ++k) {
                 const float d = xo32[k] - pj[k];
                 e32 = fmaf(d * d, c32[k], e32);
             }
-            if (screen.candidate(e32)) {
-                double d2 = 0.0;
+            return e32;
+        };
+        auto exact = [&](const float* pj) {
+            double d2 = 0.0;
 #pragma unroll
-                for (int k = 0; k < DX; ++k) {
-                    const double d = xo[k] - (double)pj[k];
-                    d2 = fma_(d * d, qa.cx[k], d2);
-                }
-                best = min_(best, d2);
+            for (int k = 0; k < DX; ++k) {
+                const double d = xo[k] - (double)pj[k];
+                d2 = fma_(d * d, qa.cx[k], d2);
             }
+            best = min_(best, d2);
+        };
+        // four rows per branch: the group is entered when its smallest FP32
+        // distance passes the screen, and its rows are then screened in order
+        int j = 0;
+        for (; j + 4 <= cnt; j += 4) {
+            float e4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) e4[u] = d32(tile + (j + u) * S);
+            if (screen.passes(fminf(fminf(e4[0], e4[1]), fminf(e4[2], e4[3])))) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (screen.candidate(e4[u])) exact(tile + (j + u) * S);
+            }
+        }
+        for (; j < cnt; ++j) {
+            if (screen.candidate(d32(tile + j * S))) exact(tile + j * S);
         }
     }
     if (e < q) atomic_min_nonneg(mq + e, best);
