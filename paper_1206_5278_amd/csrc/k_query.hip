@@ -46,6 +46,8 @@ constexpr float QEXCLUDED = 1e20f;
 struct QueryArgs {
     double cx[16];   // log2(e) / (2 hx_k^2)
     double cy[4];    // log2(e) / (2 hy_l^2)
+    double sx[16];   // sqrt(cx_k): coordinate scales of the main kernel
+    double sy[4];    // sqrt(cy_l)
     double log_cy;
 };
 
@@ -90,33 +92,33 @@ __device__ __forceinline__ double ydist2(const double (&yo)[DY], const double* p
     return e;
 }
 
-// The same sums started from -shift: the shifted exponents of the main
-// kernel (one rounding fewer than subtracting afterwards; a live pair's
-// exponent can then fall a few ulps below 0, which the kernel tolerates).
-template <int DX>
-__device__ __forceinline__ double xdist2_shifted(const double (&xo)[DX], const double* pj,
-                                                 const QueryArgs& qa, double shift)
-{
-    double d2 = -shift;
-#pragma unroll
-    for (int kk = 0; kk < DX; ++kk) {
-        const double d = xo[kk] - pj[kk];
-        d2 = fma_(d * d, qa.cx[kk], d2);
-    }
-    return d2;
-}
-
-template <int DX, int DY>
-__device__ __forceinline__ double ydist2_shifted(const double (&yo)[DY], const double* pj,
-                                                 const QueryArgs& qa, double shift)
+// Shifted squared distance of pre-scaled coordinates (each multiplied by the
+// square root of its c in FP64), started from -shift: a difference and an
+// FMA per dimension.  The scaling rounds each coordinate once (relative
+// 2^-53); the exponent is rounded to FP32 afterwards, far above that.  The
+// shift is the exact minimum of the unscaled form, so the nearest pair's
+// exponent can fall a few ulps below 0, which the main kernel tolerates.
+template <int N>
+__device__ __forceinline__ double sdist2_shifted(const double (&o)[N], const double* pj, double shift)
 {
     double e = -shift;
 #pragma unroll
-    for (int l = 0; l < DY; ++l) {
-        const double d = yo[l] - pj[DX + l];
-        e = fma_(d * d, qa.cy[l], e);
+    for (int kk = 0; kk < N; ++kk) {
+        const double d = o[kk] - pj[kk];
+        e = fma_(d, d, e);
     }
     return e;
+}
+
+// One tile of packed FP32 rows staged in LDS as doubles scaled by sqrt(c),
+// [TILE][DX + DY].
+template <int DX, int DY>
+__device__ __forceinline__ void stage_tile_scaled(double* tile, const float* pre, int tid, const QueryArgs& qa)
+{
+#pragma unroll
+    for (int d = 0; d < DX; ++d) tile[tid * (DX + DY) + d] = (double)pre[d] * qa.sx[d];
+#pragma unroll
+    for (int l = 0; l < DY; ++l) tile[tid * (DX + DY) + DX + l] = (double)pre[DX + l] * qa.sy[l];
 }
 
 // One tile of packed FP32 rows staged in LDS as doubles, [TILE][DX + DY]
@@ -269,14 +271,14 @@ __global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pt
     const int qi = min(q0 + (lane & 15), q - 1);
     double xo[DX];
 #pragma unroll
-    for (int kk = 0; kk < DX; ++kk) xo[kk] = (double)xq[(size_t)qi * DX + kk];
+    for (int kk = 0; kk < DX; ++kk) xo[kk] = (double)xq[(size_t)qi * DX + kk] * qa.sx[kk];
     const double m_q = mq[qi];
     // y-kernel role: grid column tid % GW, panel rows tid / GW + PSTEP r
     const int gcol = tid % GW;
     const int gy = min(g0 + gcol, k - 1);
     double yo[DY];
 #pragma unroll
-    for (int l = 0; l < DY; ++l) yo[l] = (double)yg[(size_t)gy * DY + l];
+    for (int l = 0; l < DY; ++l) yo[l] = (double)yg[(size_t)gy * DY + l] * qa.sy[l];
     const double mu_g = mu[gy];
     const int prow = tid / GW;
 
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pt
     for (int t0 = j0; t0 < j1; t0 += TILE) {
         __syncthreads();
         if (stager) {
-            stage_tile_d<DX, DY>(tile, pre, tid);
+            stage_tile_scaled<DX, DY>(tile, pre, tid, qa);
             if (t0 + TILE < j1) load_row<S>(pre, pts + ((size_t)t0 + TILE + tid) * S);
         }
         const int cnt = min(TILE, j1 - t0);
@@ -308,7 +310,7 @@ __global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pt
 #pragma unroll
             for (int r = 0; r < YPT; ++r) {
                 const int p = prow + PSTEP * r;
-                const float a = (float)ydist2_shifted<DX, DY>(yo, tile + (s0 + p) * SD, qa, mu_g);
+                const float a = (float)sdist2_shifted<DY>(yo, tile + (s0 + p) * SD + DX, mu_g);
                 ykv[p * YS + gcol] = exp2_<float>(-fmaxf(a, 0.f));
             }
             __syncthreads();
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pt
             // x-kernel value of a 4-point step; the next step's is formed
             // before the current step's MFMAs are issued
             auto weight = [&](int ii) {
-                const double d2 = xdist2_shifted<DX>(xo, tile + ii * SD, qa, m_q);
+                const double d2 = sdist2_shifted<DX>(xo, tile + ii * SD, m_q);
                 const float xa = ii < cnt ? (float)d2 : QEXCLUDED;
                 return exp2_<float>(-xa);
             };
@@ -410,10 +412,14 @@ static hipError_t query_t(const cde_model* m, const float* xq, int q, const floa
                           const double* h, double* f, double* work, hipStream_t stream)
 {
     QueryArgs qa;
-    for (int kk = 0; kk < 16; ++kk) qa.cx[kk] = kk < DX ? LOG2E / (2.0 * h[kk] * h[kk]) : 0.0;
+    for (int kk = 0; kk < 16; ++kk) {
+        qa.cx[kk] = kk < DX ? LOG2E / (2.0 * h[kk] * h[kk]) : 0.0;
+        qa.sx[kk] = sqrt(qa.cx[kk]);
+    }
     double lcy = 0.0;
     for (int l = 0; l < 4; ++l) {
         qa.cy[l] = l < DY ? LOG2E / (2.0 * h[DX + l] * h[DX + l]) : 0.0;
+        qa.sy[l] = sqrt(qa.cy[l]);
         if (l < DY) lcy -= log(h[DX + l]) + HALF_LOG_2PI;
     }
     qa.log_cy = lcy;
