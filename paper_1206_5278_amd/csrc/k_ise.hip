@@ -51,6 +51,8 @@ constexpr int ISEG = 8;            // tiles of j per FP64 fold
 struct IseArgs {
     double cx[16];  // log2(e) / (2 hx_k^2)
     double cg[4];   // log2(e) / (4 hy_l^2)
+    double sx[16];  // sqrt(cx_k): coordinate scales of the main kernel
+    double sg[4];   // sqrt(cg_l)
 };
 
 __device__ __forceinline__ void atomic_min_nonneg(double* p, double v)
@@ -77,29 +79,32 @@ __device__ __forceinline__ double xdist2(const double* xo, const double* pj, con
     return d2;
 }
 
-template <int DX>
-__device__ __forceinline__ double xdist2_shifted(const double* xo, const double* pj,
-                                                 const IseArgs& a, double shift)
+// Squared distance of pre-scaled coordinates (each multiplied by the square
+// root of its c in FP64), started from -shift: a difference and an FMA per
+// dimension.  The scaling rounds each coordinate once (relative 2^-53); the
+// exponent is rounded to FP32 afterwards, far above that.  The shift is the
+// exact minimum of the unscaled form, so the nearest pair's exponent can fall
+// a few ulps below 0, which is harmless.
+template <int N>
+__device__ __forceinline__ double sdist2_shifted(const double* o, const double* pj, double shift)
 {
-    double d2 = -shift;
+    double e = -shift;
 #pragma unroll
-    for (int k = 0; k < DX; ++k) {
-        const double d = xo[k] - pj[k];
-        d2 = fma_(d * d, a.cx[k], d2);
-    }
-    return d2;
-}
-
-template <int DX, int DY>
-__device__ __forceinline__ double yconv2(const double (&yo)[DY], const double* pj, const IseArgs& a)
-{
-    double e = 0.0;
-#pragma unroll
-    for (int l = 0; l < DY; ++l) {
-        const double d = yo[l] - pj[DX + l];
-        e = fma_(d * d, a.cg[l], e);
+    for (int k = 0; k < N; ++k) {
+        const double d = o[k] - pj[k];
+        e = fma_(d, d, e);
     }
     return e;
+}
+
+// A training row staged in LDS as doubles scaled by sqrt(c): x by sx, y by sg.
+template <int DX, int DY>
+__device__ __forceinline__ void stage_tile_scaled(double* tile, const float* pre, int tid, const IseArgs& a)
+{
+#pragma unroll
+    for (int d = 0; d < DX; ++d) tile[tid * (DX + DY) + d] = (double)pre[d] * a.sx[d];
+#pragma unroll
+    for (int l = 0; l < DY; ++l) tile[tid * (DX + DY) + DX + l] = (double)pre[DX + l] * a.sg[l];
 }
 
 template <int DX, int DY>
@@ -163,13 +168,13 @@ __global__ __launch_bounds__(INT) void k_ise_mfma(const float* __restrict__ pts,
     for (int v = tid; v < IPB; v += INT) {
         const int i = min(i0 + v, n - 1);
 #pragma unroll
-        for (int k = 0; k < DX; ++k) xrow[v * DX + k] = (double)pts[(size_t)i * S + k];
+        for (int k = 0; k < DX; ++k) xrow[v * DX + k] = (double)pts[(size_t)i * S + k] * a.sx[k];
         mrow[v] = mi[i];
     }
     for (int v = tid; v < IGW; v += INT) {
         const int l = min(l0 + v, n - 1);
 #pragma unroll
-        for (int k = 0; k < DX; ++k) xcol[v * DX + k] = (double)pts[(size_t)l * S + k];
+        for (int k = 0; k < DX; ++k) xcol[v * DX + k] = (double)pts[(size_t)l * S + k] * a.sx[k];
     }
 
     // A role: row qi = i0 + 16 wave + lane % 16
@@ -177,14 +182,14 @@ __global__ __launch_bounds__(INT) void k_ise_mfma(const float* __restrict__ pts,
     const int qc = min(qi, n - 1);
     double xo[DX];
 #pragma unroll
-    for (int k = 0; k < DX; ++k) xo[k] = (double)pts[(size_t)qc * S + k];
+    for (int k = 0; k < DX; ++k) xo[k] = (double)pts[(size_t)qc * S + k] * a.sx[k];
     const double m_q = mi[qc];
     // panel role: column tid % IGW, panel rows tid / IGW + PSTEP r
     const int gcol = tid % IGW;
     const int gl = min(l0 + gcol, n - 1);
     double yo[DY];
 #pragma unroll
-    for (int l = 0; l < DY; ++l) yo[l] = (double)pts[(size_t)gl * S + DX + l];
+    for (int l = 0; l < DY; ++l) yo[l] = (double)pts[(size_t)gl * S + DX + l] * a.sg[l];
     const int prow = tid / IGW;
 
     float tot[IGT][4];
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(INT) void k_ise_mfma(const float* __restrict__ pts,
         const int t0 = tt * TILE;
         __syncthreads();
         if (stager) {
-            stage_tile<DX, DY>(tile, pre, tid);
+            stage_tile_scaled<DX, DY>(tile, pre, tid, a);
             if (tt + 1 < ntiles) load_row<S>(pre, pts + ((size_t)t0 + TILE + tid) * S);
         }
         const int cnt = min(TILE, n - t0);
@@ -213,7 +218,7 @@ __global__ __launch_bounds__(INT) void k_ise_mfma(const float* __restrict__ pts,
 #pragma unroll
             for (int r = 0; r < YPT; ++r) {
                 const int p = prow + PSTEP * r;
-                const float e = (float)yconv2<DX, DY>(yo, tile + (s0 + p) * SD, a);
+                const float e = (float)sdist2_shifted<DY>(yo, tile + (s0 + p) * SD + DX, 0.0);
                 ykv[p * YS + gcol] = exp2_<float>(-e);
             }
             __syncthreads();
@@ -222,7 +227,7 @@ __global__ __launch_bounds__(INT) void k_ise_mfma(const float* __restrict__ pts,
             // before the current step's MFMAs are issued
             auto weight = [&](int jj) {
                 const int j = t0 + jj;
-                const double d2 = xdist2_shifted<DX>(xo, tile + jj * SD, a, m_q);
+                const double d2 = sdist2_shifted<DX>(xo, tile + jj * SD, m_q);
                 const float xa = (jj < cnt && j != qi) ? (float)d2 : IEXCL;
                 return exp2_<float>(-xa);
             };
@@ -256,7 +261,7 @@ __global__ __launch_bounds__(INT) void k_ise_mfma(const float* __restrict__ pts,
                 for (int t = 0; t < IGT; ++t) {
                     const int lc = 16 * t + (lane & 15);
                     const int l = l0 + lc;
-                    const double e = xdist2_shifted<DX>(xrow + ir * DX, xcol + lc * DX, a, mrow[ir]);
+                    const double e = sdist2_shifted<DX>(xrow + ir * DX, xcol + lc * DX, mrow[ir]);
                     const float wil = (l < n && l != gi) ? exp2_<float>(-(float)e) : 0.f;
                     s = fma_((double)tot[t][r], (double)wil, s);
                     tot[t][r] = 0.f;
@@ -342,10 +347,14 @@ hipError_t ise_t(const cde_model* m, const double* h, const double* ell, double*
                  double* work, hipStream_t stream)
 {
     IseArgs a;
-    for (int k = 0; k < 16; ++k) a.cx[k] = k < DX ? LOG2E / (2.0 * h[k] * h[k]) : 0.0;
+    for (int k = 0; k < 16; ++k) {
+        a.cx[k] = k < DX ? LOG2E / (2.0 * h[k] * h[k]) : 0.0;
+        a.sx[k] = sqrt(a.cx[k]);
+    }
     double cgn = 1.0;
     for (int l = 0; l < 4; ++l) {
         a.cg[l] = l < DY ? LOG2E / (4.0 * h[DX + l] * h[DX + l]) : 0.0;
+        a.sg[l] = sqrt(a.cg[l]);
         if (l < DY) cgn /= 2.0 * 1.7724538509055160273 * h[DX + l];  // 2 sqrt(pi) hy
     }
     const int n = (int)m->n;
