@@ -7,7 +7,8 @@
 //
 // and f = 0 where no training x lies inside the query's window (eq. (1) is
 // 0/0 there).  Window values are formed in FP64 (the edge 1 - |u|^2 cancels)
-// and rounded once to FP32; products run on v_mfma_f32_16x16x4f32 exactly as
+// on rows, queries and grid points scaled by 1/h when staged (one rounding
+// each, relative 2^-53), and rounded once to FP32; products run on v_mfma_f32_16x16x4f32 exactly as
 // in the Gaussian query kernel (k_query.hip): 8 waves x 16 queries per
 // block, y-kernel panels of 32 training points shared through LDS.
 //
@@ -41,9 +42,8 @@ constexpr int EQPB = 16 * EWAVES;  // queries per block
 constexpr double EQ_SKIP_MARGIN = 1.0 + 0x1p-40;
 
 struct EpanQArgs {
-    double ix2[16];  // 1 / hx_k^2
-    double iy2[4];   // 1 / hy_l^2
-    double inv[16];  // 1 / hx_k (box gaps, Morton cells)
+    double inv[16];  // 1 / hx_k (box gaps, Morton cells, scaled rows)
+    double iny[4];   // 1 / hy_l (scaled rows)
 };
 
 // Squared scaled box distance between [alo, ahi] and [blo, bhi].
@@ -146,13 +146,13 @@ __global__ __launch_bounds__(ENT) void k_query_epan(const double* __restrict__ s
     const int oq = order[min(sq, q - 1)];
     double xo[DX];
 #pragma unroll
-    for (int kk = 0; kk < DX; ++kk) xo[kk] = (double)xq[(size_t)oq * DX + kk];
+    for (int kk = 0; kk < DX; ++kk) xo[kk] = (double)xq[(size_t)oq * DX + kk] * a.inv[kk];
     // panel role: grid column tid % GW
     const int gcol = tid % GW;
     const int gy = min(g0 + gcol, k - 1);
     double yo[DY];
 #pragma unroll
-    for (int l = 0; l < DY; ++l) yo[l] = (double)yg[(size_t)gy * DY + l];
+    for (int l = 0; l < DY; ++l) yo[l] = (double)yg[(size_t)gy * DY + l] * a.iny[l];
     const int prow = tid / GW;
 
     float tot[GT][4];
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(ENT) void k_query_epan(const double* __restrict__ s
             double pre[S];
             load_row<S>(pre, spts + ((size_t)t0 + tid) * S);
 #pragma unroll
-            for (int d = 0; d < SD; ++d) tile[tid * SD + d] = pre[d];
+            for (int d = 0; d < SD; ++d) tile[tid * SD + d] = pre[d] * (d < DX ? a.inv[d] : a.iny[d - DX]);
         }
         const int cnt = min(TILE, j1 - t0);
         float dp = 0.f;
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(ENT) void k_query_epan(const double* __restrict__ s
 #pragma unroll
                 for (int l = 0; l < DY; ++l) {
                     const double d = yo[l] - tile[(s0p + pr) * SD + DX + l];
-                    e = fma(d * d, a.iy2[l], e);
+                    e = fma(d, d, e);
                 }
                 ykv[pr * YS + gcol] = (float)fmax(-e, 0.0);  // (1 - |v|^2)_+, in [0, 1] for any row
             }
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(ENT) void k_query_epan(const double* __restrict__ s
 #pragma unroll
                 for (int kk = 0; kk < DX; ++kk) {
                     const double d = xo[kk] - tile[ii * SD + kk];
-                    s2 = fma(d * d, a.ix2[kk], s2);
+                    s2 = fma(d, d, s2);
                 }
                 return ii < cnt ? (float)fmax(-s2, 0.0) : 0.f;
             };
@@ -274,10 +274,11 @@ hipError_t query_epan_t(const cde_model* m, const float* xq, int q, const float*
 {
     EpanQArgs a;
     for (int kk = 0; kk < 16; ++kk) {
-        a.ix2[kk] = kk < DX ? 1.0 / (h[kk] * h[kk]) : 0.0;
         a.inv[kk] = kk < DX ? 1.0 / h[kk] : 0.0;
     }
-    for (int l = 0; l < 4; ++l) a.iy2[l] = l < DY ? 1.0 / (h[DX + l] * h[DX + l]) : 0.0;
+    for (int l = 0; l < 4; ++l) {
+        a.iny[l] = l < DY ? 1.0 / h[DX + l] : 0.0;
+    }
     const double cy = exp(log_epan_norm(h + DX, DY));
     const int n = (int)m->n;
     const int gt = query_grid_tiles(k);
