@@ -58,6 +58,34 @@ def test_conditional_mean_parity(dx, dy, dtype):
         assert np.all(np.abs(got - ref) <= 1e-12 * scale), float(np.max(np.abs(got - ref)))
 
 
+@pytest.mark.parametrize("n", [1001, 1026])
+def test_query_and_mean_ragged_tail(n):
+    # The shift prepasses screen four training rows per branch and the rows
+    # of a tile beyond a multiple of four one at a time.  Here the last tile
+    # holds n % 256 rows (233 and 2), and some queries sit on the last
+    # training point, so their nearest neighbour, which fixes the shift, is
+    # one of those single rows; a tiny bandwidth makes a wrong shift visible.
+    say(f"case: query and conditional mean, ragged tail n={n}")
+    x, y = workloads.gmm(n, seed=21, dx=3)
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    rng = np.random.default_rng(n)
+    xq = np.concatenate([xo[n - 1:n], xo[n - 1:n] + 1e-3, xo[rng.choice(n, 13)] + 0.05 * rng.normal(size=(13, 3))])
+    xq = xq.astype(np.float32).astype(np.float64)
+    yg = np.linspace(yo.min() - 1, yo.max() + 1, 70).astype(np.float32).astype(np.float64)
+    for hs in (0.4, 0.01):
+        h = [hs] * 3 + [0.3]
+        f = m.query(P.to_dev(xq), P.to_dev(yg), h).cpu().numpy()
+        ref = oracle.density(xo, yo, h, xq, yg, nthreads=NT)
+        peak = ref.max(axis=1, keepdims=True)
+        err = np.abs(f - ref)
+        assert np.all(err <= 1e-5 * ref + 1e-7 * peak), float(np.max(err / (1e-5 * ref + 1e-7 * peak)))
+        got = m.conditional_mean(P.to_dev(xq, torch.float32), h).cpu().numpy()
+        ref_m = oracle.cond_mean(xo, yo, h, xq)
+        assert np.all(np.abs(got - ref_m) <= 1e-12 * np.abs(yo).max()), float(np.max(np.abs(got - ref_m)))
+    m.close()
+
+
 def test_conditional_mean_large_set_slices():
     # 70,000 training points (64 chunks) and 20,000 queries (two slices)
     say("case: conditional mean n=70000 q=20000")
