@@ -134,7 +134,7 @@ __global__ __launch_bounds__(TILE) void k_cmean_sums(const T* __restrict__ pts, 
                                                      double* __restrict__ part)
 {
     constexpr int S = row_stride(DX, DY);
-    __shared__ T tile[TILE * S];
+    __shared__ double tile[TILE * S];  // staged as doubles: one exact conversion per row
     const int tid = threadIdx.x;
     const int e = blockIdx.x * TILE + tid;
     const int ec = e < q ? e : q - 1;
@@ -150,15 +150,18 @@ __global__ __launch_bounds__(TILE) void k_cmean_sums(const T* __restrict__ pts, 
         __syncthreads();
         T pre[S];
         load_row<S>(pre, pts + ((size_t)t0 + tid) * S);
-        store_row<S>(tile + tid * S, pre);
+        double pd[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) pd[c] = (double)pre[c];
+        store_row<S>(tile + tid * S, pd);
         __syncthreads();
         const int cnt = min(TILE, j1 - t0);
         for (int j = 0; j < cnt; ++j) {
-            const T* pj = tile + j * S;
-            const double w = exp(m - xdist<T, DX>(xo, pj, a));
+            const double* pj = tile + j * S;
+            const double w = exp(m - xdist<double, DX>(xo, pj, a));
             D += w;
 #pragma unroll
-            for (int l = 0; l < DY; ++l) Sy[l] = fma(w, (double)pj[DX + l], Sy[l]);
+            for (int l = 0; l < DY; ++l) Sy[l] = fma(w, pj[DX + l], Sy[l]);
         }
     }
     if (e < q) {
