@@ -113,6 +113,25 @@ __device__ __forceinline__ void dist2(const double* a, const float* b, double& d
     dys = f;
 }
 
+template <int DX, int DY>
+__device__ __forceinline__ void dist2(const double* a, const double* b, double& dxs, double& dys)
+{
+    double e = 0.0;
+#pragma unroll
+    for (int k = 0; k < DX; ++k) {
+        double d = a[k] - b[k];
+        e = fma_(d, d, e);
+    }
+    double f = 0.0;
+#pragma unroll
+    for (int l = 0; l < DY; ++l) {
+        double d = a[DX + l] - b[DX + l];
+        f = fma_(d, d, f);
+    }
+    dxs = e;
+    dys = f;
+}
+
 template <int S>
 __device__ __forceinline__ void own_f64(double (&dst)[S], const float* src)
 {
@@ -445,7 +464,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
     static_assert(PW == 4 || PW == 8, "4 or 8 points per wave");
     constexpr int S = row_stride(DX, DY);
     constexpr int JG = 64 / PW;  // tile rows per distance group
-    __shared__ float tile[TILE * S];
+    __shared__ double tile[TILE * S];  // staged as doubles: one exact conversion per row
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i0 = blockIdx.x * (4 * PW) + wave * PW;
     const int tb = ga.gyp / 16;
@@ -481,7 +500,12 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
     load_row<S>(pre, pts + (size_t)tid * S);
     for (int t = 0; t < ntiles; ++t) {
         __syncthreads();
-        store_row<S>(tile + tid * S, pre);
+        {
+            double pd[S];
+#pragma unroll
+            for (int c = 0; c < S; ++c) pd[c] = (double)pre[c];
+            store_row<S>(tile + tid * S, pd);
+        }
         __syncthreads();
         if (t + 1 < ntiles) load_row<S>(pre, pts + ((size_t)(t + 1) * TILE + tid) * S);
         const int base = t * TILE;
@@ -489,7 +513,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
         const int ngroups = (cnt + JG - 1) / JG;
         for (int g = 0; g < ngroups; ++g) {
             const int jj = g * JG + jo;
-            float pj[S];
+            double pj[S];
             load_row<S>(pj, tile + jj * S);  // jj < 256: rows >= cnt are packed padding
             double d2x, d2y;
             dist2<DX, DY>(own, pj, d2x, d2y);
