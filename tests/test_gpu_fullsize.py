@@ -129,6 +129,27 @@ def test_gmm_300k_16x16_grid_sampled_points():
     m.close()
 
 
+def test_highdim_1m_16x16_grid_sampled_points():
+    # The 1,000,000-point 16-D set on its 16 x 16 grid, in the default
+    # configuration the benchmark times (FP32 pass with FP64-difference
+    # distances, FP64 rerun of flagged points): 16 sampled points, each
+    # checked against the oracle over all other 999,999 points.
+    print("case: highdim n=1000000 16x16 grid, 16 sampled points", flush=True)
+    x, y = workloads.highdim()
+    hx, hy = workloads.WORKLOADS["highdim"]["grid"]
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    tot, pp, nonfin = m.loo_grid(hx, hy, per_point=True)
+    assert int(nonfin.item()) == 0
+    idx = np.sort(np.random.default_rng(19).choice(len(xo), 16, replace=False))
+    got = pp[:, torch.from_numpy(idx).to(pp.device)].cpu().numpy()
+    np.testing.assert_allclose(tot.cpu().numpy(), pp.sum(dim=1).cpu().numpy(), rtol=1e-10)
+    del pp
+    m.close()
+    ref = oracle.loo_grid(xo, yo, hx, hy, idx=idx, nthreads=NT)
+    P.assert_points(got, ref)
+
+
 def test_ascend_checkpoint_resume_is_exact(tmp_path):
     print("case: ascend checkpoint/resume", flush=True)
     x, y = workloads.photoz(3000, seed=9)
