@@ -5,9 +5,10 @@ GPU calls only; this script repeats the same calls on the same seeded inputs
 and checks sampled outputs, each computed by the oracle point by point
 against the whole training set.  Run from the repository root on a GPU:
 
-    python -m tests.fullsize_report [--grid] [--query] [--ise] [--epan]
+    python -m tests.fullsize_report [--grid] [--query] [--ise] [--epan] [--headline]
 
-(no flag: all four).  Prints one JSON line per section.  The pass/fail
+(no flag: the first four; --headline sums the oracle over all 500,000 points
+of the headline workload, about five minutes on 16 threads).  Prints one JSON line per section.  The pass/fail
 checks at these sizes live in the ``gpu`` tests; this script reports the
 numbers.
 """
@@ -102,6 +103,52 @@ def grid_report():
     m.close()
     m5.close()
     return out
+
+
+def headline_report():
+    """The headline workload in full: photoz N = 500,000, value and gradient
+    at the normal-reference bandwidths, against the oracle summed over all
+    500,000 points (in 10 slices of 50,000, a progress line after each).
+    Tolerances: total 1e-6 relative; gradient per component 1e-4 of
+    max(|g*_k|, 1e-2 max_k |g*_k|)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1206_5278_amd as cde
+    import workloads
+    n = 500_000
+    x, y = workloads.photoz(n, seed=0)
+    x32 = np.ascontiguousarray(x, dtype=np.float32)
+    y32 = np.ascontiguousarray(y, dtype=np.float32)
+    xo, yo = x32.astype(np.float64), y32.astype(np.float64)
+    m = cde.Model(torch.from_numpy(x32).cuda(), torch.from_numpy(y32).cuda())
+    h = cde.normal_reference_bandwidths(xo, yo).tolist()
+    total, grad, _ = m.loo_grad(h)
+    total, grad = float(total.item()), grad.cpu().numpy()
+    m.close()
+    ells, dells = [], []
+    t0 = time.perf_counter()
+    for c in range(10):
+        idx = np.arange(c * 50_000, (c + 1) * 50_000)
+        ell, dell = oracle.loo(xo, yo, h, idx=idx, grad=True, nthreads=NT)
+        ells.append(ell)
+        dells.append(dell)
+        print(f"oracle slice {c + 1}/10 done ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    ell = np.concatenate(ells)
+    dell = np.concatenate(dells)
+    ref = math.fsum(ell.tolist())
+    gref = np.array([math.fsum(dell[:, k].tolist()) for k in range(dell.shape[1])])
+    gscale = np.maximum(np.abs(gref), 1e-2 * np.abs(gref).max())
+    return {
+        "section": "headline", "n": n, "h": h,
+        "total": total, "total_oracle": ref, "total_rel_err": abs(total - ref) / abs(ref),
+        "grad": grad.tolist(), "grad_oracle": gref.tolist(),
+        "grad_err_over_scale_max": float(np.max(np.abs(grad - gref) / gscale)),
+        "oracle_seconds": time.perf_counter() - t0, "oracle_cores": NT,
+    }
 
 
 def query_report():
@@ -234,11 +281,13 @@ def epan_report():
 
 def main():
     ap = argparse.ArgumentParser()
-    for s in ("grid", "query", "ise", "epan"):
+    for s in ("grid", "query", "ise", "epan", "headline"):
         ap.add_argument(f"--{s}", action="store_true")
     args = ap.parse_args()
-    chosen = [s for s in ("grid", "query", "ise", "epan") if getattr(args, s)] or ["grid", "query", "ise", "epan"]
-    fns = {"grid": grid_report, "query": query_report, "ise": ise_report, "epan": epan_report}
+    chosen = [s for s in ("grid", "query", "ise", "epan", "headline") if getattr(args, s)] or \
+        ["grid", "query", "ise", "epan"]
+    fns = {"grid": grid_report, "query": query_report, "ise": ise_report, "epan": epan_report,
+           "headline": headline_report}
     for s in chosen:
         print(f"section: {s}", file=sys.stderr, flush=True)
         print(json.dumps(fns[s]()), flush=True)
