@@ -2,6 +2,8 @@
 
 * tiny    -- N = 2,000, dx = dy = 1, FP64, 8 x 8 grid (launch-bound).
 * gmm     -- N = 50,000, dx = 5, dy = 1, FP32, 32 x 32 grid.
+* photoz  -- N = 500,000, dx = 5, dy = 1, FP32, 16 x 16 grid (the headline
+             data on a scalar grid).
 * highdim -- N = 1,000,000, dx = 16, dy = 2, FP32, 16 x 16 grid, with the
              x-distances from FP64 coordinate differences (VALU) and with the
              split-bf16 x3 MFMA cross term.
@@ -36,7 +38,8 @@ def timed_grid(model, hx, hy, reps, xterm):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--skip-highdim", action="store_true")
+    ap.add_argument("--skip-highdim", action="store_true",
+                    help="skip the two large sets (photoz 500k and highdim 1M)")
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -68,6 +71,16 @@ def main():
     print(json.dumps({"gmm": out["gmm"]}), file=sys.stderr, flush=True)
 
     if not args.skip_highdim:
+        # photoz 500k, 16 x 16
+        x, y = workloads.photoz(500_000, seed=0)
+        x32, y32 = x.astype(np.float32), y.astype(np.float32)
+        hx, hy = workloads.WORKLOADS["photoz"]["grid"]
+        m = cde.Model(torch.from_numpy(x32).to(dev), torch.from_numpy(y32).to(dev))
+        dt, tot, nf = timed_grid(m, hx, hy, 2, B.CDE_XTERM_AUTO)
+        out["photoz"] = {"s": dt, "evals_per_s": 500_000 * 499_999 * 256 / dt, "nonfinite": int(nf.item())}
+        m.close()
+        print(json.dumps({"photoz": out["photoz"]}), file=sys.stderr, flush=True)
+
         hx, hy = workloads.WORKLOADS["highdim"]["grid"]
         x, y = workloads.highdim()
         x32, y32 = x.astype(np.float32), y.astype(np.float32)

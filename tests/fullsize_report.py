@@ -35,7 +35,8 @@ def rel_point_err(got, ref):
 
 def grid_report():
     """Scalar-bandwidth grids: the 2,000-point FP64 set (totals), the 50k
-    mixture on 32 x 32 (16 sampled points) and the 16-D set on 16 x 16 (16
+    mixture on 32 x 32 (16 sampled points), the 500k photoz set on 16 x 16
+    (16 sampled points) and the 16-D set on 16 x 16 (16
     sampled points of the full 1M set; 256 sampled points of its 20k subset
     and totals of a 5k subset, both x-distance variants)."""
     import numpy as np
@@ -68,6 +69,18 @@ def grid_report():
                   "nonfinite": int(nf.item())}
     del pp
     m.close()
+
+    x, y = workloads.photoz(500_000, seed=0)
+    x32, y32 = x.astype(np.float32), y.astype(np.float32)
+    hx, hy = workloads.WORKLOADS["photoz"]["grid"]
+    m = cde.Model(torch.from_numpy(x32).to(dev), torch.from_numpy(y32).to(dev))
+    _, pp, nf = m.loo_grid(hx, hy, per_point=True)
+    idx = np.sort(np.random.default_rng(23).choice(500_000, 16, replace=False))
+    got = pp[:, torch.from_numpy(idx).to(pp.device)].cpu().numpy()
+    del pp
+    m.close()
+    refp = oracle.loo_grid(x32.astype(np.float64), y32.astype(np.float64), hx, hy, idx=idx, nthreads=NT)
+    out["photoz"] = {"per_point_err_16_sampled_points": rel_point_err(got, refp), "nonfinite": int(nf.item())}
 
     hx, hy = workloads.WORKLOADS["highdim"]["grid"]
     x, y = workloads.highdim()

@@ -178,7 +178,10 @@ WORKLOADS = {
                  precision="f64"),
     "gmm": dict(n=50_000, dx=5, dy=1, grid=(geomspace(0.05, 5.0, 32), geomspace(0.05, 5.0, 32)),
                 precision="f32"),
-    "photoz": dict(n=500_000, dx=5, dy=1, precision="f32", steps=50),
+    # scalar grid on the same data: 1/4x to 4x the normal-reference scale
+    # (hx about 0.08, hy about 0.028 at n = 500,000)
+    "photoz": dict(n=500_000, dx=5, dy=1, precision="f32", steps=50,
+                   grid=(geomspace(0.02, 0.32, 16), geomspace(0.007, 0.112, 16))),
     "highdim": dict(n=1_000_000, dx=16, dy=2,
                     grid=(geomspace(0.2, 5.0, 16), geomspace(0.02, 1.0, 16)), precision="f32"),
 }
