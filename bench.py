@@ -64,19 +64,45 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--trace-steps", type=int, default=0,
+                    help="after the timed steps, run this many untimed ascent steps from the "
+                         "normal-reference start and report the whole trace of S")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (a known-size kernel "
                          "for scaling hardware byte counters)")
     return ap.parse_args()
 
 
+def host_cpu():
+    """(threads the oracle may use, nproc, CPU model): every core this
+    process may run on, capped by OMP_NUM_THREADS when the host sets it (a
+    GPU machine gives each GPU a share of its cores that way)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(avail, int(omp)) if omp.isdigit() and int(omp) > 0 else avail
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return threads, os.cpu_count() or 1, model
+
+
 def cpu_baseline(x64, y64, h, target_s):
     """The FP64 oracle (unchanged) on a bounded sample: m points i, each
-    against all N points j, value and gradient, all host threads."""
+    against all N points j, value and gradient, on every host core this
+    process may use."""
     import numpy as np
 
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    threads, nproc, cpu_model = host_cpu()
     n = x64.shape[0]
     rng = np.random.default_rng(123)
     m = 8 * threads
@@ -90,8 +116,11 @@ def cpu_baseline(x64, y64, h, target_s):
         m = min(n, int(m * max(2.0, 0.5 * target_s / max(dt, 1e-3))))
     rate = m * (n - 1) / dt
     return {"value": rate, "unit": "pair-kernel evals/s", "cores": threads, "kind": "oracle",
+            "nproc": nproc, "cpu_model": cpu_model,
             "sample": f"value+gradient for {m} sampled points i, each against all {n - 1} j != i "
-                      f"(single-setting FP64 oracle, {threads} threads, {dt:.2f} s wall)"}
+                      f"(single-setting FP64 oracle, {threads} threads = the cores this process may "
+                      f"use (nproc {nproc}, OMP_NUM_THREADS {os.environ.get('OMP_NUM_THREADS', 'unset')}), "
+                      f"{dt:.2f} s wall)"}
 
 
 def main():
@@ -181,6 +210,18 @@ def main():
     torch.cuda.synchronize()
     vo_ms = 1e3 * (time.perf_counter() - t0) / 3
 
+    trace_run = None
+    if args.trace_steps > 0:
+        t0 = time.perf_counter()
+        st = cde.ascend(model, h0.tolist(), steps=args.trace_steps)
+        tr = st["trace"]
+        trace_run = {"steps": args.trace_steps, "first": tr[0], "last": tr[-1], "max": max(tr),
+                     "argmax_step": int(max(range(len(tr)), key=lambda k: tr[k])),
+                     "nondecreasing_steps": int(sum(b >= a for a, b in zip(tr, tr[1:]))),
+                     "h_start": h0.tolist(), "h_end": st["h"], "trace": tr,
+                     "wall_s": time.perf_counter() - t0}
+        print(f"bench: ascent trace of {args.trace_steps} steps done", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(x32.astype(np.float64), y32.astype(np.float64), h0.tolist(),
@@ -199,6 +240,8 @@ def main():
         "trace_first_last": [trace[0], trace[-1]] if trace else None,
         "secondary": {"value_only_ms": vo_ms, "value_only_pair_evals_per_s": pairs / (vo_ms * 1e-3)},
     }
+    if trace_run is not None:
+        out["ascent"] = trace_run
     print(json.dumps(out))
     model.close()
 

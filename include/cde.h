@@ -37,6 +37,17 @@
  *     After a non-OK status, cde_last_error() returns a message (per thread).
  *   - Results are deterministic: fixed reduction orders, no float atomics on
  *     result paths, so repeated calls give identical bits.
+ *   - Bandwidths: every h must be finite and > 0 (else CDE_EINVAL) and inside
+ *     the range the kernels' arithmetic represents for the model's data
+ *     (else CDE_EUNSUPPORTED, with a message): with range_k = max_i x_ik -
+ *     min_i x_ik the extent of dimension k and c_k = log2(e) / (2 h_k^2),
+ *     each c_k <= 2^59 and sum_k range_k^2 c_k <= 2^100 over the x dimensions
+ *     and over the y dimensions (FP32 models), or 2^900 for both (FP64
+ *     models).  cde_check_bandwidths applies the same test on the host.
+ *     Training data must be finite: a model whose data hold a NaN or an
+ *     infinity rejects every call with CDE_EINVAL.  The extent is computed
+ *     by cde_create on its stream; the model's first call that checks
+ *     bandwidths waits for that work to finish.
  */
 #ifndef CDE_H
 #define CDE_H
@@ -48,7 +59,7 @@
 extern "C" {
 #endif
 
-#define CDE_ABI_VERSION 3
+#define CDE_ABI_VERSION 4
 
 typedef struct cde_model cde_model; /* opaque handle */
 
@@ -103,11 +114,29 @@ const char* cde_last_error(void);
 cde_status cde_create(cde_model** out, const void* x_dev, const void* y_dev, int64_t n,
                       int32_t dx, int32_t dy, cde_precision precision, void* stream);
 
-/* Release the model and its device memory (synchronises the device first). */
+/* Release a model made by cde_create (the training set of Section 2 held on
+ * the device) and all of its device and pinned host memory.  Frees
+ * synchronise the device, so no call on the model may still be running on
+ * any stream.  NULL is accepted (CDE_OK).  Returns CDE_EDEVICE if a HIP
+ * release call fails; the handle is invalid afterwards either way. */
 cde_status cde_destroy(cde_model* m);
 
-/* Device bytes held by the model (packed data, per-point shifts, scratch). */
+/* Device bytes the model holds now: the packed training set of Section 2
+ * (with its extent record), per-point shifts, the spatial index and the
+ * per-call scratch of the criterion of Section 3, which grows to the largest
+ * call so far and is kept.  Host-only; 0 for NULL.  A serving admission
+ * controller budgets HBM with it. */
 size_t cde_model_device_bytes(const cde_model* m);
+
+/* Host-only form of the bandwidth range test of every model call (see
+ * "Bandwidths" above) for one diagonal setting of the Gaussian kernel of
+ * Section 2: range [dx+dy] are the data's per-dimension extents (max - min,
+ * finite, >= 0), h [dx+dy] the bandwidths (hx_1..hx_dx, hy_1..hy_dy).
+ * Returns CDE_OK, CDE_EINVAL (NULL pointer, dx or dy < 1, dx + dy > 18,
+ * non-finite or negative range, h not finite and > 0) or CDE_EUNSUPPORTED
+ * (outside the representable range of `precision`).  No device is used. */
+cde_status cde_check_bandwidths(const double* range, int32_t dx, int32_t dy, const double* h,
+                                cde_precision precision);
 
 /* Device bytes a model of this shape holds after cde_create and one
  * cde_loo_loglik call over an n_hx x n_hy grid (Gaussian kernel, default cross term)

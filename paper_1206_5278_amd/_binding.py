@@ -18,7 +18,7 @@ CDE_F32, CDE_F64 = 0, 1
 CDE_COND, CDE_JOINT = 0, 1
 CDE_XTERM_AUTO, CDE_XTERM_VALU, CDE_XTERM_MFMA_BF16X3 = 0, 1, 2
 CDE_GAUSSIAN, CDE_EPANECHNIKOV = 0, 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 # Every symbol the header declares, with (restype, argtypes).
 _vp = ctypes.c_void_p
@@ -40,6 +40,7 @@ SIGNATURES = {
     "cde_conditional_mean": (ctypes.c_int, [_vp, _vp, _i64, _dp, _vp, _vp]),
     "cde_density_summary": (ctypes.c_int, [_vp, _vp, _i64, _i64, ctypes.c_double, _vp, _vp]),
     "cde_cv_ise": (ctypes.c_int, [_vp, _dp, _vp, _vp, _vp]),
+    "cde_check_bandwidths": (ctypes.c_int, [_dp, _i32, _i32, _dp, ctypes.c_int]),
 }
 
 

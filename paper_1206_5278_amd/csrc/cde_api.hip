@@ -1,6 +1,7 @@
 // cde_api.hip -- host side of the C ABI declared in include/cde.h: argument
 // validation, per-setting coefficient preparation in FP64, device memory of
 // the model, and stream-ordered kernel launches.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -50,6 +51,125 @@ bool valid_bandwidths(const double* h, int k)
     for (int q = 0; q < k; ++q)
         if (!(h[q] > 0.0) || !std::isfinite(h[q])) return false;
     return true;
+}
+
+// Representable range of a Gaussian setting for a model of precision p, over
+// data whose per-dimension extents (max - min) are `range`:
+//   - every exponent coefficient c_k = log2(e) / (2 h_k^2) is at most CMAX,
+//     so that it, and the excluded-pair sentinel 1e20 times it, stay finite in
+//     the kernels' arithmetic (FP32 for FP32 models);
+//   - the largest possible exponent, sum_k range_k^2 c_k over the x
+//     dimensions and over the y dimensions, is at most SMAX, so that no
+//     pair's exponent overflows.
+// Outside it the kernels would produce inf - inf or 0 * inf.
+constexpr double CMAX_F32 = 0x1p59, SMAX_F32 = 0x1p100;
+constexpr double CMAX_F64 = 0x1p900, SMAX_F64 = 0x1p900;
+
+// Largest exponent of one group of dimensions; h_step = 0 broadcasts h[0].
+double group_exponent(const double* range, int cnt, const double* h, int h_step, double* cmax)
+{
+    double s = 0.0, cm = 0.0;
+    for (int k = 0; k < cnt; ++k) {
+        const double hk = h[k * h_step];
+        const double c = LOG2E / (2.0 * hk * hk);
+        cm = std::max(cm, c);
+        s += range[k] * range[k] * c;
+    }
+    *cmax = cm;
+    return s;
+}
+
+cde_status check_group(const double* range, int cnt, const double* h, int h_step, cde_precision p,
+                       const char* who, const char* axis)
+{
+    double cm = 0.0;
+    const double e = group_exponent(range, cnt, h, h_step, &cm);
+    const double cmax = p == CDE_F64 ? CMAX_F64 : CMAX_F32, smax = p == CDE_F64 ? SMAX_F64 : SMAX_F32;
+    if (cm <= cmax && e <= smax) return CDE_OK;
+    char msg[320];
+    std::snprintf(msg, sizeof msg,
+                  "%s: %s bandwidth too small for the kernels' %s arithmetic on this data "
+                  "(needs log2(e)/(2h^2) <= 2^%d and sum_k range_k^2 log2(e)/(2h_k^2) <= 2^%d; "
+                  "got %.3g and %.3g)",
+                  who, axis, p == CDE_F64 ? "FP64" : "FP32", p == CDE_F64 ? 900 : 59,
+                  p == CDE_F64 ? 900 : 100, cm, e);
+    return fail(CDE_EUNSUPPORTED, msg);
+}
+
+// One diagonal setting h [dx + dy] against the extents `range` [dx + dy].
+cde_status check_setting(const double* range, int dx, int dy, const double* h, cde_precision p,
+                         const char* who)
+{
+    cde_status st = check_group(range, dx, h, 1, p, who, "x");
+    if (st != CDE_OK) return st;
+    return check_group(range + dx, dy, h + dx, 1, p, who, "y");
+}
+
+unsigned long long decode_ordered(unsigned long long u)
+{
+    return (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
+}
+
+// The model's data extent, computed by cde_create; the first call waits for
+// its device-to-host copy.
+cde_status ensure_extent(cde_model* m, const char* who)
+{
+    if (!m->ext_known) {
+        hipError_t e = hipEventSynchronize(m->ext_event);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(data extent)");
+        const int d = m->dx + m->dy;
+        for (int c = 0; c < d; ++c) {
+            const unsigned long long lo = decode_ordered(m->ext_host[2 * c]);
+            const unsigned long long hi = decode_ordered(m->ext_host[2 * c + 1]);
+            double a, b;
+            std::memcpy(&a, &lo, sizeof a);
+            std::memcpy(&b, &hi, sizeof b);
+            m->range[c] = b - a;
+        }
+        m->data_finite = m->ext_host[2 * MAXP] == 0;
+        m->ext_known = true;
+    }
+    if (!m->data_finite)
+        return fail(CDE_EINVAL, std::string(who) + ": the training data hold non-finite values");
+    return CDE_OK;
+}
+
+// Bandwidth checks of the model calls: finite and > 0 (CDE_EINVAL), then
+// within the representable range for the model's data (CDE_EUNSUPPORTED).
+cde_status check_model_settings(cde_model* m, const double* h, int g, const char* who)
+{
+    const int p = m->dx + m->dy;
+    if (!valid_bandwidths(h, g * p))
+        return fail(CDE_EINVAL, std::string(who) + ": bandwidths must be finite and > 0");
+    cde_status st = ensure_extent(m, who);
+    if (st != CDE_OK) return st;
+    for (int s = 0; s < g; ++s) {
+        st = check_setting(m->range, m->dx, m->dy, h + (size_t)s * p, m->prec, who);
+        if (st != CDE_OK) return st;
+    }
+    return CDE_OK;
+}
+
+cde_status check_model_grid(cde_model* m, const double* hx, int n_hx, const double* hy, int n_hy,
+                            const char* who)
+{
+    if (!valid_bandwidths(hx, n_hx) || !valid_bandwidths(hy, n_hy))
+        return fail(CDE_EINVAL, std::string(who) + ": bandwidths must be finite and > 0");
+    cde_status st = ensure_extent(m, who);
+    if (st != CDE_OK) return st;
+    for (int a = 0; a < n_hx; ++a)
+        if ((st = check_group(m->range, m->dx, hx + a, 0, m->prec, who, "x")) != CDE_OK) return st;
+    for (int b = 0; b < n_hy; ++b)
+        if ((st = check_group(m->range + m->dx, m->dy, hy + b, 0, m->prec, who, "y")) != CDE_OK)
+            return st;
+    return CDE_OK;
+}
+
+// Device bytes of a model's packed rows plus the extent record in their tail.
+constexpr size_t EXT_BYTES = 512;
+size_t packed_bytes(int64_t npad, int stride, size_t elt)
+{
+    return ((size_t)npad * stride * elt + 255) / 256 * 256 + EXT_BYTES;
 }
 
 // Gaussian coefficients of one diagonal setting (Section 2: K_h(t) =
@@ -276,18 +396,33 @@ cde_status cde_create(cde_model** out, const void* x_dev, const void* y_dev, int
         e = hipDeviceGetAttribute(&m->ncu, hipDeviceAttributeMultiprocessorCount, m->device);
         if (e != hipSuccess) { delete m; return hip_fail(e, "hipDeviceGetAttribute"); }
         const size_t elt = precision == CDE_F64 ? sizeof(double) : sizeof(float);
-        const size_t pts_bytes = (size_t)m->npad * m->stride * elt;
+        const size_t pts_bytes = packed_bytes(m->npad, m->stride, elt);
         e = hipMalloc(&m->pts, pts_bytes);
         if (e != hipSuccess) { delete m; return hip_fail(e, "hipMalloc(points)"); }
         m->bytes = pts_bytes;
+        m->ext_dev = (unsigned long long*)((char*)m->pts + (pts_bytes - EXT_BYTES));
+        auto undo = [&](hipError_t err, const char* what) {
+            if (m->ext_event) (void)hipEventDestroy(m->ext_event);
+            if (m->ext_host) (void)hipHostFree(m->ext_host);
+            (void)hipFree(m->pts);
+            delete m;
+            return hip_fail(err, what);
+        };
+        e = hipHostMalloc((void**)&m->ext_host, EXT_BYTES, hipHostMallocDefault);
+        if (e != hipSuccess) { m->ext_host = nullptr; return undo(e, "hipHostMalloc(data extent)"); }
+        e = hipEventCreateWithFlags(&m->ext_event, hipEventDisableTiming);
+        if (e != hipSuccess) { m->ext_event = nullptr; return undo(e, "hipEventCreate"); }
         hipStream_t s = (hipStream_t)stream;
         e = precision == CDE_F64 ? launch_pack<double>(m, (const double*)x_dev, (const double*)y_dev, s)
                                  : launch_pack<float>(m, (const float*)x_dev, (const float*)y_dev, s);
-        if (e != hipSuccess) {
-            (void)hipFree(m->pts);
-            delete m;
-            return hip_fail(e, "launch k_pack");
-        }
+        if (e != hipSuccess) return undo(e, "launch k_pack");
+        e = precision == CDE_F64 ? launch_extent<double>(m, m->ext_dev, s) : launch_extent<float>(m, m->ext_dev, s);
+        if (e != hipSuccess) return undo(e, "launch k_extent");
+        e = hipMemcpyAsync(m->ext_host, m->ext_dev, sizeof(unsigned long long) * (2 * MAXP + 1),
+                           hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return undo(e, "hipMemcpyAsync(data extent)");
+        e = hipEventRecord(m->ext_event, s);
+        if (e != hipSuccess) return undo(e, "hipEventRecord(data extent)");
         *out = m;
         return CDE_OK;
     } catch (...) {
@@ -300,6 +435,15 @@ cde_status cde_destroy(cde_model* m)
     if (!m) return CDE_OK;
     DeviceGuard guard(m->device);
     cde_status st = CDE_OK;
+    if (m->ext_event) {
+        hipError_t e = hipEventSynchronize(m->ext_event);  // the extent copy targets ext_host
+        if (e == hipSuccess) e = hipEventDestroy(m->ext_event);
+        if (e != hipSuccess && st == CDE_OK) st = hip_fail(e, "hipEventDestroy");
+    }
+    if (m->ext_host) {
+        hipError_t e = hipHostFree(m->ext_host);
+        if (e != hipSuccess && st == CDE_OK) st = hip_fail(e, "hipHostFree");
+    }
     for (void* p : {m->pts, m->nn, m->xmean, m->spts, m->perm, m->tbox, m->sbox, m->scratch}) {
         if (!p) continue;
         hipError_t e = hipFree(p);
@@ -329,7 +473,7 @@ size_t cde_workspace_bytes(int64_t n, int32_t dx, int32_t dy, cde_precision prec
             hipDeviceGetAttribute(&t.ncu, hipDeviceAttributeMultiprocessorCount, t.device) != hipSuccess)
             t.ncu = 0;
         const size_t elt = precision == CDE_F64 ? sizeof(double) : sizeof(float);
-        size_t bytes = (size_t)t.npad * t.stride * elt;
+        size_t bytes = packed_bytes(t.npad, t.stride, elt);
         if (n_hx == 0) return bytes;
         if (precision == CDE_F64)
             return bytes + round_scratch(diag_list_scratch<double>(&t, n_hx * n_hy, false, nullptr));
@@ -337,6 +481,26 @@ size_t cde_workspace_bytes(int64_t n, int32_t dx, int32_t dy, cde_precision prec
                round_scratch(grid_call_scratch(&t, n_hx, n_hy));
     } catch (...) {
         return 0;
+    }
+}
+
+cde_status cde_check_bandwidths(const double* range, int32_t dx, int32_t dy, const double* h,
+                                cde_precision precision)
+{
+    try {
+        if (!range || !h) return fail(CDE_EINVAL, "cde_check_bandwidths: NULL pointer");
+        if (dx < 1 || dy < 1 || dx + dy > MAXP)
+            return fail(CDE_EINVAL, "cde_check_bandwidths: need dx, dy >= 1 and dx + dy <= 18");
+        if (precision != CDE_F32 && precision != CDE_F64)
+            return fail(CDE_EINVAL, "cde_check_bandwidths: unknown precision");
+        for (int k = 0; k < dx + dy; ++k)
+            if (!(range[k] >= 0.0) || !std::isfinite(range[k]))
+                return fail(CDE_EINVAL, "cde_check_bandwidths: ranges must be finite and >= 0");
+        if (!valid_bandwidths(h, dx + dy))
+            return fail(CDE_EINVAL, "cde_check_bandwidths: bandwidths must be finite and > 0");
+        return check_setting(range, dx, dy, h, precision, "cde_check_bandwidths");
+    } catch (...) {
+        return fail(CDE_EDEVICE, "cde_check_bandwidths: unexpected exception");
     }
 }
 
@@ -350,10 +514,10 @@ cde_status cde_loo_loglik_list(cde_model* m, const double* h, int32_t g, cde_cri
         if (g < 1 || g > 4096) return fail(CDE_EINVAL, "cde_loo_loglik_list: g must be in [1, 4096]");
         if (criterion != CDE_COND && criterion != CDE_JOINT)
             return fail(CDE_EINVAL, "cde_loo_loglik_list: unknown criterion");
-        if (!valid_bandwidths(h, g * (m->dx + m->dy)))
-            return fail(CDE_EINVAL, "cde_loo_loglik_list: bandwidths must be finite and > 0");
         if (kernel != CDE_GAUSSIAN && kernel != CDE_EPANECHNIKOV)
             return fail(CDE_EINVAL, "cde_loo_loglik_list: unknown kernel");
+        cde_status st = check_model_settings(m, h, g, "cde_loo_loglik_list");
+        if (st != CDE_OK) return st;
         DeviceGuard guard(m->device);
         hipStream_t s = (hipStream_t)stream;
         if (kernel == CDE_EPANECHNIKOV)
@@ -378,8 +542,6 @@ cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const do
         if (!totals_dev) return fail(CDE_EINVAL, "cde_loo_loglik: totals_dev is NULL");
         if (n_hx < 1 || n_hx > 64 || n_hy < 1 || n_hy > 64)
             return fail(CDE_EINVAL, "cde_loo_loglik: grid sizes must be in [1, 64]");
-        if (!valid_bandwidths(hx, n_hx) || !valid_bandwidths(hy, n_hy))
-            return fail(CDE_EINVAL, "cde_loo_loglik: bandwidths must be finite and > 0");
         if (criterion != CDE_COND && criterion != CDE_JOINT)
             return fail(CDE_EINVAL, "cde_loo_loglik: unknown criterion");
         if (xterm != CDE_XTERM_AUTO && xterm != CDE_XTERM_VALU && xterm != CDE_XTERM_MFMA_BF16X3)
@@ -390,6 +552,10 @@ cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const do
         if (xt && (m->dx < 16 || m->prec != CDE_F32 || kernel != CDE_GAUSSIAN))
             return fail(CDE_EUNSUPPORTED,
                         "cde_loo_loglik: the MFMA cross term needs dx >= 16, FP32 data and the Gaussian kernel");
+        {
+            cde_status st = check_model_grid(m, hx, n_hx, hy, n_hy, "cde_loo_loglik");
+            if (st != CDE_OK) return st;
+        }
         DeviceGuard guard(m->device);
         hipStream_t s = (hipStream_t)stream;
         const int g = n_hx * n_hy;
@@ -450,8 +616,10 @@ cde_status cde_loo_grad(cde_model* m, const double* h, cde_criterion criterion, 
         if (!total_dev || !grad_dev) return fail(CDE_EINVAL, "cde_loo_grad: output pointer is NULL");
         if (criterion != CDE_COND && criterion != CDE_JOINT)
             return fail(CDE_EINVAL, "cde_loo_grad: unknown criterion");
-        if (!valid_bandwidths(h, m->dx + m->dy))
-            return fail(CDE_EINVAL, "cde_loo_grad: bandwidths must be finite and > 0");
+        {
+            cde_status st = check_model_settings(m, h, 1, "cde_loo_grad");
+            if (st != CDE_OK) return st;
+        }
         DeviceGuard guard(m->device);
         hipStream_t s = (hipStream_t)stream;
         return m->prec == CDE_F64
@@ -469,9 +637,11 @@ cde_status cde_cv_ise(cde_model* m, const double* h, double* out_dev, double* te
     try {
         if (!m) return fail(CDE_EINVAL, "cde_cv_ise: model is NULL");
         if (!out_dev) return fail(CDE_EINVAL, "cde_cv_ise: output pointer is NULL");
-        if (!valid_bandwidths(h, m->dx + m->dy))
-            return fail(CDE_EINVAL, "cde_cv_ise: bandwidths must be finite and > 0");
         if (m->prec != CDE_F32) return fail(CDE_EUNSUPPORTED, "cde_cv_ise: FP32 models only");
+        {
+            cde_status st = check_model_settings(m, h, 1, "cde_cv_ise");
+            if (st != CDE_OK) return st;
+        }
         if (m->n > CDE_ISE_MAX_N) return fail(CDE_EUNSUPPORTED, "cde_cv_ise: n > 262144");
         DeviceGuard guard(m->device);
         hipStream_t s = (hipStream_t)stream;
@@ -507,8 +677,10 @@ cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const 
         if (q < 0 || k < 0 || k > 4096) return fail(CDE_EINVAL, "cde_density_query: need q >= 0, 0 <= k <= 4096");
         if (q > 0 && k > 0 && (!xq_dev || !ygrid_dev || !f_dev))
             return fail(CDE_EINVAL, "cde_density_query: NULL device pointer");
-        if (!valid_bandwidths(h, m->dx + m->dy))
-            return fail(CDE_EINVAL, "cde_density_query: bandwidths must be finite and > 0");
+        {
+            cde_status st = check_model_settings(m, h, 1, "cde_density_query");
+            if (st != CDE_OK) return st;
+        }
         if (q == 0 || k == 0) return CDE_OK;
         if (q * k >= (int64_t(1) << 40)) return fail(CDE_EUNSUPPORTED, "cde_density_query: q*k too large");
         DeviceGuard guard(m->device);
@@ -552,8 +724,10 @@ cde_status cde_conditional_mean(cde_model* m, const void* xq_dev, int64_t q, con
         if (!m) return fail(CDE_EINVAL, "cde_conditional_mean: model is NULL");
         if (q < 0) return fail(CDE_EINVAL, "cde_conditional_mean: q must be >= 0");
         if (q > 0 && (!xq_dev || !mean_dev)) return fail(CDE_EINVAL, "cde_conditional_mean: NULL device pointer");
-        if (!valid_bandwidths(h, m->dx + m->dy))
-            return fail(CDE_EINVAL, "cde_conditional_mean: bandwidths must be finite and > 0");
+        {
+            cde_status st = check_model_settings(m, h, 1, "cde_conditional_mean");
+            if (st != CDE_OK) return st;
+        }
         if (q == 0) return CDE_OK;
         if (q >= (int64_t(1) << 40)) return fail(CDE_EUNSUPPORTED, "cde_conditional_mean: q too large");
         DeviceGuard guard(m->device);

@@ -80,4 +80,14 @@ struct cde_model {
     void* scratch = nullptr; // block partials and flags
     size_t scratch_bytes = 0;
     size_t bytes = 0;
+    // Data extent (per-dimension minimum and maximum of the training set and
+    // a non-finite flag), computed on the device by cde_create and copied to
+    // pinned host memory; read once, at the first call that checks
+    // bandwidths (ext_event marks the copy's completion).
+    unsigned long long* ext_dev = nullptr;   // [2 * MAXP + 1], in the tail of pts
+    unsigned long long* ext_host = nullptr;  // pinned copy
+    hipEvent_t ext_event = nullptr;
+    bool ext_known = false;
+    bool data_finite = true;
+    double range[cde::MAXP] = {};            // max - min per dimension
 };

@@ -8,6 +8,10 @@ namespace cde {
 // Pack row-major x [n][dx] and y [n][dy] into the model's [npad][stride] rows.
 template <typename T>
 hipError_t launch_pack(cde_model* m, const T* x, const T* y, hipStream_t stream);
+// Per-dimension minimum and maximum of the packed rows and a non-finite flag
+// into ext [2 * MAXP + 1] (order-preserving 64-bit encodings of the doubles).
+template <typename T>
+hipError_t launch_extent(const cde_model* m, unsigned long long* ext, hipStream_t stream);
 
 // Diagonal-bandwidth LOO pass (value, optionally gradient) for `nsets`
 // settings.  The j range is split into `chunks` chunks (diag_chunks); the

@@ -21,8 +21,9 @@
 // exponent relative to a per-point reference (a running minimum, so the
 // largest term is about 1 and nothing overflows or underflows: den' >= 1 and
 // num' >= 1 by construction).  Values are summed in FP32 over 32-point
-// subtiles, the subtile sums are added into plain per-tile sums, and those
-// are folded into Kahan-compensated totals once per 256-point tile.  The
+// subtiles, the subtile sums are added into plain FP32 per-tile sums, and
+// those are added once per 256-point tile into FP64 per-point totals held in
+// LDS (FP64 accumulation in place of a compensated FP32 pair).  The
 // reference is moved lazily, only when a subtile holds a term more than 2^32
 // above it: the totals and the subtile's own sums are then rescaled, which is
 // exact in real arithmetic (the common factor cancels in num/den); a subtile

@@ -764,11 +764,15 @@ __global__ void k_compact_points(const int* __restrict__ flag, int n, int npad, 
 
 // Exact recomputation of queued (setting, point) entries: one wave per entry,
 // lanes split j; pass 1 finds the entry's largest term, pass 2 sums all terms
-// relative to it (Kahan per lane, FP64 across lanes).
+// relative to it (Kahan per lane, FP64 across lanes).  When more entries were
+// flagged than the queue holds (fix_count > fix_cap), the waves instead scan
+// every (setting, point) entry of numbuf and recompute each one below the
+// same 2^-1000 threshold, so no flagged entry is ever left unfixed.
 template <int DX, int DY>
 __global__ __launch_bounds__(TILE) void k_grid_fixup(const float* __restrict__ pts,
                                                      const double* __restrict__ nn, int n, int npad,
                                                      GridArgs ga, GridFin gf, int crit,
+                                                     const double* __restrict__ numbuf,
                                                      const double* __restrict__ denbuf,
                                                      double* __restrict__ ell,
                                                      const int* __restrict__ fix_count,
@@ -778,10 +782,20 @@ __global__ __launch_bounds__(TILE) void k_grid_fixup(const float* __restrict__ p
     const int lane = threadIdx.x & 63;
     const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nw = (gridDim.x * blockDim.x) >> 6;
-    const int count = min(*fix_count, fix_cap);
-    for (int e = wid; e < count; e += nw) {
-        const int2 gi = fix_list[e];
-        const int g = gi.x, i = gi.y;
+    const int queued = *fix_count;
+    const bool scan = queued > fix_cap;
+    const int64_t count = scan ? (int64_t)ga.gx * ga.gy * n : queued;
+    for (int64_t e = wid; e < count; e += nw) {
+        int g, i;
+        if (scan) {
+            g = (int)(e / n);
+            i = (int)(e - (int64_t)g * n);
+            if (numbuf[(size_t)g * npad + i] >= 0x1p-1000) continue;  // wave-uniform
+        } else {
+            const int2 gi = fix_list[e];
+            g = gi.x;
+            i = gi.y;
+        }
         const int a = g / ga.gy, b = g - a * ga.gy;
         const float ca = ga.cx[a], cb = ga.cy[b];
         double own[S];
@@ -965,8 +979,8 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
                        w.fix_cap, (int*)nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((k_grid_fixup<DX, DY>), dim3(1024), dim3(TILE), 0, stream, pts, nn, n, npad,
-                       ga, gf, crit, (const double*)w.denbuf, w.ell, (const int*)w.fix_count,
-                       (const int2*)w.fix_list, w.fix_cap);
+                       ga, gf, crit, (const double*)w.numbuf, (const double*)w.denbuf, w.ell,
+                       (const int*)w.fix_count, (const int2*)w.fix_list, w.fix_cap);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_grid_rows, dim3((unsigned)G), dim3(256), 0, stream, (const double*)w.ell, n,
                        npad, totals, per_point, counts);
@@ -1064,7 +1078,9 @@ hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* h
 size_t grid_work_bytes(const cde_model* m, int n_hx, int n_hy)
 {
     const size_t G = (size_t)n_hx * n_hy;
-    const size_t fix_cap = std::max<size_t>(G * m->npad / 8, 1 << 20);  // 1/8 of all entries
+    // queue of entries for the per-entry fixup: 1/64 of all entries (more are
+    // handled by k_grid_fixup's scan of numbuf)
+    const size_t fix_cap = std::max<size_t>(G * m->npad / 64, 4096);
     const size_t ntl = (size_t)((n_hx + 15) / 16) * ((n_hy + 15) / 16);  // grid tiles
     return sizeof(double) * (2 * G + n_hx) * m->npad + (2 * ntl * m->npad + 128) * sizeof(int) +
            fix_cap * sizeof(int2) + 64;

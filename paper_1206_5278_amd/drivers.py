@@ -80,7 +80,7 @@ def ascend(model: Model, h0, steps: int = 50, lr: float = 0.05, criterion: str =
         opt.zero_grad()
         s = LooLogLik.apply(theta, model, criterion)
         (-s).backward()  # maximise S
-        trace.append(float(s))
+        trace.append(float(s.detach()))
         opt.step()
         st = opt.state[theta]
         state = {"step": step + 1, "theta": theta.detach().tolist(), "trace": trace,

@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.cde_abi_version() == 3
+    assert lib.cde_abi_version() == 4
 
 
 def test_invalid_arguments_return_status(lib):
@@ -79,10 +79,11 @@ def test_product_path_does_not_reference_oracle():
 
 def test_workspace_bytes_host_arithmetic(lib):
     from paper_1206_5278_amd import _binding as B
-    # after cde_create alone: the packed [npad][stride] rows (stride = dx + dy rounded up to 4)
-    assert B.workspace_bytes(1000, 5, 1, B.CDE_F32) == 1024 * 8 * 4
-    assert B.workspace_bytes(1000, 5, 1, B.CDE_F64) == 1024 * 8 * 8
-    assert B.workspace_bytes(256, 16, 2, B.CDE_F32) == 256 * 20 * 4
+    # after cde_create alone: the packed [npad][stride] rows (stride = dx + dy
+    # rounded up to 4), 256-byte aligned, and the 512-byte data-extent record
+    assert B.workspace_bytes(1000, 5, 1, B.CDE_F32) == 1024 * 8 * 4 + 512
+    assert B.workspace_bytes(1000, 5, 1, B.CDE_F64) == 1024 * 8 * 8 + 512
+    assert B.workspace_bytes(256, 16, 2, B.CDE_F32) == 256 * 20 * 4 + 512
     # a grid call adds shifts and scratch, growing with the grid
     base = B.workspace_bytes(5000, 3, 1, B.CDE_F32)
     g8 = B.workspace_bytes(5000, 3, 1, B.CDE_F32, 8, 8)
@@ -92,3 +93,41 @@ def test_workspace_bytes_host_arithmetic(lib):
     for args in [(1, 1, 1, 0), (100, 0, 1, 0), (100, 9, 1, 0), (100, 1, 3, 0), (100, 1, 1, 7),
                  (100, 1, 1, 0, 65, 1), (100, 1, 1, 0, 4, 0), (100, 1, 1, 0, -1, -1)]:
         assert B.workspace_bytes(*args) == 0, args
+
+
+def test_bandwidth_range_check_host(lib):
+    """The representable-range rule of every model call, on the host: each
+    c_k = log2(e)/(2 h_k^2) <= 2^59 and sum_k range_k^2 c_k <= 2^100 per axis
+    (FP32 models); 2^900 for both (FP64 models)."""
+    import math
+
+    from paper_1206_5278_amd import _binding as B
+
+    def check(rng, h, prec=B.CDE_F32, dx=5, dy=1):
+        return lib.cde_check_bandwidths(B.doubles(rng), dx, dy, B.doubles(h), prec)
+
+    one = [1.0] * 6
+    assert check(one, [0.1] * 6) == B.CDE_OK
+    # the coefficient bound: c = 2^59 exactly at h* = sqrt(log2(e) / 2^60)
+    hstar = math.sqrt(math.log2(math.e) / 2.0 ** 60)
+    assert check([0.0] * 6, [0.1] * 5 + [hstar * (1 + 1e-9)]) == B.CDE_OK
+    assert check([0.0] * 6, [0.1] * 5 + [hstar * (1 - 1e-9)]) == B.CDE_EUNSUPPORTED
+    assert b"y bandwidth" in lib.cde_last_error()
+    assert check([0.0] * 6, [hstar * 0.5] + [0.1] * 5) == B.CDE_EUNSUPPORTED
+    assert b"x bandwidth" in lib.cde_last_error()
+    # the data-relative bound: the largest exponent sum_k range_k^2 c_k
+    big = [1e20, 1.0, 1.0, 1.0, 1.0, 1.0]
+    assert check(big, [1.0] * 6) == B.CDE_EUNSUPPORTED
+    assert check(big, [1e6] + [1.0] * 5) == B.CDE_OK
+    # the same settings on FP64 models, whose bounds are 2^900
+    assert check(big, [1.0] * 6, B.CDE_F64) == B.CDE_OK
+    assert check(one, [1e-100] * 6, B.CDE_F64) == B.CDE_OK
+    assert check(one, [1e-140] * 6, B.CDE_F64) == B.CDE_EUNSUPPORTED
+    # malformed arguments
+    assert check(one, [0.1] * 5 + [0.0]) == B.CDE_EINVAL
+    assert check(one, [0.1] * 5 + [float("nan")]) == B.CDE_EINVAL
+    assert check([1.0] * 5 + [-1.0], [0.1] * 6) == B.CDE_EINVAL
+    assert check([1.0] * 5 + [float("inf")], [0.1] * 6) == B.CDE_EINVAL
+    assert check(one, [0.1] * 6, 7) == B.CDE_EINVAL
+    assert lib.cde_check_bandwidths(None, 5, 1, B.doubles([0.1] * 6), 0) == B.CDE_EINVAL
+    assert check(one, [0.1] * 6, B.CDE_F32, 0, 1) == B.CDE_EINVAL

@@ -1,0 +1,144 @@
+"""GPU checks of the argument contract and of rare numerical paths, through
+the C ABI: the bandwidth range test against the model's data extent,
+non-finite training data, results at the edge of the supported bandwidth
+range, the per-entry fixup when more entries need it than its queue holds,
+and the n = 2 closed form of the criterion and of gradient ascent (Section 3,
+eq. 3: at n = 2, l_i = log phi_hy(y_1 - y_2), maximised at hy = |y_1 - y_2|)."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+NT = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def cde():
+    import paper_1206_5278_amd as m
+    return m
+
+
+def hmin_f32():
+    """Smallest bandwidth whose coefficient log2(e)/(2h^2) is <= 2^59."""
+    return math.sqrt(math.log2(math.e) / 2.0 ** 60)
+
+
+def status_of(fn):
+    from paper_1206_5278_amd import CdeError
+    try:
+        fn()
+    except CdeError as e:
+        return e.status
+    return 0
+
+
+def test_bandwidths_outside_the_range_are_rejected():
+    print("case: bandwidth range rejection, n=300 dx=3", flush=True)
+    from paper_1206_5278_amd import _binding as B
+    x, y = workloads.gmm(300, seed=41, dx=3)
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    tiny = 0.5 * hmin_f32()
+    ok = [0.5, 0.5, 0.5, 0.3]
+    bad = [0.5, tiny, 0.5, 0.3]
+    xq = xd[:4].contiguous()
+    yg = torch.linspace(-3, 3, 16, device="cuda").reshape(-1, 1)
+    assert status_of(lambda: m.loo_grad(bad)) == B.CDE_EUNSUPPORTED
+    assert status_of(lambda: m.loo_list([ok, bad])) == B.CDE_EUNSUPPORTED
+    assert status_of(lambda: m.loo_grid([0.5, tiny], [0.3])) == B.CDE_EUNSUPPORTED
+    assert status_of(lambda: m.loo_grid([0.5], [0.3, tiny])) == B.CDE_EUNSUPPORTED
+    assert status_of(lambda: m.query(xq, yg, bad)) == B.CDE_EUNSUPPORTED
+    assert status_of(lambda: m.conditional_mean(xq, bad)) == B.CDE_EUNSUPPORTED
+    assert status_of(lambda: m.cv_ise(bad)) == B.CDE_EUNSUPPORTED
+    assert status_of(lambda: m.loo_list([bad], kernel="epanechnikov")) == B.CDE_EUNSUPPORTED
+    # data-relative: scaling the data by 2^45 makes a moderate bandwidth unsupported
+    m2 = cde().Model((xd * 2.0 ** 45).contiguous(), yd)
+    assert status_of(lambda: m2.loo_grad([1e-2, 1e-2, 1e-2, 0.3])) == B.CDE_EUNSUPPORTED
+    assert status_of(lambda: m2.loo_grad([2.0 ** 45] * 3 + [0.3])) == 0
+    # the accepted setting still runs and matches the oracle
+    _, _, pp = m.loo_grad(ok, per_point=True)
+    P.assert_points(pp.cpu().numpy(), oracle.loo(xo, yo, ok, nthreads=NT))
+
+
+def test_nonfinite_training_data_rejected():
+    print("case: non-finite training data", flush=True)
+    from paper_1206_5278_amd import _binding as B
+    x, y = workloads.gmm(100, seed=42, dx=2)
+    for bad in (float("nan"), float("inf")):
+        xb = np.array(x, dtype=np.float32)
+        xb[37, 1] = bad
+        m = cde().Model(P.to_dev(xb), P.to_dev(y))
+        assert status_of(lambda: m.loo_grad([0.5, 0.5, 0.5])) == B.CDE_EINVAL
+        assert status_of(lambda: m.loo_grid([0.5], [0.5])) == B.CDE_EINVAL
+
+
+def test_edge_of_the_supported_range_matches_oracle():
+    # bandwidths a few times the smallest supported one: every kernel value
+    # but the nearest neighbours' underflows, and the values are ~1e14 in
+    # magnitude; the per-point tolerance is relative to |l*|
+    print("case: edge-of-range bandwidths, n=300 dx=2", flush=True)
+    x, y = workloads.gmm(300, seed=43, dx=2)
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    h0 = 4.0 * hmin_f32()
+    hs = [[h0, h0, 0.3], [0.3, 0.3, h0], [h0, 0.5, h0]]
+    tot, pp = m.loo_list(hs, per_point=True)
+    pp = pp.cpu().numpy()
+    for s, h in enumerate(hs):
+        ref = oracle.loo(xo, yo, h, nthreads=NT)
+        P.assert_points(pp[s], ref)
+    hx = [h0, 0.3]
+    hy = [h0, 0.2]
+    tg, ppg, nonfin = m.loo_grid(hx, hy, per_point=True)
+    assert int(nonfin.item()) == 0
+    P.assert_points(ppg.cpu().numpy(), oracle.loo_grid(xo, yo, hx, hy, nthreads=NT))
+
+
+def test_grid_fixup_beyond_its_queue():
+    # 22,108 of the 38,400 (setting, point) entries have num' < 2^-1000,
+    # more than the 4,096-entry fixup queue holds: the fixup scans every entry
+    print("case: grid fixup overflow n=600 dx=2 8x8 tiny bandwidths", flush=True)
+    x, y = workloads.gmm(600, seed=31, dx=2)
+    hx = workloads.geomspace(1e-3, 0.05, 8)
+    hy = workloads.geomspace(1e-3, 0.02, 8)
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    tot, pp, nonfin = m.loo_grid(hx, hy, per_point=True)
+    ref = oracle.loo_grid(xo, yo, hx, hy, nthreads=NT)
+    assert int(nonfin.item()) == 0
+    P.assert_points(pp.cpu().numpy(), ref)
+    tot = tot.cpu().numpy()
+    for s in range(ref.shape[0]):
+        P.assert_total(float(tot[s]), oracle.total(ref[s]), ref[s])
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_n2_closed_form_and_ascent(dtype):
+    print(f"case: n=2 closed form and ascend, {dtype}", flush=True)
+    x = torch.tensor([[0.25], [1.75]], dtype=dtype, device="cuda")
+    y = torch.tensor([[0.5], [-0.2]], dtype=dtype, device="cuda")
+    dy = abs(float(y[0, 0] - y[1, 0]))
+    m = cde().Model(x, y)
+    for hy in (0.3, 0.7, 2.0):
+        total, grad, _ = m.loo_grad([0.9, hy])
+        s_ref = 2.0 * (-math.log(hy) - 0.5 * math.log(2 * math.pi) - dy * dy / (2 * hy * hy))
+        g_ref = 2.0 * (dy * dy / hy ** 3 - 1.0 / hy)
+        g = grad.cpu().numpy()
+        assert abs(float(total.item()) - s_ref) <= 1e-6 * abs(s_ref)
+        assert abs(g[1] - g_ref) <= 1e-5 * max(abs(g_ref), 1.0)
+        assert abs(g[0]) <= 1e-5 * max(abs(g_ref), 1.0)  # S does not depend on hx
+    st = cde().ascend(m, [0.9, 3.0 * dy], steps=300)
+    assert abs(st["h"][1] / dy - 1.0) < 1e-3, st["h"]
+    assert max(st["trace"]) <= 2.0 * (-math.log(dy) - 0.5 * math.log(2 * math.pi) - 0.5) + 1e-5
