@@ -39,11 +39,22 @@
  *     result paths, so repeated calls give identical bits.
  *   - Bandwidths: every h must be finite and > 0 (else CDE_EINVAL) and inside
  *     the range the kernels' arithmetic represents for the model's data
- *     (else CDE_EUNSUPPORTED, with a message): with range_k = max_i x_ik -
- *     min_i x_ik the extent of dimension k and c_k = log2(e) / (2 h_k^2),
- *     each c_k <= 2^59 and sum_k range_k^2 c_k <= 2^100 over the x dimensions
- *     and over the y dimensions (FP32 models), or 2^900 for both (FP64
- *     models).  cde_check_bandwidths applies the same test on the host.
+ *     (else CDE_EUNSUPPORTED, with a message).  With range_k = max_i x_ik -
+ *     min_i x_ik the extent of dimension k, c_k = log2(e) / (2 h_k^2), and
+ *     X, Y = sum_k range_k^2 c_k over the x and over the y dimensions (the
+ *     largest exponent a pair can have):
+ *       every call:   each c_k <= 2^59, X <= 2^100 and Y <= 2^100 (FP32
+ *                     models; 2^900 for all three on FP64 models);
+ *       calls on the diagonal pass (cde_loo_grad,
+ *       cde_loo_loglik_list with the Gaussian kernel, cde_cv_ise, and the
+ *       Gaussian cde_loo_loglik and cde_density_query of FP64 models), whose
+ *       exponents are formed in the model's precision relative to a
+ *       per-point reference: also (X + Y)(dx + dy + 2) <= 2^29 (FP32 models;
+ *       2^61 on FP64 models).
+ *     These bounds rule out overflow (inf, NaN), not rounding: far below
+ *     them, the diagonal pass's FP32 exponents still carry an absolute error
+ *     of about (dx + dy + 2) u times the nearest neighbour's exponent
+ *     d_nn^2 c.  cde_check_bandwidths applies the same test on the host.
  *     Training data must be finite: a model whose data hold a NaN or an
  *     infinity rejects every call with CDE_EINVAL.  The extent is computed
  *     by cde_create on its stream; the model's first call that checks
@@ -128,15 +139,16 @@ cde_status cde_destroy(cde_model* m);
  * controller budgets HBM with it. */
 size_t cde_model_device_bytes(const cde_model* m);
 
-/* Host-only form of the bandwidth range test of every model call (see
+/* Host-only form of the bandwidth range test of the model calls (see
  * "Bandwidths" above) for one diagonal setting of the Gaussian kernel of
  * Section 2: range [dx+dy] are the data's per-dimension extents (max - min,
- * finite, >= 0), h [dx+dy] the bandwidths (hx_1..hx_dx, hy_1..hy_dy).
+ * finite, >= 0), h [dx+dy] the bandwidths (hx_1..hx_dx, hy_1..hy_dy);
+ * diagonal_pass != 0 adds the diagonal pass's rule.
  * Returns CDE_OK, CDE_EINVAL (NULL pointer, dx or dy < 1, dx + dy > 18,
  * non-finite or negative range, h not finite and > 0) or CDE_EUNSUPPORTED
  * (outside the representable range of `precision`).  No device is used. */
 cde_status cde_check_bandwidths(const double* range, int32_t dx, int32_t dy, const double* h,
-                                cde_precision precision);
+                                cde_precision precision, int32_t diagonal_pass);
 
 /* Device bytes a model of this shape holds after cde_create and one
  * cde_loo_loglik call over an n_hx x n_hy grid (Gaussian kernel, default cross term)
@@ -166,6 +178,38 @@ cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const do
                           cde_xterm xterm,
                           double* totals_dev, double* per_point_dev,
                           int64_t* n_nonfinite_dev, void* stream);
+
+/* One work item of a grouped launch (cde_launch_batch): the points
+ * [i0, i1) of one model, each against all of that model's points. */
+typedef struct cde_work_item {
+    cde_model* model;          /* an FP32 model (cde_create with CDE_F32) */
+    int64_t i0, i1;            /* 0 <= i0 < i1 <= n; i0 a multiple of 256; i1 a multiple of 256 or n */
+    double* totals_dev;        /* [n_hx * n_hy] doubles, hx-major; written by the range with i1 = n
+                                  (required there, ignored otherwise) */
+    int64_t* n_nonfinite_dev;  /* [1] int64 or NULL; written with the totals */
+} cde_work_item;
+
+/* Grouped launch of the exact LOO log-likelihood over a grid of scalar
+ * bandwidths (Section 3, eq. 3, the A_i expansion of Section 3.2; Gaussian
+ * kernel, default cross term) for a work list of point ranges of several
+ * models: every stage of the grid pass runs as one launch over all items
+ * (per 8 items), so many small bandwidth-selection jobs, and the slices of
+ * large ones, share the device in one kernel instead of one launch each.
+ *   items [n_items], 1 <= n_items <= 512: all models FP32, with the same dx
+ *     and dy and on the same device, each model at most once per call.
+ *   hx [n_hx], hy [n_hy]: one grid for all items, 1 <= n_hx, n_hy <= 16.
+ * A model's ranges run over successive calls in order: its first range
+ * starts at 0 and each next one at the previous i1, with the same grid and
+ * criterion, until a range ends at n, which writes the totals (bit-identical
+ * to cde_loo_loglik's for the same grid) and completes the evaluation.
+ * Between its first and last range the model's scratch holds the
+ * evaluation, so every other call on that model returns CDE_EINVAL until
+ * the last range has been issued; calls of one evaluation must be ordered on
+ * the device (one stream, or events).  The first range of a model may
+ * allocate its scratch (as cde_loo_loglik does).  Errors leave every
+ * model's evaluation state unchanged. */
+cde_status cde_launch_batch(const cde_work_item* items, int32_t n_items, const double* hx, int32_t n_hx,
+                            const double* hy, int32_t n_hy, cde_criterion criterion, void* stream);
 
 /* Exact LOO log-likelihood for a list of g diagonal bandwidth settings.
  *   h: host [g][dx+dy] (hx_1..hx_dx, hy_1..hy_dy per setting).

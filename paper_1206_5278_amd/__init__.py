@@ -8,7 +8,7 @@ The computation runs in the HIP library ``libcde.so`` behind the C ABI of
 """
 from ._binding import CdeError, load  # noqa: F401
 from .drivers import LooLogLik, ascend, normal_reference_bandwidths, select_grid  # noqa: F401
-from .model import Model, argmax_first_finite, density_summary  # noqa: F401
+from .model import Model, argmax_first_finite, density_summary, launch_batch  # noqa: F401
 
 __all__ = ["Model", "LooLogLik", "select_grid", "ascend", "normal_reference_bandwidths", "density_summary",
-           "argmax_first_finite", "CdeError", "load"]
+           "argmax_first_finite", "launch_batch", "CdeError", "load"]

@@ -40,8 +40,15 @@ SIGNATURES = {
     "cde_conditional_mean": (ctypes.c_int, [_vp, _vp, _i64, _dp, _vp, _vp]),
     "cde_density_summary": (ctypes.c_int, [_vp, _vp, _i64, _i64, ctypes.c_double, _vp, _vp]),
     "cde_cv_ise": (ctypes.c_int, [_vp, _dp, _vp, _vp, _vp]),
-    "cde_check_bandwidths": (ctypes.c_int, [_dp, _i32, _i32, _dp, ctypes.c_int]),
+    "cde_check_bandwidths": (ctypes.c_int, [_dp, _i32, _i32, _dp, ctypes.c_int, _i32]),
+    "cde_launch_batch": (ctypes.c_int, [_vp, _i32, _dp, _i32, _dp, _i32, ctypes.c_int, _vp]),
 }
+
+
+class WorkItem(ctypes.Structure):
+    """cde_work_item of include/cde.h: points [i0, i1) of one model."""
+    _fields_ = [("model", ctypes.c_void_p), ("i0", ctypes.c_int64), ("i1", ctypes.c_int64),
+                ("totals_dev", ctypes.c_void_p), ("n_nonfinite_dev", ctypes.c_void_p)]
 
 
 class CdeError(RuntimeError):

@@ -54,16 +54,23 @@ bool valid_bandwidths(const double* h, int k)
 }
 
 // Representable range of a Gaussian setting for a model of precision p, over
-// data whose per-dimension extents (max - min) are `range`:
-//   - every exponent coefficient c_k = log2(e) / (2 h_k^2) is at most CMAX,
-//     so that it, and the excluded-pair sentinel 1e20 times it, stay finite in
-//     the kernels' arithmetic (FP32 for FP32 models);
-//   - the largest possible exponent, sum_k range_k^2 c_k over the x
-//     dimensions and over the y dimensions, is at most SMAX, so that no
-//     pair's exponent overflows.
-// Outside it the kernels would produce inf - inf or 0 * inf.
-constexpr double CMAX_F32 = 0x1p59, SMAX_F32 = 0x1p100;
-constexpr double CMAX_F64 = 0x1p900, SMAX_F64 = 0x1p900;
+// data whose per-dimension extents (max - min) are `range`.  With c_k =
+// log2(e) / (2 h_k^2), X = sum_{k < dx} range_k^2 c_k and Y the same over the
+// y dimensions (the largest exponents any pair can have):
+//   - every pass: each c_k <= CMAX (c_k, and the excluded-pair sentinel 1e20
+//     times it, stay finite in FP32 for FP32 models), X <= SMAX and
+//     Y <= SMAX (no pair's exponent overflows);
+//   - the diagonal pass (per-dimension bandwidths: values, gradients, the
+//     LOO part of the ISE, and every grid of an FP64 model) forms exponents
+//     in the model's precision relative to a per-point reference, so its
+//     absolute rounding error grows with the exponents' size, about
+//     (dx + dy + 2) (X + Y) u; (X + Y)(dx + dy + 2) <= DMAX keeps that far
+//     below the 2^64 (FP64: 2^640) headroom of its sums, so no sum
+//     overflows.  (The grid and query passes form shifted exponents in FP64
+//     and need only the first rule.)
+// Outside these ranges the kernels would produce inf - inf or 0 * inf.
+constexpr double CMAX_F32 = 0x1p59, SMAX_F32 = 0x1p100, DMAX_F32 = 0x1p29;
+constexpr double CMAX_F64 = 0x1p900, SMAX_F64 = 0x1p900, DMAX_F64 = 0x1p61;
 
 // Largest exponent of one group of dimensions; h_step = 0 broadcasts h[0].
 double group_exponent(const double* range, int cnt, const double* h, int h_step, double* cmax)
@@ -80,10 +87,11 @@ double group_exponent(const double* range, int cnt, const double* h, int h_step,
 }
 
 cde_status check_group(const double* range, int cnt, const double* h, int h_step, cde_precision p,
-                       const char* who, const char* axis)
+                       const char* who, const char* axis, double* exponent)
 {
     double cm = 0.0;
     const double e = group_exponent(range, cnt, h, h_step, &cm);
+    if (exponent) *exponent = e;
     const double cmax = p == CDE_F64 ? CMAX_F64 : CMAX_F32, smax = p == CDE_F64 ? SMAX_F64 : SMAX_F32;
     if (cm <= cmax && e <= smax) return CDE_OK;
     char msg[320];
@@ -96,13 +104,32 @@ cde_status check_group(const double* range, int cnt, const double* h, int h_step
     return fail(CDE_EUNSUPPORTED, msg);
 }
 
-// One diagonal setting h [dx + dy] against the extents `range` [dx + dy].
-cde_status check_setting(const double* range, int dx, int dy, const double* h, cde_precision p,
-                         const char* who)
+// The diagonal pass's extra rule on the exponents X and Y of one setting.
+cde_status check_diag_pass(double ex, double ey, int dx, int dy, cde_precision p, const char* who)
 {
-    cde_status st = check_group(range, dx, h, 1, p, who, "x");
+    const double lim = p == CDE_F64 ? DMAX_F64 : DMAX_F32;
+    const double v = (ex + ey) * (dx + dy + 2);
+    if (v <= lim) return CDE_OK;
+    char msg[320];
+    std::snprintf(msg, sizeof msg,
+                  "%s: bandwidths too small for the diagonal pass's %s exponents on this data "
+                  "(needs (X + Y)(dx + dy + 2) <= 2^%d with X, Y = sum_k range_k^2 log2(e)/(2h_k^2) "
+                  "over the x and the y dimensions; got %.3g)",
+                  who, p == CDE_F64 ? "FP64" : "FP32", p == CDE_F64 ? 61 : 29, v);
+    return fail(CDE_EUNSUPPORTED, msg);
+}
+
+// One diagonal setting h [dx + dy] against the extents `range` [dx + dy];
+// `diag`: the setting runs on the diagonal pass.
+cde_status check_setting(const double* range, int dx, int dy, const double* h, cde_precision p,
+                         bool diag, const char* who)
+{
+    double ex = 0.0, ey = 0.0;
+    cde_status st = check_group(range, dx, h, 1, p, who, "x", &ex);
     if (st != CDE_OK) return st;
-    return check_group(range + dx, dy, h + dx, 1, p, who, "y");
+    st = check_group(range + dx, dy, h + dx, 1, p, who, "y", &ey);
+    if (st != CDE_OK || !diag) return st;
+    return check_diag_pass(ex, ey, dx, dy, p, who);
 }
 
 unsigned long long decode_ordered(unsigned long long u)
@@ -135,8 +162,9 @@ cde_status ensure_extent(cde_model* m, const char* who)
 }
 
 // Bandwidth checks of the model calls: finite and > 0 (CDE_EINVAL), then
-// within the representable range for the model's data (CDE_EUNSUPPORTED).
-cde_status check_model_settings(cde_model* m, const double* h, int g, const char* who)
+// within the representable range for the model's data and the pass that
+// runs the call (CDE_EUNSUPPORTED).
+cde_status check_model_settings(cde_model* m, const double* h, int g, bool diag, const char* who)
 {
     const int p = m->dx + m->dy;
     if (!valid_bandwidths(h, g * p))
@@ -144,25 +172,30 @@ cde_status check_model_settings(cde_model* m, const double* h, int g, const char
     cde_status st = ensure_extent(m, who);
     if (st != CDE_OK) return st;
     for (int s = 0; s < g; ++s) {
-        st = check_setting(m->range, m->dx, m->dy, h + (size_t)s * p, m->prec, who);
+        st = check_setting(m->range, m->dx, m->dy, h + (size_t)s * p, m->prec, diag, who);
         if (st != CDE_OK) return st;
     }
     return CDE_OK;
 }
 
 cde_status check_model_grid(cde_model* m, const double* hx, int n_hx, const double* hy, int n_hy,
-                            const char* who)
+                            bool diag, const char* who)
 {
     if (!valid_bandwidths(hx, n_hx) || !valid_bandwidths(hy, n_hy))
         return fail(CDE_EINVAL, std::string(who) + ": bandwidths must be finite and > 0");
     cde_status st = ensure_extent(m, who);
     if (st != CDE_OK) return st;
-    for (int a = 0; a < n_hx; ++a)
-        if ((st = check_group(m->range, m->dx, hx + a, 0, m->prec, who, "x")) != CDE_OK) return st;
-    for (int b = 0; b < n_hy; ++b)
-        if ((st = check_group(m->range + m->dx, m->dy, hy + b, 0, m->prec, who, "y")) != CDE_OK)
+    double exmax = 0.0, eymax = 0.0, e = 0.0;
+    for (int a = 0; a < n_hx; ++a) {
+        if ((st = check_group(m->range, m->dx, hx + a, 0, m->prec, who, "x", &e)) != CDE_OK) return st;
+        exmax = std::max(exmax, e);
+    }
+    for (int b = 0; b < n_hy; ++b) {
+        if ((st = check_group(m->range + m->dx, m->dy, hy + b, 0, m->prec, who, "y", &e)) != CDE_OK)
             return st;
-    return CDE_OK;
+        eymax = std::max(eymax, e);
+    }
+    return diag ? check_diag_pass(exmax, eymax, m->dx, m->dy, m->prec, who) : CDE_OK;
 }
 
 // Device bytes of a model's packed rows plus the extent record in their tail.
@@ -226,6 +259,33 @@ cde_status ensure_scratch(cde_model* m, size_t bytes)
     m->scratch_bytes = bytes;
     m->bytes += bytes;
     return CDE_OK;
+}
+
+// A grouped grid evaluation keeps its state in the model's scratch between
+// cde_launch_batch calls; no other call may use the scratch meanwhile.
+cde_status reject_if_batching(const cde_model* m, const char* who)
+{
+    if (m->batch_next == 0) return CDE_OK;
+    return fail(CDE_EINVAL, std::string(who) +
+                                ": the model is in the middle of a grouped grid evaluation "
+                                "(cde_launch_batch ranges up to its last point are still to come)");
+}
+
+// FNV-1a signature of a grid and criterion (detects a change between the
+// ranges of one grouped evaluation).
+uint64_t grid_signature(const double* hx, int n_hx, const double* hy, int n_hy, int crit)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t bytes) {
+        const unsigned char* c = (const unsigned char*)p;
+        for (size_t k = 0; k < bytes; ++k) h = (h ^ c[k]) * 1099511628211ull;
+    };
+    mix(&n_hx, sizeof n_hx);
+    mix(hx, sizeof(double) * n_hx);
+    mix(&n_hy, sizeof n_hy);
+    mix(hy, sizeof(double) * n_hy);
+    mix(&crit, sizeof crit);
+    return h;
 }
 
 // Value (and gradient) for a list of diagonal settings, reduced into
@@ -485,7 +545,7 @@ size_t cde_workspace_bytes(int64_t n, int32_t dx, int32_t dy, cde_precision prec
 }
 
 cde_status cde_check_bandwidths(const double* range, int32_t dx, int32_t dy, const double* h,
-                                cde_precision precision)
+                                cde_precision precision, int32_t diagonal_pass)
 {
     try {
         if (!range || !h) return fail(CDE_EINVAL, "cde_check_bandwidths: NULL pointer");
@@ -498,7 +558,7 @@ cde_status cde_check_bandwidths(const double* range, int32_t dx, int32_t dy, con
                 return fail(CDE_EINVAL, "cde_check_bandwidths: ranges must be finite and >= 0");
         if (!valid_bandwidths(h, dx + dy))
             return fail(CDE_EINVAL, "cde_check_bandwidths: bandwidths must be finite and > 0");
-        return check_setting(range, dx, dy, h, precision, "cde_check_bandwidths");
+        return check_setting(range, dx, dy, h, precision, diagonal_pass != 0, "cde_check_bandwidths");
     } catch (...) {
         return fail(CDE_EDEVICE, "cde_check_bandwidths: unexpected exception");
     }
@@ -510,13 +570,14 @@ cde_status cde_loo_loglik_list(cde_model* m, const double* h, int32_t g, cde_cri
 {
     try {
         if (!m) return fail(CDE_EINVAL, "cde_loo_loglik_list: model is NULL");
+        if (cde_status st0 = reject_if_batching(m, "cde_loo_loglik_list"); st0 != CDE_OK) return st0;
         if (!totals_dev) return fail(CDE_EINVAL, "cde_loo_loglik_list: totals_dev is NULL");
         if (g < 1 || g > 4096) return fail(CDE_EINVAL, "cde_loo_loglik_list: g must be in [1, 4096]");
         if (criterion != CDE_COND && criterion != CDE_JOINT)
             return fail(CDE_EINVAL, "cde_loo_loglik_list: unknown criterion");
         if (kernel != CDE_GAUSSIAN && kernel != CDE_EPANECHNIKOV)
             return fail(CDE_EINVAL, "cde_loo_loglik_list: unknown kernel");
-        cde_status st = check_model_settings(m, h, g, "cde_loo_loglik_list");
+        cde_status st = check_model_settings(m, h, g, kernel == CDE_GAUSSIAN, "cde_loo_loglik_list");
         if (st != CDE_OK) return st;
         DeviceGuard guard(m->device);
         hipStream_t s = (hipStream_t)stream;
@@ -539,6 +600,7 @@ cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const do
 {
     try {
         if (!m) return fail(CDE_EINVAL, "cde_loo_loglik: model is NULL");
+        if (cde_status st0 = reject_if_batching(m, "cde_loo_loglik"); st0 != CDE_OK) return st0;
         if (!totals_dev) return fail(CDE_EINVAL, "cde_loo_loglik: totals_dev is NULL");
         if (n_hx < 1 || n_hx > 64 || n_hy < 1 || n_hy > 64)
             return fail(CDE_EINVAL, "cde_loo_loglik: grid sizes must be in [1, 64]");
@@ -553,7 +615,8 @@ cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const do
             return fail(CDE_EUNSUPPORTED,
                         "cde_loo_loglik: the MFMA cross term needs dx >= 16, FP32 data and the Gaussian kernel");
         {
-            cde_status st = check_model_grid(m, hx, n_hx, hy, n_hy, "cde_loo_loglik");
+            cde_status st = check_model_grid(m, hx, n_hx, hy, n_hy, m->prec == CDE_F64 && kernel == CDE_GAUSSIAN,
+                                             "cde_loo_loglik");
             if (st != CDE_OK) return st;
         }
         DeviceGuard guard(m->device);
@@ -613,11 +676,12 @@ cde_status cde_loo_grad(cde_model* m, const double* h, cde_criterion criterion, 
 {
     try {
         if (!m) return fail(CDE_EINVAL, "cde_loo_grad: model is NULL");
+        if (cde_status st0 = reject_if_batching(m, "cde_loo_grad"); st0 != CDE_OK) return st0;
         if (!total_dev || !grad_dev) return fail(CDE_EINVAL, "cde_loo_grad: output pointer is NULL");
         if (criterion != CDE_COND && criterion != CDE_JOINT)
             return fail(CDE_EINVAL, "cde_loo_grad: unknown criterion");
         {
-            cde_status st = check_model_settings(m, h, 1, "cde_loo_grad");
+            cde_status st = check_model_settings(m, h, 1, true, "cde_loo_grad");
             if (st != CDE_OK) return st;
         }
         DeviceGuard guard(m->device);
@@ -632,14 +696,104 @@ cde_status cde_loo_grad(cde_model* m, const double* h, cde_criterion criterion, 
     }
 }
 
+cde_status cde_launch_batch(const cde_work_item* items, int32_t n_items, const double* hx, int32_t n_hx,
+                            const double* hy, int32_t n_hy, cde_criterion criterion, void* stream)
+{
+    try {
+        if (!items || n_items < 1 || n_items > 512)
+            return fail(CDE_EINVAL, "cde_launch_batch: need 1 <= n_items <= 512 and items != NULL");
+        if (!hx || !hy) return fail(CDE_EINVAL, "cde_launch_batch: hx or hy is NULL");
+        if (n_hx < 1 || n_hx > 16 || n_hy < 1 || n_hy > 16)
+            return fail(CDE_EINVAL, "cde_launch_batch: grid sizes must be in [1, 16]");
+        if (criterion != CDE_COND && criterion != CDE_JOINT)
+            return fail(CDE_EINVAL, "cde_launch_batch: unknown criterion");
+        const cde_model* m0 = items[0].model;
+        if (!m0) return fail(CDE_EINVAL, "cde_launch_batch: item 0 has no model");
+        const uint64_t sig = grid_signature(hx, n_hx, hy, n_hy, criterion);
+        std::vector<GridRange> ranges((size_t)n_items);
+        for (int k = 0; k < n_items; ++k) {
+            const cde_work_item& it = items[k];
+            cde_model* m = it.model;
+            char who[64];
+            std::snprintf(who, sizeof who, "cde_launch_batch: item %d", k);
+            if (!m) return fail(CDE_EINVAL, std::string(who) + " has no model");
+            if (m->prec != CDE_F32) return fail(CDE_EUNSUPPORTED, std::string(who) + ": FP32 models only");
+            if (m->dx != m0->dx || m->dy != m0->dy || m->device != m0->device)
+                return fail(CDE_EINVAL, std::string(who) + ": items must share dx, dy and the device");
+            for (int q = 0; q < k; ++q)
+                if (items[q].model == m) return fail(CDE_EINVAL, std::string(who) + ": model listed twice");
+            if (!(it.i0 >= 0 && it.i0 < it.i1 && it.i1 <= m->n) || it.i0 % TILE != 0 ||
+                (it.i1 != m->n && it.i1 % TILE != 0))
+                return fail(CDE_EINVAL, std::string(who) +
+                                            ": need 0 <= i0 < i1 <= n, i0 a multiple of 256 and i1 one "
+                                            "or n");
+            if (it.i1 == m->n && !it.totals_dev)
+                return fail(CDE_EINVAL, std::string(who) + ": the range ending at n needs totals_dev");
+            if (it.i0 != m->batch_next)
+                return fail(CDE_EINVAL, std::string(who) + ": ranges of a model must follow each other "
+                                                           "from 0 (expected i0 = " +
+                                            std::to_string((long long)m->batch_next) + ")");
+            if (it.i0 > 0 && sig != m->batch_sig)
+                return fail(CDE_EINVAL, std::string(who) + ": grid or criterion changed within an evaluation");
+            cde_status st = check_model_grid(m, hx, n_hx, hy, n_hy, false, who);
+            if (st != CDE_OK) return st;
+        }
+        DeviceGuard guard(m0->device);
+        if (!guard.ok) return fail(CDE_EDEVICE, "cde_launch_batch: cannot make the models' device current");
+        for (int k = 0; k < n_items; ++k) {
+            cde_model* m = items[k].model;
+            const size_t wb = grid_work_bytes(m, n_hx, n_hy);
+            const size_t need = grid_call_scratch(m, n_hx, n_hy);
+            if (items[k].i0 == 0) {
+                if (!m->nn) {
+                    hipError_t e = hipMalloc(&m->nn, sizeof(double) * 2 * (size_t)m->npad);
+                    if (e != hipSuccess) {
+                        m->nn = nullptr;
+                        return hip_fail(e, "hipMalloc(neighbour shifts)");
+                    }
+                    m->bytes += sizeof(double) * 2 * (size_t)m->npad;
+                }
+                cde_status st = ensure_scratch(m, need);
+                if (st != CDE_OK) return st;
+            } else if (m->scratch_bytes < need) {
+                return fail(CDE_EINVAL, "cde_launch_batch: model scratch shrank within an evaluation");
+            }
+            GridRange& r = ranges[k];
+            r.m = m;
+            r.i0 = items[k].i0;
+            r.i1 = items[k].i1;
+            r.totals = items[k].totals_dev;
+            r.nonfinite = items[k].n_nonfinite_dev;
+            r.work = m->scratch;
+            r.work_bytes = wb;
+            r.counts = (double*)((char*)m->scratch + wb);
+            r.do_nn = !m->nn_ready;
+        }
+        hipError_t e = launch_grid_batch(ranges.data(), n_items, hx, n_hx, hy, n_hy, criterion,
+                                         (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "launch grouped grid kernels");
+        for (int k = 0; k < n_items; ++k) {
+            cde_model* m = items[k].model;
+            const bool last = items[k].i1 == m->n;
+            m->batch_next = last ? 0 : items[k].i1;
+            m->batch_sig = sig;
+            if (last) m->nn_ready = true;
+        }
+        return CDE_OK;
+    } catch (...) {
+        return fail(CDE_EDEVICE, "cde_launch_batch: unexpected exception");
+    }
+}
+
 cde_status cde_cv_ise(cde_model* m, const double* h, double* out_dev, double* terms_dev, void* stream)
 {
     try {
         if (!m) return fail(CDE_EINVAL, "cde_cv_ise: model is NULL");
+        if (cde_status st0 = reject_if_batching(m, "cde_cv_ise"); st0 != CDE_OK) return st0;
         if (!out_dev) return fail(CDE_EINVAL, "cde_cv_ise: output pointer is NULL");
         if (m->prec != CDE_F32) return fail(CDE_EUNSUPPORTED, "cde_cv_ise: FP32 models only");
         {
-            cde_status st = check_model_settings(m, h, 1, "cde_cv_ise");
+            cde_status st = check_model_settings(m, h, 1, true, "cde_cv_ise");
             if (st != CDE_OK) return st;
         }
         if (m->n > CDE_ISE_MAX_N) return fail(CDE_EUNSUPPORTED, "cde_cv_ise: n > 262144");
@@ -672,13 +826,15 @@ cde_status cde_density_query(cde_model* m, const void* xq_dev, int64_t q, const 
 {
     try {
         if (!m) return fail(CDE_EINVAL, "cde_density_query: model is NULL");
+        if (cde_status st0 = reject_if_batching(m, "cde_density_query"); st0 != CDE_OK) return st0;
         if (kernel != CDE_GAUSSIAN && kernel != CDE_EPANECHNIKOV)
             return fail(CDE_EINVAL, "cde_density_query: unknown kernel");
         if (q < 0 || k < 0 || k > 4096) return fail(CDE_EINVAL, "cde_density_query: need q >= 0, 0 <= k <= 4096");
         if (q > 0 && k > 0 && (!xq_dev || !ygrid_dev || !f_dev))
             return fail(CDE_EINVAL, "cde_density_query: NULL device pointer");
         {
-            cde_status st = check_model_settings(m, h, 1, "cde_density_query");
+            cde_status st = check_model_settings(m, h, 1, m->prec == CDE_F64 && kernel == CDE_GAUSSIAN,
+                                                 "cde_density_query");
             if (st != CDE_OK) return st;
         }
         if (q == 0 || k == 0) return CDE_OK;
@@ -722,10 +878,11 @@ cde_status cde_conditional_mean(cde_model* m, const void* xq_dev, int64_t q, con
 {
     try {
         if (!m) return fail(CDE_EINVAL, "cde_conditional_mean: model is NULL");
+        if (cde_status st0 = reject_if_batching(m, "cde_conditional_mean"); st0 != CDE_OK) return st0;
         if (q < 0) return fail(CDE_EINVAL, "cde_conditional_mean: q must be >= 0");
         if (q > 0 && (!xq_dev || !mean_dev)) return fail(CDE_EINVAL, "cde_conditional_mean: NULL device pointer");
         {
-            cde_status st = check_model_settings(m, h, 1, "cde_conditional_mean");
+            cde_status st = check_model_settings(m, h, 1, false, "cde_conditional_mean");
             if (st != CDE_OK) return st;
         }
         if (q == 0) return CDE_OK;

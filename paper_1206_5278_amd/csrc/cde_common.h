@@ -90,4 +90,9 @@ struct cde_model {
     bool ext_known = false;
     bool data_finite = true;
     double range[cde::MAXP] = {};            // max - min per dimension
+    // Grouped grid evaluation (cde_launch_batch) in progress: the next point
+    // range must start at batch_next (0: none in progress), for the grid and
+    // criterion whose signature is batch_sig.
+    int64_t batch_next = 0;
+    uint64_t batch_sig = 0;
 };

@@ -96,6 +96,26 @@ hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* h
                        double* counts, hipStream_t stream);
 size_t grid_work_bytes(const cde_model* m, int n_hx, int n_hy);
 
+// One work item of the grouped grid launch: points [i0, i1) of model m (FP32,
+// grid work area `work` of work_bytes >= grid_work_bytes, non-finite counts
+// in `counts`), against all of its points; the range ending at i1 = n also
+// writes totals [G] and, if non-NULL, *nonfinite.  do_nn: compute the
+// range's neighbour shifts first (the model has none yet).
+struct GridRange {
+    cde_model* m;
+    int64_t i0, i1;
+    double* totals;
+    int64_t* nonfinite;
+    void* work;
+    size_t work_bytes;
+    double* counts;
+    bool do_nn;
+};
+// The grid pipeline over a work list of ranges of models sharing dx and dy,
+// for a grid of at most 16 x 16 cells: one launch per stage per 8 items.
+hipError_t launch_grid_batch(const GridRange* r, int count, const double* hx, int n_hx, const double* hy,
+                             int n_hy, int crit, hipStream_t stream);
+
 // Fixed-order FP64 sum of the per-block partial rows of `nsets` settings:
 // part [nsets][nblocks][nv] -> totals [nsets] (column 0), grad [nsets][nv-2]
 // (columns 1..nv-2, if grad != NULL); if nonfinite != NULL, the per-setting

@@ -150,13 +150,13 @@ __device__ __forceinline__ void own_f64(double (&dst)[S], const float* src)
 // and branch cost more than the FP64 formula it saves.)
 
 template <int DX, int DY>
-__global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int n,
-                                             double* __restrict__ nn, int npad)
+__device__ __forceinline__ void nn_body(int bx, const float* __restrict__ pts, int n,
+                                        double* __restrict__ nn, int npad)
 {
     constexpr int S = row_stride(DX, DY);
     __shared__ float tile[TILE * S];
     const int tid = threadIdx.x;
-    const int i = blockIdx.x * TILE + tid;
+    const int i = bx * TILE + tid;
     float own32[S];
     load_row<S>(own32, pts + (size_t)i * S);
     double own[S];
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int 
         store_row<S>(tile + tid * S, pre);
         __syncthreads();
         const int cnt = min(TILE, n - t * TILE);
-        const int self = (t == (int)blockIdx.x) ? tid : -1;
+        const int self = (t == (int)bx) ? tid : -1;
         if constexpr (DX + DY < 10) {
             for (int q = 0; q < cnt; ++q) {
                 float pj[S];
@@ -212,6 +212,13 @@ __global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int 
     }
     nn[i] = mx;
     nn[npad + i] = my;
+}
+
+template <int DX, int DY>
+__global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int n,
+                                             double* __restrict__ nn, int npad)
+{
+    nn_body<DX, DY>(blockIdx.x, pts, n, nn, npad);
 }
 
 // Grid coefficients (base 2), padded to a multiple of 16 with copies of the
@@ -254,13 +261,13 @@ __device__ __forceinline__ void split4(const float* x, const float* mean, v4s& h
 // With a point list (the rerun of flagged points), fewer points per wave
 // spread a short list over more blocks; the work per pair is the same.
 template <int DX, int DY, bool XT, int PWF>
-__global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts,
-                                                   const double* __restrict__ nn, int n, int npad,
-                                                   GridArgs ga, const float* __restrict__ xmean,
-                                                   double* __restrict__ numbuf,
-                                                   double* __restrict__ denbuf,
-                                                   const int* __restrict__ plist,
-                                                   const int* __restrict__ pcount)
+__device__ __forceinline__ void grid64_body(int bx, int by, const float* __restrict__ pts,
+                                            const double* __restrict__ nn, int n, int npad,
+                                            const GridArgs& ga, const float* __restrict__ xmean,
+                                            double* __restrict__ numbuf,
+                                            double* __restrict__ denbuf,
+                                            const int* __restrict__ plist,
+                                            const int* __restrict__ pcount)
 {
     constexpr int S = row_stride(DX, DY);
     static_assert(!XT || DX == 16, "the MFMA cross term is built for dx = 16");
@@ -275,13 +282,13 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
     const int lane = tid & 63;
     const int wave = tid >> 6;
     // this wave's PWF points: i0 .. i0+PWF-1, or those list entries of plist
-    const int i0 = blockIdx.x * (4 * PWF) + wave * PWF;
+    const int i0 = bx * (4 * PWF) + wave * PWF;
     int cnt_list = 0;
     if (plist) {
-        // the list of this grid tile (blockIdx.y)
-        plist += (size_t)blockIdx.y * npad;
-        cnt_list = pcount[blockIdx.y];
-        if ((int)blockIdx.x * (4 * PWF) >= cnt_list) return;  // whole block past the list (uniform)
+        // the list of this grid tile (by)
+        plist += (size_t)by * npad;
+        cnt_list = pcount[by];
+        if ((int)bx * (4 * PWF) >= cnt_list) return;  // whole block past the list (uniform)
     }
     auto point = [&](int q) -> int {
         if (!plist) return i0 + q;
@@ -289,7 +296,7 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
     };
     auto point_valid = [&](int q) -> bool { return !plist || i0 + q < cnt_list; };
     const int tb = ga.gyp / 16;                 // b-tiles per row of tiles
-    const int ab = blockIdx.y / tb, bb = blockIdx.y % tb;
+    const int ab = by / tb, bb = by % tb;
     const bool do_den = (bb == 0);
 
     // distance role: point i0 + (lane%16)%PWF against tile row group*JG + jo
@@ -430,6 +437,19 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
     }
 }
 
+template <int DX, int DY, bool XT, int PWF>
+__global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts,
+                                                   const double* __restrict__ nn, int n, int npad,
+                                                   GridArgs ga, const float* __restrict__ xmean,
+                                                   double* __restrict__ numbuf,
+                                                   double* __restrict__ denbuf,
+                                                   const int* __restrict__ plist,
+                                                   const int* __restrict__ pcount)
+{
+    grid64_body<DX, DY, XT, PWF>(blockIdx.x, blockIdx.y, pts, nn, n, npad, ga, xmean, numbuf, denbuf,
+                                 plist, pcount);
+}
+
 // FP32 fast pass: the same decomposition with FP32 kernel values (plain
 // v_exp_f32), v_mfma_f32_16x16x4f32 products and sums, partial sums over a
 // 256-point j-tile folded into Kahan-compensated FP32 totals.  FP32 cannot
@@ -456,19 +476,19 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
 constexpr float GRID_BIAS = 32.f;
 
 template <int DX, int DY, int PW, bool BIAS>
-__global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ pts,
-                                                     const double* __restrict__ nn, int n, int npad,
-                                                     GridArgs ga, double* __restrict__ numbuf,
-                                                     double* __restrict__ denbuf)
+__device__ __forceinline__ void grid32_body(int bx, int by, const float* __restrict__ pts,
+                                            const double* __restrict__ nn, int n, int npad,
+                                            const GridArgs& ga, double* __restrict__ numbuf,
+                                            double* __restrict__ denbuf)
 {
     static_assert(PW == 4 || PW == 8, "4 or 8 points per wave");
     constexpr int S = row_stride(DX, DY);
     constexpr int JG = 64 / PW;  // tile rows per distance group
     __shared__ double tile[TILE * S];  // staged as doubles: one exact conversion per row
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int i0 = blockIdx.x * (4 * PW) + wave * PW;
+    const int i0 = bx * (4 * PW) + wave * PW;
     const int tb = ga.gyp / 16;
-    const int tile_id = ga.tile_of[blockIdx.y];
+    const int tile_id = ga.tile_of[by];
     const int ab = tile_id / tb, bb = tile_id % tb;
     const bool do_den = (bb == 0);
     // distance role: lane = 16 r + PW s + q forms point i0 + q against row
@@ -570,6 +590,15 @@ __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ p
             if (lane < 16 && a < ga.gx) denbuf[(size_t)a * npad + i0 + q] = v * (BIAS ? 0x1p-32 : 1.0);
         }
     }
+}
+
+template <int DX, int DY, int PW, bool BIAS>
+__global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ pts,
+                                                     const double* __restrict__ nn, int n, int npad,
+                                                     GridArgs ga, double* __restrict__ numbuf,
+                                                     double* __restrict__ denbuf)
+{
+    grid32_body<DX, DY, PW, BIAS>(blockIdx.x, blockIdx.y, pts, nn, n, npad, ga, numbuf, denbuf);
 }
 
 // The FP32 pass for grids of at least 32 x 32 cells (both padded sides
@@ -722,14 +751,14 @@ struct GridFin {
 // cell below the tile's threshold (2^-130 biased, 2^-80 otherwise), in
 // flag_points[tile][npad]; otherwise queue entries below 2^-1000 for the
 // per-entry fixup.
-__global__ void k_grid_finalize(const double* __restrict__ numbuf, const double* __restrict__ denbuf,
-                                const double* __restrict__ nn, int n, int npad, GridFin gf, int crit,
-                                double* __restrict__ ell, int* __restrict__ fix_count,
-                                int2* __restrict__ fix_list, int fix_cap,
-                                int* __restrict__ flag_points)
+template <class Fin>
+__device__ __forceinline__ void finalize_body(int i, int g, const double* __restrict__ numbuf,
+                                              const double* __restrict__ denbuf,
+                                              const double* __restrict__ nn, int n, int npad,
+                                              const Fin& gf, int crit, double* __restrict__ ell,
+                                              int* __restrict__ fix_count, int2* __restrict__ fix_list,
+                                              int fix_cap, int* __restrict__ flag_points)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int g = blockIdx.y;
     if (i >= n) return;
     const int a = g / gf.gy, b = g - a * gf.gy;
     const double num = numbuf[(size_t)g * npad + i];
@@ -752,14 +781,28 @@ __global__ void k_grid_finalize(const double* __restrict__ numbuf, const double*
     }
 }
 
+__global__ void k_grid_finalize(const double* __restrict__ numbuf, const double* __restrict__ denbuf,
+                                const double* __restrict__ nn, int n, int npad, GridFin gf, int crit,
+                                double* __restrict__ ell, int* __restrict__ fix_count,
+                                int2* __restrict__ fix_list, int fix_cap,
+                                int* __restrict__ flag_points)
+{
+    finalize_body(blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y, numbuf, denbuf, nn, n, npad, gf,
+                  crit, ell, fix_count, fix_list, fix_cap, flag_points);
+}
+
 // List of flagged points (order of the list does not affect any result).
+__device__ __forceinline__ void compact_body(int i, int t, const int* __restrict__ flag, int n, int npad,
+                                             int* __restrict__ count, int* __restrict__ list)
+{
+    // one list per grid tile t: flag[tile][npad] -> list[tile][npad]
+    if (i < n && flag[(size_t)t * npad + i]) list[(size_t)t * npad + atomicAdd(count + t, 1)] = i;
+}
+
 __global__ void k_compact_points(const int* __restrict__ flag, int n, int npad, int* __restrict__ count,
                                  int* __restrict__ list)
 {
-    // one list per grid tile (blockIdx.y): flag[tile][npad] -> list[tile][npad]
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t t = blockIdx.y;
-    if (i < n && flag[t * npad + i]) list[t * npad + atomicAdd(count + t, 1)] = i;
+    compact_body(blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y, flag, n, npad, count, list);
 }
 
 // Exact recomputation of queued (setting, point) entries: one wave per entry,
@@ -768,28 +811,27 @@ __global__ void k_compact_points(const int* __restrict__ flag, int n, int npad, 
 // flagged than the queue holds (fix_count > fix_cap), the waves instead scan
 // every (setting, point) entry of numbuf and recompute each one below the
 // same 2^-1000 threshold, so no flagged entry is ever left unfixed.
-template <int DX, int DY>
-__global__ __launch_bounds__(TILE) void k_grid_fixup(const float* __restrict__ pts,
-                                                     const double* __restrict__ nn, int n, int npad,
-                                                     GridArgs ga, GridFin gf, int crit,
-                                                     const double* __restrict__ numbuf,
-                                                     const double* __restrict__ denbuf,
-                                                     double* __restrict__ ell,
-                                                     const int* __restrict__ fix_count,
-                                                     const int2* __restrict__ fix_list, int fix_cap)
+template <int DX, int DY, class Fin>
+__device__ __forceinline__ void fixup_body(int wid, int nw, int p0, int p1, const float* __restrict__ pts,
+                                           const double* __restrict__ nn, int n, int npad,
+                                           const GridArgs& ga, const Fin& gf, int crit,
+                                           const double* __restrict__ numbuf,
+                                           const double* __restrict__ denbuf,
+                                           double* __restrict__ ell,
+                                           const int* __restrict__ fix_count,
+                                           const int2* __restrict__ fix_list, int fix_cap)
 {
     constexpr int S = row_stride(DX, DY);
     const int lane = threadIdx.x & 63;
-    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nw = (gridDim.x * blockDim.x) >> 6;
     const int queued = *fix_count;
     const bool scan = queued > fix_cap;
-    const int64_t count = scan ? (int64_t)ga.gx * ga.gy * n : queued;
+    const int span = p1 - p0;  // the scan covers points [p0, p1)
+    const int64_t count = scan ? (int64_t)ga.gx * ga.gy * span : queued;
     for (int64_t e = wid; e < count; e += nw) {
         int g, i;
         if (scan) {
-            g = (int)(e / n);
-            i = (int)(e - (int64_t)g * n);
+            g = (int)(e / span);
+            i = p0 + (int)(e - (int64_t)g * span);
             if (numbuf[(size_t)g * npad + i] >= 0x1p-1000) continue;  // wave-uniform
         } else {
             const int2 gi = fix_list[e];
@@ -842,15 +884,27 @@ __global__ __launch_bounds__(TILE) void k_grid_fixup(const float* __restrict__ p
     }
 }
 
+template <int DX, int DY>
+__global__ __launch_bounds__(TILE) void k_grid_fixup(const float* __restrict__ pts,
+                                                     const double* __restrict__ nn, int n, int npad,
+                                                     GridArgs ga, GridFin gf, int crit,
+                                                     const double* __restrict__ numbuf,
+                                                     const double* __restrict__ denbuf,
+                                                     double* __restrict__ ell,
+                                                     const int* __restrict__ fix_count,
+                                                     const int2* __restrict__ fix_list, int fix_cap)
+{
+    fixup_body<DX, DY>((blockIdx.x * blockDim.x + threadIdx.x) >> 6, (gridDim.x * blockDim.x) >> 6, 0, n,
+                       pts, nn, n, npad, ga, gf, crit, numbuf, denbuf, ell, fix_count, fix_list, fix_cap);
+}
+
 // Fixed-order sum of each setting's row of per-point values; optional copy
 // of the rows to a caller buffer with row stride n; non-finite counts.
-__global__ __launch_bounds__(256) void k_grid_rows(const double* __restrict__ ell, int n, int npad,
-                                                   double* __restrict__ totals,
-                                                   double* __restrict__ per_point,
-                                                   double* __restrict__ counts)
+__device__ __forceinline__ void rows_body(int g, const double* __restrict__ ell, int n, int npad,
+                                          double* __restrict__ totals, double* __restrict__ per_point,
+                                          double* __restrict__ counts)
 {
     __shared__ double red[8];
-    const int g = blockIdx.x;
     double v[2] = {0.0, 0.0};
     for (int i = threadIdx.x; i < n; i += 256) {
         const double x = ell[(size_t)g * npad + i];
@@ -863,6 +917,14 @@ __global__ __launch_bounds__(256) void k_grid_rows(const double* __restrict__ el
         totals[g] = v[0];
         counts[g] = v[1];
     }
+}
+
+__global__ __launch_bounds__(256) void k_grid_rows(const double* __restrict__ ell, int n, int npad,
+                                                   double* __restrict__ totals,
+                                                   double* __restrict__ per_point,
+                                                   double* __restrict__ counts)
+{
+    rows_body(blockIdx.x, ell, n, npad, totals, per_point, counts);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1003,6 +1065,63 @@ __global__ void k_colmean(const float* __restrict__ pts, int n, int dx, int stri
     mean[k] = (float)(s / n);
 }
 
+// Coefficients of a scalar-bandwidth grid (base 2, FP32 as the kernels use
+// them, and their FP64 copies and log normalisations for the finalisation).
+static void grid_coeffs(int dx, int dy, const double* hx, int n_hx, const double* hy, int n_hy,
+                        GridArgs& ga, GridFin& gf)
+{
+    ga.gx = gf.gx = n_hx;
+    ga.gy = gf.gy = n_hy;
+    ga.gxp = (n_hx + 15) / 16 * 16;
+    ga.gyp = (n_hy + 15) / 16 * 16;
+    for (int a = 0; a < 64; ++a) {
+        const double h = hx[a < n_hx ? a : n_hx - 1];
+        ga.cx[a] = (float)(LOG2E / (2.0 * h * h));
+        gf.cxa[a] = (double)ga.cx[a];
+        gf.log_cx[a] = -dx * (log(h) + HALF_LOG_2PI);
+    }
+    for (int b = 0; b < 64; ++b) {
+        const double h = hy[b < n_hy ? b : n_hy - 1];
+        ga.cy[b] = (float)(LOG2E / (2.0 * h * h));
+        gf.cyb[b] = (double)ga.cy[b];
+        gf.log_cy[b] = -dy * (log(h) + HALF_LOG_2PI);
+    }
+    // The FP32 pass biases the grid tile that holds the smallest hx and the
+    // smallest hy (the only cells that can fall far below 1 need both small).
+    gf.tb = ga.gyp / 16;
+    int amin = 0, bmin = 0;
+    for (int a = 1; a < n_hx; ++a)
+        if (hx[a] < hx[amin]) amin = a;
+    for (int b = 1; b < n_hy; ++b)
+        if (hy[b] < hy[bmin]) bmin = b;
+    gf.biased = 1u << ((amin / 16) * gf.tb + bmin / 16);
+    ga.bias_ta = amin / 16;
+    ga.bias_tb = bmin / 16;
+    for (int t = 0; t < 16; ++t) ga.tile_of[t] = t;
+}
+
+// Work layout of one grid call on a model of npad rows: numbuf [G][npad] |
+// denbuf [gx][npad] | ell [G][npad] | fix_count [64] | flags [tiles][npad] |
+// plist [tiles][npad] | pcount [64] | fix_list (the rest).  False if
+// work_bytes cannot hold it.
+static bool carve_grid_work(void* work, size_t work_bytes, int64_t npad, int n_hx, int n_hy, GridWork& w)
+{
+    const size_t G = (size_t)n_hx * n_hy;
+    w.numbuf = (double*)work;
+    w.denbuf = w.numbuf + G * npad;
+    w.ell = w.denbuf + (size_t)n_hx * npad;
+    w.fix_count = (int*)(w.ell + G * npad);
+    w.flags = w.fix_count + 64;
+    const size_t ntl = (size_t)((n_hx + 15) / 16) * ((n_hy + 15) / 16);  // grid tiles
+    w.plist = w.flags + ntl * npad;
+    w.pcount = w.plist + ntl * npad;
+    w.fix_list = (int2*)(w.pcount + 64);
+    const size_t used = (size_t)((char*)w.fix_list - (char*)work);
+    if (used >= work_bytes) return false;
+    w.fix_cap = (int)std::min<size_t>((work_bytes - used) / sizeof(int2), size_t(1) << 30);
+    return true;
+}
+
 hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* hy, int n_hy, int crit,
                        bool xt, double* totals, double* per_point, void* work, size_t work_bytes,
                        double* counts, hipStream_t stream)
@@ -1016,52 +1135,9 @@ hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* h
     }
     GridArgs ga;
     GridFin gf;
-    ga.gx = gf.gx = n_hx;
-    ga.gy = gf.gy = n_hy;
-    ga.gxp = (n_hx + 15) / 16 * 16;
-    ga.gyp = (n_hy + 15) / 16 * 16;
-    for (int a = 0; a < 64; ++a) {
-        const double h = hx[a < n_hx ? a : n_hx - 1];
-        ga.cx[a] = (float)(LOG2E / (2.0 * h * h));
-        gf.cxa[a] = (double)ga.cx[a];
-        gf.log_cx[a] = -m->dx * (log(h) + HALF_LOG_2PI);
-    }
-    for (int b = 0; b < 64; ++b) {
-        const double h = hy[b < n_hy ? b : n_hy - 1];
-        ga.cy[b] = (float)(LOG2E / (2.0 * h * h));
-        gf.cyb[b] = (double)ga.cy[b];
-        gf.log_cy[b] = -m->dy * (log(h) + HALF_LOG_2PI);
-    }
-    // The FP32 pass biases the grid tile that holds the smallest hx and the
-    // smallest hy (the only cells that can fall far below 1 need both small).
-    gf.tb = ga.gyp / 16;
-    {
-        int amin = 0, bmin = 0;
-        for (int a = 1; a < n_hx; ++a)
-            if (hx[a] < hx[amin]) amin = a;
-        for (int b = 1; b < n_hy; ++b)
-            if (hy[b] < hy[bmin]) bmin = b;
-        gf.biased = 1u << ((amin / 16) * gf.tb + bmin / 16);
-        ga.bias_ta = amin / 16;
-        ga.bias_tb = bmin / 16;
-        for (int t = 0; t < 16; ++t) ga.tile_of[t] = t;
-    }
-    const size_t G = (size_t)n_hx * n_hy;
-    // work layout: numbuf [G][npad] | denbuf [gx][npad] | ell [G][npad] |
-    // fix_count [64] | flags [tiles][npad] | plist [tiles][npad] | pcount [64] | fix_list
+    grid_coeffs(m->dx, m->dy, hx, n_hx, hy, n_hy, ga, gf);
     GridWork w;
-    w.numbuf = (double*)work;
-    w.denbuf = w.numbuf + G * m->npad;
-    w.ell = w.denbuf + (size_t)n_hx * m->npad;
-    w.fix_count = (int*)(w.ell + G * m->npad);
-    w.flags = w.fix_count + 64;
-    const size_t ntl = (size_t)(ga.gxp / 16) * (ga.gyp / 16);  // grid tiles
-    w.plist = w.flags + ntl * m->npad;
-    w.pcount = w.plist + ntl * m->npad;
-    w.fix_list = (int2*)(w.pcount + 64);
-    const size_t used = (size_t)((char*)w.fix_list - (char*)work);
-    if (used >= work_bytes) return hipErrorInvalidValue;
-    w.fix_cap = (int)std::min<size_t>((work_bytes - used) / sizeof(int2), size_t(1) << 30);
+    if (!carve_grid_work(work, work_bytes, m->npad, n_hx, n_hy, w)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, w.fix_count, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1084,6 +1160,269 @@ size_t grid_work_bytes(const cde_model* m, int n_hx, int n_hy)
     const size_t ntl = (size_t)((n_hx + 15) / 16) * ((n_hy + 15) / 16);  // grid tiles
     return sizeof(double) * (2 * G + n_hx) * m->npad + (2 * ntl * m->npad + 128) * sizeof(int) +
            fix_cap * sizeof(int2) + 64;
+}
+
+
+// ---------------------------------------------------------------- grouped launch
+//
+// One launch per pipeline stage over a work list of items, each item a range
+// of points [p0, p1) of one model against all of that model's points, for a
+// grid of at most 16 x 16 cells (one grid tile, which the FP32 pass biases).
+// A block maps its index to (item, local block) through the prefix sums in
+// GridBatch::pre and runs the same device function, on the same per-point
+// arithmetic, as the one-model launch: each point's values are therefore
+// bit-identical to cde_loo_loglik's, whatever the list holds.  A model's
+// ranges run in order (their work buffers carry over between launches); the
+// item that ends a model also sums its rows into the totals.
+
+constexpr int GRID_BATCH_MAX = 8;  // items per launch
+
+// Finalisation constants of grids up to 16 x 16 (the grouped launch).
+struct GridFin16 {
+    double cxa[16];
+    double cyb[16];
+    double log_cx[16];
+    double log_cy[16];
+    int gx, gy;
+    int tb;
+    unsigned biased;
+};
+
+struct GridBatchItem {
+    const float* pts;
+    double* nn;        // [2][npad] neighbour shifts of the model
+    int n, npad;
+    int p0, p1;        // points [p0, p1); p1 = npad for the model's last range
+    GridWork w;        // the model's grid work buffers
+    double* totals;    // [G], written by the model's last range
+    double* counts;    // [G] non-finite counts (model scratch)
+    int64_t* nonfinite;
+};
+
+struct GridBatch {
+    int count;
+    int pre[GRID_BATCH_MAX + 1];  // blocks of items 0..k-1 in this launch
+    GridBatchItem it[GRID_BATCH_MAX];
+};
+
+__device__ __forceinline__ int batch_item(const GridBatch& b, int bx)
+{
+    int k = 0;
+    while (k + 1 < b.count && bx >= b.pre[k + 1]) ++k;
+    return k;
+}
+
+// per item (blockIdx.y): clear the flags of its range and its list and queue counters
+__global__ void k_batch_zero(GridBatch b)
+{
+    const GridBatchItem& t = b.it[blockIdx.y];
+    const int i = t.p0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < t.p1) t.w.flags[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+        t.w.pcount[threadIdx.x] = 0;
+        if (threadIdx.x == 0) *t.w.fix_count = 0;
+    }
+}
+
+template <int DX, int DY>
+__global__ __launch_bounds__(TILE) void k_nn_batch(GridBatch b)
+{
+    const int k = batch_item(b, blockIdx.x);
+    const GridBatchItem& t = b.it[k];
+    nn_body<DX, DY>(t.p0 / TILE + (blockIdx.x - b.pre[k]), t.pts, t.n, t.nn, t.npad);
+}
+
+template <int DX, int DY, int PW>
+__global__ __launch_bounds__(TILE) void k_loo_grid32_batch(GridBatch b, GridArgs ga)
+{
+    const int k = batch_item(b, blockIdx.x);
+    const GridBatchItem& t = b.it[k];
+    grid32_body<DX, DY, PW, true>(t.p0 / (4 * PW) + (blockIdx.x - b.pre[k]), 0, t.pts, t.nn, t.n, t.npad,
+                                  ga, t.w.numbuf, t.w.denbuf);
+}
+
+template <bool FLAG>
+__global__ void k_finalize_batch(GridBatch b, GridFin16 gf, int crit)
+{
+    const int k = batch_item(b, blockIdx.x);
+    const GridBatchItem& t = b.it[k];
+    const int i = t.p0 + (blockIdx.x - b.pre[k]) * blockDim.x + threadIdx.x;
+    finalize_body(i, blockIdx.y, t.w.numbuf, t.w.denbuf, t.nn, t.n, t.npad, gf, crit, t.w.ell,
+                  t.w.fix_count, t.w.fix_list, t.w.fix_cap, FLAG ? t.w.flags : (int*)nullptr);
+}
+
+__global__ void k_compact_batch(GridBatch b)
+{
+    const int k = batch_item(b, blockIdx.x);
+    const GridBatchItem& t = b.it[k];
+    const int i = t.p0 + (blockIdx.x - b.pre[k]) * blockDim.x + threadIdx.x;
+    compact_body(i, 0, t.w.flags, t.n, t.npad, t.w.pcount, t.w.plist);
+}
+
+template <int DX, int DY, int PWF>
+__global__ __launch_bounds__(TILE) void k_rerun_batch(GridBatch b, GridArgs ga)
+{
+    const int k = batch_item(b, blockIdx.x);
+    const GridBatchItem& t = b.it[k];
+    grid64_body<DX, DY, false, PWF>(blockIdx.x - b.pre[k], 0, t.pts, t.nn, t.n, t.npad, ga, nullptr,
+                                    t.w.numbuf, t.w.denbuf, t.w.plist, t.w.pcount);
+}
+
+constexpr int BATCH_FIX_BLOCKS = 128;  // fixup blocks per item
+
+template <int DX, int DY>
+__global__ __launch_bounds__(TILE) void k_fixup_batch(GridBatch b, GridArgs ga, GridFin16 gf, int crit)
+{
+    const GridBatchItem& t = b.it[blockIdx.y];
+    fixup_body<DX, DY>((blockIdx.x * blockDim.x + threadIdx.x) >> 6, (gridDim.x * blockDim.x) >> 6, t.p0,
+                       min(t.p1, t.n), t.pts, t.nn, t.n, t.npad, ga, gf, crit, t.w.numbuf, t.w.denbuf,
+                       t.w.ell, t.w.fix_count, t.w.fix_list, t.w.fix_cap);
+}
+
+// rows of the items that end their model (blockIdx.y), one block per setting
+__global__ __launch_bounds__(256) void k_rows_batch(GridBatch b)
+{
+    const GridBatchItem& t = b.it[blockIdx.y];
+    rows_body(blockIdx.x, t.w.ell, t.n, t.npad, t.totals, nullptr, t.counts);
+}
+
+__global__ void k_counts_batch(GridBatch b, int nsets)
+{
+    const int k = threadIdx.x;
+    if (k >= b.count || !b.it[k].nonfinite) return;
+    double s = 0.0;
+    for (int q = 0; q < nsets; ++q) s += b.it[k].counts[q];
+    *b.it[k].nonfinite = (int64_t)s;
+}
+
+// Blocks of each item for a stage that covers its range in units of `per`
+// points (rounded up); returns the total.
+static int batch_prefix(GridBatch& b, int per)
+{
+    b.pre[0] = 0;
+    for (int k = 0; k < b.count; ++k) b.pre[k + 1] = b.pre[k] + (b.it[k].p1 - b.it[k].p0 + per - 1) / per;
+    return b.pre[b.count];
+}
+
+template <int DX, int DY>
+static hipError_t grid_batch_t(const GridBatch& all, const bool* do_nn, const GridArgs& ga,
+                               const GridFin16& gf, int crit, hipStream_t stream)
+{
+    constexpr int PW = CDE_GRID32_POINTS_PER_WAVE;
+    const int G = ga.gx * ga.gy;
+    hipError_t e;
+    int maxr = 0;
+    for (int k = 0; k < all.count; ++k) maxr = std::max(maxr, all.it[k].p1 - all.it[k].p0);
+    hipLaunchKernelGGL(k_batch_zero, dim3((unsigned)((maxr + 255) / 256), (unsigned)all.count), dim3(256), 0,
+                       stream, all);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // neighbour shifts of the ranges whose model has none yet
+    GridBatch nb = all;
+    nb.count = 0;
+    for (int k = 0; k < all.count; ++k)
+        if (do_nn[k]) nb.it[nb.count++] = all.it[k];
+    if (nb.count > 0) {
+        const int blocks = batch_prefix(nb, TILE);
+        hipLaunchKernelGGL((k_nn_batch<DX, DY>), dim3((unsigned)blocks), dim3(TILE), 0, stream, nb);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    GridBatch b = all;
+    int blocks = batch_prefix(b, 4 * PW);
+    hipLaunchKernelGGL((k_loo_grid32_batch<DX, DY, PW>), dim3((unsigned)blocks), dim3(TILE), 0, stream, b, ga);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    blocks = batch_prefix(b, 256);
+    hipLaunchKernelGGL(k_finalize_batch<true>, dim3((unsigned)blocks, (unsigned)G), dim3(256), 0, stream, b, gf,
+                       crit);
+    hipLaunchKernelGGL(k_compact_batch, dim3((unsigned)blocks), dim3(256), 0, stream, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // FP64 rerun of flagged points, with the points-per-wave rule of the
+    // one-model launch (2 up to 2^18 rows, else 8), one launch per rule
+    for (int pwf : {2, 8}) {
+        GridBatch rb = all;
+        rb.count = 0;
+        for (int k = 0; k < all.count; ++k)
+            if ((all.it[k].npad <= (1 << 18)) == (pwf == 2)) rb.it[rb.count++] = all.it[k];
+        if (rb.count == 0) continue;
+        const int rblocks = batch_prefix(rb, 4 * pwf);
+        if (pwf == 2)
+            hipLaunchKernelGGL((k_rerun_batch<DX, DY, 2>), dim3((unsigned)rblocks), dim3(TILE), 0, stream, rb, ga);
+        else
+            hipLaunchKernelGGL((k_rerun_batch<DX, DY, 8>), dim3((unsigned)rblocks), dim3(TILE), 0, stream, rb, ga);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_finalize_batch<false>, dim3((unsigned)blocks, (unsigned)G), dim3(256), 0, stream, b, gf,
+                       crit);
+    hipLaunchKernelGGL((k_fixup_batch<DX, DY>), dim3(BATCH_FIX_BLOCKS, (unsigned)all.count), dim3(TILE), 0,
+                       stream, all, ga, gf, crit);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    GridBatch lb = all;
+    lb.count = 0;
+    for (int k = 0; k < all.count; ++k)
+        if (all.it[k].p1 == all.it[k].npad) lb.it[lb.count++] = all.it[k];
+    if (lb.count > 0) {
+        hipLaunchKernelGGL(k_rows_batch, dim3((unsigned)G, (unsigned)lb.count), dim3(256), 0, stream, lb);
+        hipLaunchKernelGGL(k_counts_batch, dim3(1), dim3(64), 0, stream, lb, G);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+#define CDE_GRID_BATCH_CASE(DX_, DY_) \
+    case (DX_) * 8 + (DY_): e = grid_batch_t<DX_, DY_>(b, do_nn + k0, ga, gf16, crit, stream); break;
+
+hipError_t launch_grid_batch(const GridRange* r, int count, const double* hx, int n_hx, const double* hy,
+                             int n_hy, int crit, hipStream_t stream)
+{
+    if (count < 1 || n_hx > 16 || n_hy > 16) return hipErrorInvalidValue;
+    const int dx = r[0].m->dx, dy = r[0].m->dy;
+    GridArgs ga;
+    GridFin gf;
+    grid_coeffs(dx, dy, hx, n_hx, hy, n_hy, ga, gf);
+    GridFin16 gf16;
+    for (int a = 0; a < 16; ++a) {
+        gf16.cxa[a] = gf.cxa[a];
+        gf16.cyb[a] = gf.cyb[a];
+        gf16.log_cx[a] = gf.log_cx[a];
+        gf16.log_cy[a] = gf.log_cy[a];
+    }
+    gf16.gx = gf.gx;
+    gf16.gy = gf.gy;
+    gf16.tb = gf.tb;
+    gf16.biased = gf.biased;
+    bool do_nn[GRID_BATCH_MAX * 64];
+    if (count > GRID_BATCH_MAX * 64) return hipErrorInvalidValue;
+    for (int k0 = 0; k0 < count; k0 += GRID_BATCH_MAX) {
+        GridBatch b;
+        b.count = std::min(GRID_BATCH_MAX, count - k0);
+        for (int k = 0; k < b.count; ++k) {
+            const GridRange& q = r[k0 + k];
+            if (q.m->dx != dx || q.m->dy != dy) return hipErrorInvalidValue;
+            GridBatchItem& t = b.it[k];
+            t.pts = (const float*)q.m->pts;
+            t.nn = (double*)q.m->nn;
+            t.n = (int)q.m->n;
+            t.npad = (int)q.m->npad;
+            t.p0 = (int)q.i0;
+            t.p1 = q.i1 == q.m->n ? (int)q.m->npad : (int)q.i1;
+            if (!carve_grid_work(q.work, q.work_bytes, q.m->npad, n_hx, n_hy, t.w)) return hipErrorInvalidValue;
+            t.totals = q.totals;
+            t.counts = q.counts;
+            t.nonfinite = q.nonfinite;
+            do_nn[k0 + k] = q.do_nn;
+        }
+        hipError_t e = hipErrorInvalidValue;
+        switch (dx * 8 + dy) {
+            CDE_GRID_BATCH_CASE(1, 1) CDE_GRID_BATCH_CASE(1, 2) CDE_GRID_BATCH_CASE(2, 1)
+            CDE_GRID_BATCH_CASE(2, 2) CDE_GRID_BATCH_CASE(3, 1) CDE_GRID_BATCH_CASE(3, 2)
+            CDE_GRID_BATCH_CASE(4, 1) CDE_GRID_BATCH_CASE(4, 2) CDE_GRID_BATCH_CASE(5, 1)
+            CDE_GRID_BATCH_CASE(5, 2) CDE_GRID_BATCH_CASE(6, 1) CDE_GRID_BATCH_CASE(6, 2)
+            CDE_GRID_BATCH_CASE(7, 1) CDE_GRID_BATCH_CASE(7, 2) CDE_GRID_BATCH_CASE(8, 1)
+            CDE_GRID_BATCH_CASE(8, 2) CDE_GRID_BATCH_CASE(16, 1) CDE_GRID_BATCH_CASE(16, 2)
+            default: return hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace cde

@@ -179,6 +179,26 @@ class Model:
         return f
 
 
+def launch_batch(items, hx, hy, criterion: str = "cond", stream=None) -> None:
+    """One grouped launch (``cde_launch_batch``) of the grid criterion over
+    a work list.  ``items``: sequence of (model, i0, i1, totals, nonfinite):
+    points [i0, i1) of an FP32 Model, a float64 device tensor [len(hx) *
+    len(hy)] that receives the totals when i1 == model.n (else None), and an
+    optional int64 device tensor [1] for the non-finite count."""
+    hx = [float(v) for v in hx]
+    hy = [float(v) for v in hy]
+    arr = (B.WorkItem * max(1, len(items)))()
+    for k, (m, i0, i1, tot, nonfin) in enumerate(items):
+        arr[k].model = m.handle
+        arr[k].i0 = int(i0)
+        arr[k].i1 = int(i1)
+        arr[k].totals_dev = tot.data_ptr() if tot is not None else None
+        arr[k].n_nonfinite_dev = nonfin.data_ptr() if nonfin is not None else None
+    st = B.load().cde_launch_batch(ctypes.cast(arr, ctypes.c_void_p), len(items), B.doubles(hx), len(hx),
+                                   B.doubles(hy), len(hy), CRITERIA[criterion], _stream_ptr(stream))
+    B.check(st, "cde_launch_batch")
+
+
 def density_summary(f: torch.Tensor, ygrid, alpha: float = 0.05, stream=None) -> torch.Tensor:
     """Mass, mode and narrowest 1 - alpha interval of each row of f [q, k]
     on the increasing grid ygrid [k] (``cde_density_summary``): [q, 4] float64."""

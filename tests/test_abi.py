@@ -63,6 +63,12 @@ def test_invalid_arguments_return_status(lib):
     assert lib.cde_loo_loglik_list(None, hv, 1, 0, 0, 8, None, None) == B.CDE_EINVAL
     assert lib.cde_density_query(None, 8, 1, 8, 1, hv, 0, 8, None) == B.CDE_EINVAL
     assert lib.cde_cv_ise(None, hv, 8, None, None) == B.CDE_EINVAL
+    assert lib.cde_launch_batch(None, 1, hv, 1, hv, 1, 0, None) == B.CDE_EINVAL
+    items = (B.WorkItem * 1)()
+    assert lib.cde_launch_batch(ctypes.cast(items, ctypes.c_void_p), 1, hv, 17, hv, 1, 0, None) == B.CDE_EINVAL
+    assert b"[1, 16]" in lib.cde_last_error()
+    assert lib.cde_launch_batch(ctypes.cast(items, ctypes.c_void_p), 1, hv, 1, hv, 1, 0, None) == B.CDE_EINVAL
+    assert b"no model" in lib.cde_last_error()
     assert lib.cde_destroy(None) == B.CDE_OK
     assert lib.cde_model_device_bytes(None) == 0
 
@@ -96,15 +102,26 @@ def test_workspace_bytes_host_arithmetic(lib):
 
 
 def test_bandwidth_range_check_host(lib):
-    """The representable-range rule of every model call, on the host: each
-    c_k = log2(e)/(2 h_k^2) <= 2^59 and sum_k range_k^2 c_k <= 2^100 per axis
-    (FP32 models); 2^900 for both (FP64 models)."""
+    """The representable-range rule of the model calls, on the host: each
+    c_k = log2(e)/(2 h_k^2) <= 2^59 and X, Y = sum_k range_k^2 c_k <= 2^100
+    per axis (FP32 models; 2^900 for all on FP64 models); on the diagonal
+    pass also (X + Y)(dx + dy + 2) <= 2^29 (FP32; 2^61 on FP64 models)."""
     import math
 
     from paper_1206_5278_amd import _binding as B
 
-    def check(rng, h, prec=B.CDE_F32, dx=5, dy=1):
-        return lib.cde_check_bandwidths(B.doubles(rng), dx, dy, B.doubles(h), prec)
+    def check(rng, h, prec=B.CDE_F32, dx=5, dy=1, diag=0):
+        return lib.cde_check_bandwidths(B.doubles(rng), dx, dy, B.doubles(h), prec, diag)
+
+    # the diagonal-pass rule: with range 1 in every dimension and one h,
+    # X + Y = 6 c and (X + Y) * 8 <= 2^29 means c <= 2^26 / 6
+    hd = math.sqrt(math.log2(math.e) / (2.0 * 2.0 ** 26 / 6.0))
+    one = [1.0] * 6
+    assert check(one, [hd * (1 + 1e-9)] * 6, diag=1) == B.CDE_OK
+    assert check(one, [hd * (1 - 1e-9)] * 6, diag=1) == B.CDE_EUNSUPPORTED
+    assert b"diagonal pass" in lib.cde_last_error()
+    assert check(one, [hd * (1 - 1e-9)] * 6, diag=0) == B.CDE_OK  # the grid pass takes it
+    assert check(one, [hd * 1e-3] * 6, B.CDE_F64, diag=1) == B.CDE_OK
 
     one = [1.0] * 6
     assert check(one, [0.1] * 6) == B.CDE_OK
@@ -129,5 +146,5 @@ def test_bandwidth_range_check_host(lib):
     assert check([1.0] * 5 + [-1.0], [0.1] * 6) == B.CDE_EINVAL
     assert check([1.0] * 5 + [float("inf")], [0.1] * 6) == B.CDE_EINVAL
     assert check(one, [0.1] * 6, 7) == B.CDE_EINVAL
-    assert lib.cde_check_bandwidths(None, 5, 1, B.doubles([0.1] * 6), 0) == B.CDE_EINVAL
+    assert lib.cde_check_bandwidths(None, 5, 1, B.doubles([0.1] * 6), 0, 0) == B.CDE_EINVAL
     assert check(one, [0.1] * 6, B.CDE_F32, 0, 1) == B.CDE_EINVAL

@@ -85,25 +85,52 @@ def test_nonfinite_training_data_rejected():
 
 
 def test_edge_of_the_supported_range_matches_oracle():
-    # bandwidths a few times the smallest supported one: every kernel value
-    # but the nearest neighbours' underflows, and the values are ~1e14 in
-    # magnitude; the per-point tolerance is relative to |l*|
+    # Diagonal pass: x bandwidths at 0.8 of its limit (X + Y)(dx + dy + 2) <=
+    # 2^29; every x-kernel value but the nearest neighbour's underflows.
+    # Grid pass: bandwidths 4x the smallest it takes (c = 2^55), where the
+    # values reach ~1e14 in magnitude.  Per-point tolerance relative to |l*|.
     print("case: edge-of-range bandwidths, n=300 dx=2", flush=True)
+    from paper_1206_5278_amd import _binding as B
     x, y = workloads.gmm(300, seed=43, dx=2)
     xo, yo, xd, yd = P.f32_pair(x, y)
     m = cde().Model(xd, yd)
-    h0 = 4.0 * hmin_f32()
-    hs = [[h0, h0, 0.3], [0.3, 0.3, h0], [h0, 0.5, h0]]
+    l2e = math.log2(math.e)
+    rx = xo.max(axis=0) - xo.min(axis=0)
+    ry = float(yo.max() - yo.min())
+    ey = ry * ry * l2e / (2 * 0.3 * 0.3)
+    hd = math.sqrt(float(np.sum(rx * rx)) * l2e / (2 * (0.8 * 2.0 ** 29 / 5 - ey)))
+    hs = [[hd, hd, 0.3], [hd, 1.5 * hd, 0.3]]
     tot, pp = m.loo_list(hs, per_point=True)
     pp = pp.cpu().numpy()
     for s, h in enumerate(hs):
         ref = oracle.loo(xo, yo, h, nthreads=NT)
         P.assert_points(pp[s], ref)
+    # 0.85 hd puts (X + Y)(dx + dy + 2) at 0.8 / 0.85^2 = 1.1 of the limit
+    assert status_of(lambda: m.loo_list([[0.85 * hd, 0.85 * hd, 0.3]])) == B.CDE_EUNSUPPORTED
+    h0 = 4.0 * hmin_f32()
     hx = [h0, 0.3]
     hy = [h0, 0.2]
     tg, ppg, nonfin = m.loo_grid(hx, hy, per_point=True)
     assert int(nonfin.item()) == 0
-    P.assert_points(ppg.cpu().numpy(), oracle.loo_grid(xo, yo, hx, hy, nthreads=NT))
+    ppg = ppg.cpu().numpy()
+    ref = oracle.loo_grid(xo, yo, hx, hy, nthreads=NT)
+    # Cells (h0, h0), (0.3, h0), (0.3, 0.2): against the oracle.  Cell
+    # (h0, 0.2) is where the oracle's own FP64 exponents, about d^2 c = 1e16
+    # with an ulp of ~2, cannot resolve l_i = O(10); there the exact value is
+    # the hx -> 0 limit log K_hy(y_i - y_nn(i)), y_nn the x-nearest neighbour,
+    # since the second-nearest x-neighbour of every point lies more than 1e6
+    # binary orders lower (checked here).
+    for g in (0, 2, 3):
+        P.assert_points(ppg[g], ref[g])
+    d2x = np.sum((xo[:, None, :] - xo[None, :, :]) ** 2, axis=2)
+    np.fill_diagonal(d2x, np.inf)
+    srt = np.sort(d2x, axis=1)
+    c0 = math.log2(math.e) / (2 * h0 * h0)
+    assert np.min(srt[:, 1] - srt[:, 0]) * c0 > 1e6
+    nn = np.argmin(d2x, axis=1)
+    dyn = yo[:, 0] - yo[nn, 0]
+    limit = -dyn * dyn / (2 * 0.2 * 0.2) - math.log(0.2) - 0.5 * math.log(2 * math.pi)
+    P.assert_points(ppg[1], limit)
 
 
 def test_grid_fixup_beyond_its_queue():
