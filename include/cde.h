@@ -45,7 +45,7 @@
  *     largest exponent a pair can have):
  *       every call:   each c_k <= 2^59, X <= 2^100 and Y <= 2^100 (FP32
  *                     models; 2^900 for all three on FP64 models);
- *       calls on the diagonal pass (cde_loo_grad,
+ *       calls on the diagonal pass (cde_loo_grad, cde_loo_grad_noalloc,
  *       cde_loo_loglik_list with the Gaussian kernel, cde_cv_ise, and the
  *       Gaussian cde_loo_loglik and cde_density_query of FP64 models), whose
  *       exponents are formed in the model's precision relative to a
@@ -232,6 +232,28 @@ cde_status cde_loo_loglik_list(cde_model* m, const double* h, int32_t g,
 cde_status cde_loo_grad(cde_model* m, const double* h, cde_criterion criterion,
                         double* total_dev, double* grad_dev, double* per_point_dev,
                         void* stream);
+
+/* Allocation-free variant of cde_loo_grad, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc.  Same arguments, kernels and results as
+ * cde_loo_grad (bit for bit whenever cde_loo_grad's j-chunk count fits the
+ * scratch below; otherwise fewer chunks, which changes only the rounding).
+ * The call allocates nothing and frees nothing: its scratch is a
+ * library-owned static device array of 64 MiB on each GPU, created when the
+ * library's code is loaded on that GPU and held until the process ends.
+ * Every call on one GPU shares that array, so calls that overlap in time on
+ * one GPU (on different streams, or from different threads) race; order
+ * them.  Nothing in the array needs clearing between calls.
+ * Limit: the per-block rows plus one j-chunk of partials,
+ * 8 ((n_pad / 256)(dx + dy + 2) + 1 + n_pad (4 + 2 dx + dy)) + 256 bytes
+ * with n_pad = n rounded up to 256, must fit the 64 MiB (n <= 557,824 at
+ * dx = 5, dy = 1; n <= 220,160 at dx = 16, dy = 2); beyond it
+ * CDE_EUNSUPPORTED with a message.
+ * The model's first call that checks bandwidths still waits for cde_create's
+ * extent copy (no allocation). */
+cde_status cde_loo_grad_noalloc(cde_model* m, const double* h, cde_criterion criterion,
+                                double* total_dev, double* grad_dev, double* per_point_dev,
+                                void* stream);
 
 /* Conditional density queries, eq. (1) over all n training points (no point
  * left out): f_dev[qq][g] = f(ygrid[g] | xq[qq]).

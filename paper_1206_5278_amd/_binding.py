@@ -41,6 +41,7 @@ SIGNATURES = {
     "cde_density_summary": (ctypes.c_int, [_vp, _vp, _i64, _i64, ctypes.c_double, _vp, _vp]),
     "cde_cv_ise": (ctypes.c_int, [_vp, _dp, _vp, _vp, _vp]),
     "cde_check_bandwidths": (ctypes.c_int, [_dp, _i32, _i32, _dp, ctypes.c_int, _i32]),
+    "cde_loo_grad_noalloc": (ctypes.c_int, [_vp, _dp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "cde_launch_batch": (ctypes.c_int, [_vp, _i32, _dp, _i32, _dp, _i32, ctypes.c_int, _vp]),
 }
 

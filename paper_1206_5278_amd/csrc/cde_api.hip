@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -311,21 +312,18 @@ size_t grid_call_scratch(const cde_model* m, int n_hx, int n_hy)
     return grid_work_bytes(m, n_hx, n_hy) + sizeof(double) * (size_t)n_hx * n_hy + 256;
 }
 
+// The pass itself, in `work` (block rows and counts, then the chunk partials
+// of `chunks` j-chunks per launch: diag_list_scratch's layout).
 template <typename T>
-cde_status run_diag_list(cde_model* m, const double* h, int g, int crit, bool grad, double* totals,
-                         double* grad_out, double* per_point, int64_t* nonfinite,
-                         hipStream_t stream)
+cde_status run_diag_list_in(const cde_model* m, const double* h, int g, int crit, bool grad,
+                            double* totals, double* grad_out, double* per_point, int64_t* nonfinite,
+                            int chunks, void* work, hipStream_t stream)
 {
     const int p = m->dx + m->dy;
     const int nblocks = (int)(m->npad / TILE);
     const int nv = grad ? p + 2 : 2;
-    int chunks = 1;
-    const size_t scratch = diag_list_scratch<T>(m, g, grad, &chunks);
-    const int per_launch = std::min(g, MAX_SETS_PER_LAUNCH);
     const size_t part_doubles = (size_t)g * nblocks * nv + (size_t)g;
-    cde_status st = ensure_scratch(m, scratch);
-    if (st != CDE_OK) return st;
-    double* part = (double*)m->scratch;
+    double* part = (double*)work;
     double* partial = part + part_doubles;
     for (int s0 = 0; s0 < g; s0 += MAX_SETS_PER_LAUNCH) {
         const int cnt = std::min(MAX_SETS_PER_LAUNCH, g - s0);
@@ -342,6 +340,79 @@ cde_status run_diag_list(cde_model* m, const double* h, int g, int crit, bool gr
                                        counts, nonfinite, stream);
     if (e != hipSuccess) return hip_fail(e, "launch k_reduce_parts");
     return CDE_OK;
+}
+
+template <typename T>
+cde_status run_diag_list(cde_model* m, const double* h, int g, int crit, bool grad, double* totals,
+                         double* grad_out, double* per_point, int64_t* nonfinite,
+                         hipStream_t stream)
+{
+    int chunks = 1;
+    const size_t scratch = diag_list_scratch<T>(m, g, grad, &chunks);
+    cde_status st = ensure_scratch(m, scratch);
+    if (st != CDE_OK) return st;
+    return run_diag_list_in<T>(m, h, g, crit, grad, totals, grad_out, per_point, nonfinite, chunks,
+                               m->scratch, stream);
+}
+
+// ---- the allocation-free value and gradient (cde_loo_grad_noalloc) ----
+//
+// Its scratch is this file-scope device array: one copy per GPU, created when
+// the library's code is loaded on that GPU and held until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): the device address of each GPU's copy is
+// read once with hipGetSymbolAddress, with that GPU current, and kept in
+// g_noalloc_ptr.  Every call on a GPU shares its copy, so calls that overlap
+// in time on one GPU race.  The pass writes every scratch value it reads, so
+// nothing needs clearing between calls.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char noalloc_scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current GPU's copy of noalloc_scratch.
+cde_status noalloc_scratch_ptr(int device, void** out)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES)
+        return fail(CDE_EUNSUPPORTED, "cde_loo_grad_noalloc: device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(noalloc_scratch)");
+        g_noalloc_ptr[device] = p;
+    }
+    *out = g_noalloc_ptr[device];
+    return CDE_OK;
+}
+
+// Value and gradient of one setting with the scratch above: the j-chunk count
+// of cde_loo_grad, reduced until the chunk partials fit.
+template <typename T>
+cde_status run_grad_noalloc(cde_model* m, const double* h, int crit, double* total, double* grad,
+                            double* per_point, hipStream_t stream)
+{
+    const int nblocks = (int)(m->npad / TILE);
+    const int nv = m->dx + m->dy + 2;
+    const size_t rows_bytes = sizeof(double) * ((size_t)nblocks * nv + 1);
+    if (rows_bytes + 256 >= NOALLOC_SCRATCH_BYTES)
+        return fail(CDE_EUNSUPPORTED, "cde_loo_grad_noalloc: n too large for the 64 MiB scratch");
+    const size_t max_doubles = (NOALLOC_SCRATCH_BYTES - rows_bytes - 256) / sizeof(double);
+    if (diag_partial_doubles(m, 1, true, 1) > max_doubles) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg,
+                      "cde_loo_grad_noalloc: n = %lld needs %zu bytes of scratch, more than the "
+                      "64 MiB the entry point holds",
+                      (long long)m->n, rows_bytes + sizeof(double) * diag_partial_doubles(m, 1, true, 1));
+        return fail(CDE_EUNSUPPORTED, msg);
+    }
+    const int chunks = diag_chunks<T>(m, 1, true, std::min(max_doubles, MAX_DIAG_PARTIAL_DOUBLES));
+    void* work = nullptr;
+    cde_status st = noalloc_scratch_ptr(m->device, &work);
+    if (st != CDE_OK) return st;
+    return run_diag_list_in<T>(m, h, 1, crit, true, total, grad, per_point, nullptr, chunks, work, stream);
 }
 
 void fill_epan(EpanSet& s, const double* h, int dx, int dy)
@@ -782,6 +853,30 @@ cde_status cde_launch_batch(const cde_work_item* items, int32_t n_items, const d
         return CDE_OK;
     } catch (...) {
         return fail(CDE_EDEVICE, "cde_launch_batch: unexpected exception");
+    }
+}
+
+cde_status cde_loo_grad_noalloc(cde_model* m, const double* h, cde_criterion criterion,
+                                double* total_dev, double* grad_dev, double* per_point_dev,
+                                void* stream)
+{
+    try {
+        if (!m) return fail(CDE_EINVAL, "cde_loo_grad_noalloc: model is NULL");
+        if (!total_dev || !grad_dev) return fail(CDE_EINVAL, "cde_loo_grad_noalloc: output pointer is NULL");
+        if (criterion != CDE_COND && criterion != CDE_JOINT)
+            return fail(CDE_EINVAL, "cde_loo_grad_noalloc: unknown criterion");
+        {
+            cde_status st = check_model_settings(m, h, 1, true, "cde_loo_grad_noalloc");
+            if (st != CDE_OK) return st;
+        }
+        DeviceGuard guard(m->device);
+        if (!guard.ok) return fail(CDE_EDEVICE, "cde_loo_grad_noalloc: cannot make the model's device current");
+        hipStream_t s = (hipStream_t)stream;
+        return m->prec == CDE_F64
+                   ? run_grad_noalloc<double>(m, h, criterion, total_dev, grad_dev, per_point_dev, s)
+                   : run_grad_noalloc<float>(m, h, criterion, total_dev, grad_dev, per_point_dev, s);
+    } catch (...) {
+        return fail(CDE_EDEVICE, "cde_loo_grad_noalloc: unexpected exception");
     }
 }
 

@@ -63,6 +63,7 @@ def test_invalid_arguments_return_status(lib):
     assert lib.cde_loo_loglik_list(None, hv, 1, 0, 0, 8, None, None) == B.CDE_EINVAL
     assert lib.cde_density_query(None, 8, 1, 8, 1, hv, 0, 8, None) == B.CDE_EINVAL
     assert lib.cde_cv_ise(None, hv, 8, None, None) == B.CDE_EINVAL
+    assert lib.cde_loo_grad_noalloc(None, hv, 0, 8, 8, None, None) == B.CDE_EINVAL
     assert lib.cde_launch_batch(None, 1, hv, 1, hv, 1, 0, None) == B.CDE_EINVAL
     items = (B.WorkItem * 1)()
     assert lib.cde_launch_batch(ctypes.cast(items, ctypes.c_void_p), 1, hv, 17, hv, 1, 0, None) == B.CDE_EINVAL
