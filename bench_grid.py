@@ -40,6 +40,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--skip-highdim", action="store_true",
                     help="skip the two large sets (photoz 500k and highdim 1M)")
+    ap.add_argument("--highdim-only", action="store_true",
+                    help="only the 1M-point 16-D set, with its three x-distance variants")
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -49,6 +51,11 @@ def main():
     from paper_1206_5278_amd import _binding as B
     dev = torch.device("cuda:0")
     out = {"metric": "grid LOO-loglik pair-kernel evals/s"}
+
+    if args.highdim_only:
+        highdim(out, cde, workloads, B, np, torch, dev)
+        print(json.dumps(out))
+        return
 
     # tiny, FP64
     x, y = workloads.tiny()
@@ -81,19 +88,27 @@ def main():
         m.close()
         print(json.dumps({"photoz": out["photoz"]}), file=sys.stderr, flush=True)
 
-        hx, hy = workloads.WORKLOADS["highdim"]["grid"]
-        x, y = workloads.highdim()
-        x32, y32 = x.astype(np.float32), y.astype(np.float32)
-        m = cde.Model(torch.from_numpy(x32).to(dev), torch.from_numpy(y32).to(dev))
-        res = {}
-        for name, xt in (("valu_fp64_differences", B.CDE_XTERM_VALU),
-                         ("mfma_bf16x3_cross_term", B.CDE_XTERM_MFMA_BF16X3)):
-            dt, tot, nf = timed_grid(m, hx, hy, 1, xt)
-            res[name] = {"s": dt, "evals_per_s": 1e6 * (1e6 - 1) * 256 / dt, "nonfinite": int(nf.item())}
-            print(json.dumps({name: res[name]}), file=sys.stderr, flush=True)
-        m.close()
-        out["highdim"] = res
+        highdim(out, cde, workloads, B, np, torch, dev)
     print(json.dumps(out))
+
+
+def highdim(out, cde, workloads, B, np, torch, dev):
+    """The 1M-point 16-D set on its 16 x 16 grid, with each way of forming
+    the x-distances (FP64 differences, FP32 differences, split-bf16 x3 MFMA
+    cross term) in the same pass structure."""
+    hx, hy = workloads.WORKLOADS["highdim"]["grid"]
+    x, y = workloads.highdim()
+    x32, y32 = x.astype(np.float32), y.astype(np.float32)
+    m = cde.Model(torch.from_numpy(x32).to(dev), torch.from_numpy(y32).to(dev))
+    res = {}
+    for name, xt in (("valu_fp64_differences", B.CDE_XTERM_VALU),
+                     ("valu_fp32_differences", B.CDE_XTERM_VALU_F32),
+                     ("mfma_bf16x3_cross_term", B.CDE_XTERM_MFMA_BF16X3)):
+        dt, tot, nf = timed_grid(m, hx, hy, 1, xt)
+        res[name] = {"s": dt, "evals_per_s": 1e6 * (1e6 - 1) * 256 / dt, "nonfinite": int(nf.item())}
+        print(json.dumps({name: res[name]}), file=sys.stderr, flush=True)
+    m.close()
+    out["highdim"] = res
 
 
 if __name__ == "__main__":

@@ -100,11 +100,18 @@ typedef enum {
     CDE_JOINT = 1 /* sum_i log(num_i / (n-1)): eq. (3) times n */
 } cde_criterion;
 
+/* How the grid pass (cde_loo_loglik on FP32 models) forms the squared
+ * x-distances ||x_i - x_j||^2 of Section 2's kernel argument. */
 typedef enum {
-    CDE_XTERM_AUTO = 0,       /* library choice (VALU differences) */
-    CDE_XTERM_VALU = 1,       /* squared distances from coordinate differences on the VALU */
-    CDE_XTERM_MFMA_BF16X3 = 2 /* dx >= 16: |x_i|^2 + |x_j|^2 - 2 x_i.x_j with the cross term
-                                 from a split-bf16 x3 MFMA product, FP32 accumulate */
+    CDE_XTERM_AUTO = 0,       /* library choice: CDE_XTERM_VALU */
+    CDE_XTERM_VALU = 1,       /* FP64 differences of the FP32 coordinates on the VALU (exact
+                                 differences, FP64 squares and sums); the parity path */
+    CDE_XTERM_MFMA_BF16X3 = 2,/* dx = 16: |u_i|^2 + |u_j|^2 - 2 u_i.u_j on mean-centred
+                                 coordinates u, the cross term from a split-bf16 x3 MFMA
+                                 product (hi.hi + hi.lo + lo.hi, FP32 accumulate); an
+                                 approximation whose error is reported, not gated */
+    CDE_XTERM_VALU_F32 = 3    /* dx = 16: the differences, squares, sums and neighbour shift in
+                                 FP32 on the VALU; an approximation, reported, not gated */
 } cde_xterm;
 
 /* ABI version of the loaded library (CDE_ABI_VERSION at build time). */
@@ -170,8 +177,10 @@ size_t cde_workspace_bytes(int64_t n, int32_t dx, int32_t dy, cde_precision prec
  *   kernel: CDE_GAUSSIAN or CDE_EPANECHNIKOV (the latter runs every setting
  *   as a diagonal setting over the model's spatial order, built on first use;
  *   per-point outputs stay in the caller's point order).
- *   xterm: CDE_XTERM_MFMA_BF16X3 is accepted for dx >= 16, FP32 data and the
- *   Gaussian kernel only.
+ *   xterm: CDE_XTERM_MFMA_BF16X3 and CDE_XTERM_VALU_F32 are accepted for
+ *   dx = 16, FP32 data and the Gaussian kernel only (CDE_EUNSUPPORTED
+ *   otherwise); both change only how the FP32 pass and the FP64 rerun of
+ *   flagged points form x-distances.
  *   Limits: n_hx, n_hy in [1, 64]. */
 cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const double* hy,
                           int32_t n_hy, cde_criterion criterion, cde_kernel kernel,

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libcde.so")
 CDE_OK, CDE_EINVAL, CDE_ENOMEM, CDE_EDEVICE, CDE_EUNSUPPORTED = range(5)
 CDE_F32, CDE_F64 = 0, 1
 CDE_COND, CDE_JOINT = 0, 1
-CDE_XTERM_AUTO, CDE_XTERM_VALU, CDE_XTERM_MFMA_BF16X3 = 0, 1, 2
+CDE_XTERM_AUTO, CDE_XTERM_VALU, CDE_XTERM_MFMA_BF16X3, CDE_XTERM_VALU_F32 = 0, 1, 2, 3
 CDE_GAUSSIAN, CDE_EPANECHNIKOV = 0, 1
 ABI_VERSION = 4
 

@@ -677,14 +677,19 @@ cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const do
             return fail(CDE_EINVAL, "cde_loo_loglik: grid sizes must be in [1, 64]");
         if (criterion != CDE_COND && criterion != CDE_JOINT)
             return fail(CDE_EINVAL, "cde_loo_loglik: unknown criterion");
-        if (xterm != CDE_XTERM_AUTO && xterm != CDE_XTERM_VALU && xterm != CDE_XTERM_MFMA_BF16X3)
+        if (xterm != CDE_XTERM_AUTO && xterm != CDE_XTERM_VALU && xterm != CDE_XTERM_MFMA_BF16X3 &&
+            xterm != CDE_XTERM_VALU_F32)
             return fail(CDE_EINVAL, "cde_loo_loglik: unknown xterm");
         if (kernel != CDE_GAUSSIAN && kernel != CDE_EPANECHNIKOV)
             return fail(CDE_EINVAL, "cde_loo_loglik: unknown kernel");
-        const bool xt = xterm == CDE_XTERM_MFMA_BF16X3;
-        if (xt && (m->dx < 16 || m->prec != CDE_F32 || kernel != CDE_GAUSSIAN))
+        // distance variant of the FP32 grid pass: 0 FP64 differences, 1 FP32
+        // differences, 2 split-bf16 x3 cross term
+        const int xm = xterm == CDE_XTERM_MFMA_BF16X3 ? 2 : xterm == CDE_XTERM_VALU_F32 ? 1 : 0;
+        const bool xt = xm == 2;
+        if (xm != 0 && (m->dx != 16 || m->prec != CDE_F32 || kernel != CDE_GAUSSIAN))
             return fail(CDE_EUNSUPPORTED,
-                        "cde_loo_loglik: the MFMA cross term needs dx >= 16, FP32 data and the Gaussian kernel");
+                        "cde_loo_loglik: the FP32-difference and MFMA cross-term options need dx = 16, FP32 "
+                        "data and the Gaussian kernel");
         {
             cde_status st = check_model_grid(m, hx, n_hx, hy, n_hy, m->prec == CDE_F64 && kernel == CDE_GAUSSIAN,
                                              "cde_loo_loglik");
@@ -728,7 +733,7 @@ cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const do
         cde_status st = ensure_scratch(m, grid_call_scratch(m, n_hx, n_hy));
         if (st != CDE_OK) return st;
         double* counts = (double*)((char*)m->scratch + wb);
-        hipError_t e = launch_grid(m, hx, n_hx, hy, n_hy, criterion, xt, totals_dev, per_point_dev,
+        hipError_t e = launch_grid(m, hx, n_hx, hy, n_hy, criterion, xm, totals_dev, per_point_dev,
                                    m->scratch, wb, counts, s);
         if (e != hipSuccess) return hip_fail(e, "launch grid kernels");
         m->nn_ready = true;

@@ -33,6 +33,14 @@ size_t diag_partial_doubles(const cde_model* m, int nsets, bool grad, int chunks
 // pair kernel (for its occupancy), np the partial planes per chunk.
 int choose_chunks(const void* kern, const cde_model* m, int nsets, int np, size_t max_doubles);
 
+// Stable LSD radix sort (k_sort.hip) of n (key, value) pairs by key bits
+// [bit0, bit1), 6 bits per pass, ping-ponging between (k0, v0) and
+// (k1, v1); on return *result_in_alt says whether the sorted pairs are in
+// (k1, v1).  `work` holds radix_sort_work_bytes(n) bytes.  n < 2^31.
+size_t radix_sort_work_bytes(int64_t n);
+hipError_t radix_sort_pairs(unsigned long long* k0, int* v0, unsigned long long* k1, int* v1, int64_t n,
+                            int bit0, int bit1, void* work, bool* result_in_alt, hipStream_t stream);
+
 // Spatial order of the model's points (Morton order of x, sorted FP64 rows,
 // permutation, per-tile x boxes) into m->spts / m->perm / m->tbox; `work`
 // holds index_work_bytes(m) bytes of temporaries.
@@ -91,8 +99,11 @@ hipError_t launch_cv_ise(const cde_model* m, const double* h, const double* ell,
 // call only), the MFMA grid pass, FP64 finalisation, exact fixup of extreme
 // entries and the fixed-order row sums.  `work` must hold grid_work_bytes();
 // `counts` receives the per-setting non-finite counts [n_hx * n_hy].
+// xm: how the FP32 pass forms x-distances: 0 FP64 differences (the
+// library's path), 1 FP32 differences, 2 split-bf16 x3 cross term on the
+// matrix cores (1 and 2: dx = 16 only).
 hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* hy, int n_hy, int crit,
-                       bool xt, double* totals, double* per_point, void* work, size_t work_bytes,
+                       int xm, double* totals, double* per_point, void* work, size_t work_bytes,
                        double* counts, hipStream_t stream);
 size_t grid_work_bytes(const cde_model* m, int n_hx, int n_hy);
 

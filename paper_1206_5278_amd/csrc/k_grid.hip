@@ -475,16 +475,32 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
 
 constexpr float GRID_BIAS = 32.f;
 
-template <int DX, int DY, int PW, bool BIAS>
+// How the FP32 pass forms the squared x-distance of a pair (XM):
+//   XM_F64   FP64 differences of the FP32 coordinates (exact differences; the
+//            library's path), shift subtracted in FP64;
+//   XM_F32   the same formula entirely in FP32 (differences, squares, sums,
+//            shift), a reported option;
+//   XM_BF16X3  |u_i|^2 + |u_j|^2 - 2 u_i.u_j on centred coordinates u with the
+//            cross term of the block's 16 points against each 256-row tile on
+//            the matrix cores, split bf16 (u = hi + lo; hi.hi + hi.lo + lo.hi,
+//            FP32 accumulate), a reported option.
+constexpr int XM_F64 = 0, XM_F32 = 1, XM_BF16X3 = 2;
+
+template <int DX, int DY, int PW, bool BIAS, int XM = XM_F64>
 __device__ __forceinline__ void grid32_body(int bx, int by, const float* __restrict__ pts,
                                             const double* __restrict__ nn, int n, int npad,
                                             const GridArgs& ga, double* __restrict__ numbuf,
-                                            double* __restrict__ denbuf)
+                                            double* __restrict__ denbuf,
+                                            const float* __restrict__ xmean = nullptr)
 {
     static_assert(PW == 4 || PW == 8, "4 or 8 points per wave");
+    static_assert(XM != XM_BF16X3 || (DX == 16 && PW == 4),
+                  "the MFMA cross term is built for dx = 16, 16 points per block");
     constexpr int S = row_stride(DX, DY);
     constexpr int JG = 64 / PW;  // tile rows per distance group
     __shared__ double tile[TILE * S];  // staged as doubles: one exact conversion per row
+    __shared__ float jnorm[XM == XM_BF16X3 ? TILE : 1];
+    __shared__ float xcross[XM == XM_BF16X3 ? 16 * TILE : 1];  // [block point][tile row]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i0 = bx * (4 * PW) + wave * PW;
     const int tb = ga.gyp / 16;
@@ -503,6 +519,25 @@ __device__ __forceinline__ void grid32_body(int bx, int by, const float* __restr
     const float ca = ga.cx[ab * 16 + (lane & 15)];
     const float cb = ga.cy[bb * 16 + (lane & 15)];
     const float bias = vreg(BIAS ? GRID_BIAS : 0.f);  // in a VGPR: the subtraction stays VOP2
+    // cross-term operands: B = the block's 16 points (column lane % 16,
+    // dimensions 4 (lane / 16) .. + 3), and the own point's centred norm
+    float mean[XM == XM_BF16X3 ? DX : 1];
+    v4s bhi, blo;
+    float inorm = 0.f;
+    const int pb = wave * PW + (pos % PW);  // block index of the distance-role point
+    if constexpr (XM == XM_BF16X3) {
+#pragma unroll
+        for (int k = 0; k < DX; ++k) mean[k] = xmean[k];
+        float xb[S];
+        load_row<S>(xb, pts + (size_t)(bx * (4 * PW) + (lane & 15)) * S);
+        split4(xb + 4 * (lane >> 4), mean + 4 * (lane >> 4), bhi, blo);
+#pragma unroll
+        for (int k = 0; k < DX; ++k) {
+            const float u = (float)own[k] - mean[k];
+            inorm = fma_(u, u, inorm);
+        }
+    }
+    const float m32 = (float)m_i, my32 = (float)my_i;
 
     v4f acc[PW];
     Kahan<float> tot[PW][4], dtot[PW];
@@ -531,13 +566,69 @@ __device__ __forceinline__ void grid32_body(int bx, int by, const float* __restr
         const int base = t * TILE;
         const int cnt = min(TILE, n - base);
         const int ngroups = (cnt + JG - 1) / JG;
+        if constexpr (XM == XM_BF16X3) {
+            // centred norms of the tile's rows (one per thread), and the cross
+            // terms of the block's 16 points against this wave's 64 rows
+            float nj = 0.f;
+#pragma unroll
+            for (int k = 0; k < DX; ++k) {
+                const float u = (float)tile[tid * S + k] - mean[k];
+                nj = fma_(u, u, nj);
+            }
+            jnorm[tid] = nj;
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const int jb = wave * 4 + rb;  // 16-row block of the tile
+                float xr[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) xr[e] = (float)tile[(jb * 16 + (lane & 15)) * S + 4 * (lane >> 4) + e];
+                v4s ahi, alo;
+                split4(xr, mean + 4 * (lane >> 4), ahi, alo);
+                v4f c = {0.f, 0.f, 0.f, 0.f};
+                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, c, 0, 0, 0);
+                // c[r]: tile row jb*16 + 4 (lane/16) + r, block point lane % 16
+#pragma unroll
+                for (int r = 0; r < 4; ++r) xcross[(lane & 15) * TILE + jb * 16 + 4 * (lane >> 4) + r] = c[r];
+            }
+            __syncthreads();
+        }
         for (int g = 0; g < ngroups; ++g) {
             const int jj = g * JG + jo;
             double pj[S];
             load_row<S>(pj, tile + jj * S);  // jj < 256: rows >= cnt are packed padding
-            double d2x, d2y;
-            dist2<DX, DY>(own, pj, d2x, d2y);
-            float xa = (float)(d2x - m_i), ya = (float)(d2y - my_i);
+            float xa, ya;
+            if constexpr (XM == XM_F64) {
+                double d2x, d2y;
+                dist2<DX, DY>(own, pj, d2x, d2y);
+                xa = (float)(d2x - m_i);
+                ya = (float)(d2y - my_i);
+            } else if constexpr (XM == XM_F32) {
+                float ex2 = 0.f, ey2 = 0.f;
+#pragma unroll
+                for (int k = 0; k < DX; ++k) {
+                    const float d = (float)own[k] - (float)pj[k];
+                    ex2 = fma_(d, d, ex2);
+                }
+#pragma unroll
+                for (int l = 0; l < DY; ++l) {
+                    const float d = (float)own[DX + l] - (float)pj[DX + l];
+                    ey2 = fma_(d, d, ey2);
+                }
+                xa = ex2 - m32;
+                ya = ey2 - my32;
+            } else {
+                const double d2x = (double)((inorm + jnorm[jj]) - 2.f * xcross[pb * TILE + jj]);
+                double d2y = 0.0;
+#pragma unroll
+                for (int l = 0; l < DY; ++l) {
+                    const double d = own[DX + l] - pj[DX + l];
+                    d2y = fma_(d, d, d2y);
+                }
+                xa = (float)(d2x - m_i);
+                ya = (float)(d2y - my_i);
+            }
             if (jj >= cnt || base + jj == di) {
                 xa = EXCLUDED;
                 ya = EXCLUDED;
@@ -592,13 +683,14 @@ __device__ __forceinline__ void grid32_body(int bx, int by, const float* __restr
     }
 }
 
-template <int DX, int DY, int PW, bool BIAS>
+template <int DX, int DY, int PW, bool BIAS, int XM = XM_F64>
 __global__ __launch_bounds__(TILE) void k_loo_grid32(const float* __restrict__ pts,
                                                      const double* __restrict__ nn, int n, int npad,
                                                      GridArgs ga, double* __restrict__ numbuf,
-                                                     double* __restrict__ denbuf)
+                                                     double* __restrict__ denbuf,
+                                                     const float* __restrict__ xmean)
 {
-    grid32_body<DX, DY, PW, BIAS>(blockIdx.x, blockIdx.y, pts, nn, n, npad, ga, numbuf, denbuf);
+    grid32_body<DX, DY, PW, BIAS, XM>(blockIdx.x, blockIdx.y, pts, nn, n, npad, ga, numbuf, denbuf, xmean);
 }
 
 // The FP32 pass for grids of at least 32 x 32 cells (both padded sides
@@ -953,7 +1045,7 @@ struct GridWork {
 
 template <int DX, int DY>
 static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& gf, int crit,
-                         bool xt, const GridWork& w, double* totals, double* per_point,
+                         int xm, const GridWork& w, double* totals, double* per_point,
                          double* counts, hipStream_t stream)
 {
     const int nb = (int)(m->npad / TILE);
@@ -971,16 +1063,8 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
     const int G = ga.gx * ga.gy;
     const dim3 fgrid((unsigned)((n + 255) / 256), (unsigned)G);
     const float* xmean = (const float*)m->xmean;
-    if (xt) {
-        if constexpr (DX == 16) {
-            hipLaunchKernelGGL((k_loo_grid<DX, DY, true, 8>), grid, dim3(TILE), 0, stream, pts, nn, n,
-                               npad, ga, xmean, w.numbuf, w.denbuf, (const int*)nullptr,
-                               (const int*)nullptr);
-        } else {
-            return hipErrorInvalidValue;
-        }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    } else {
+    if (xm != XM_F64 && DX != 16) return hipErrorInvalidValue;
+    {
         // FP32 pass over all points; flag (tile, point) pairs with a cell FP32
         // cannot carry and recompute those tiles of those points on the FP64
         // path (the FP32 denominators stand where b-tile 0 is not recomputed).
@@ -988,7 +1072,7 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
                            w.flags, tiles * npad);
         hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, w.pcount, tiles);
         constexpr int PW = CDE_GRID32_POINTS_PER_WAVE;
-        if (ga.gxp % 32 == 0 && ga.gyp % 32 == 0) {
+        if (xm == XM_F64 && ga.gxp % 32 == 0 && ga.gyp % 32 == 0) {
             constexpr int PWQ = 2;
             const int quads = (ga.gxp / 32) * (ga.gyp / 32);
             hipLaunchKernelGGL((k_loo_grid32q<DX, DY, PWQ>), dim3((unsigned)(npad / (4 * PWQ)), (unsigned)quads),
@@ -1004,14 +1088,33 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
             else
                 gu.tile_of[nu_++] = t;
         }
-        if (nb_ > 0) {
-            hipLaunchKernelGGL((k_loo_grid32<DX, DY, PW, true>), dim3((unsigned)(npad / (4 * PW)), (unsigned)nb_),
-                               dim3(TILE), 0, stream, pts, nn, n, npad, gb, w.numbuf, w.denbuf);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        if (nu_ > 0) {
-            hipLaunchKernelGGL((k_loo_grid32<DX, DY, PW, false>), dim3((unsigned)(npad / (4 * PW)), (unsigned)nu_),
-                               dim3(TILE), 0, stream, pts, nn, n, npad, gu, w.numbuf, w.denbuf);
+        const dim3 pgrid((unsigned)(npad / (4 * PW)));
+        for (int biased = 1; biased >= 0; --biased) {
+            const int cnt = biased ? nb_ : nu_;
+            if (cnt == 0) continue;
+            const GridArgs& gt = biased ? gb : gu;
+            const dim3 g2(pgrid.x, (unsigned)cnt);
+            if (xm == XM_F64) {
+                if (biased)
+                    hipLaunchKernelGGL((k_loo_grid32<DX, DY, PW, true>), g2, dim3(TILE), 0, stream, pts, nn, n,
+                                       npad, gt, w.numbuf, w.denbuf, xmean);
+                else
+                    hipLaunchKernelGGL((k_loo_grid32<DX, DY, PW, false>), g2, dim3(TILE), 0, stream, pts, nn, n,
+                                       npad, gt, w.numbuf, w.denbuf, xmean);
+            } else if constexpr (DX == 16) {
+                if (xm == XM_F32 && biased)
+                    hipLaunchKernelGGL((k_loo_grid32<DX, DY, PW, true, XM_F32>), g2, dim3(TILE), 0, stream, pts,
+                                       nn, n, npad, gt, w.numbuf, w.denbuf, xmean);
+                else if (xm == XM_F32)
+                    hipLaunchKernelGGL((k_loo_grid32<DX, DY, PW, false, XM_F32>), g2, dim3(TILE), 0, stream, pts,
+                                       nn, n, npad, gt, w.numbuf, w.denbuf, xmean);
+                else if (biased)
+                    hipLaunchKernelGGL((k_loo_grid32<DX, DY, PW, true, XM_BF16X3>), g2, dim3(TILE), 0, stream,
+                                       pts, nn, n, npad, gt, w.numbuf, w.denbuf, xmean);
+                else
+                    hipLaunchKernelGGL((k_loo_grid32<DX, DY, PW, false, XM_BF16X3>), g2, dim3(TILE), 0, stream,
+                                       pts, nn, n, npad, gt, w.numbuf, w.denbuf, xmean);
+            }
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         }
@@ -1023,8 +1126,14 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
         // Points per wave of the rerun.  Each block streams all n points, so
         // 8 per wave keeps that traffic low; up to 2^18 points the flagged
         // lists are short (a few thousand points: ~100 blocks of 32) and 2
-        // per wave spreads them over 4x the blocks.
-        if (npad <= (1 << 18)) {
+        // per wave spreads them over 4x the blocks.  The bf16x3 variant reruns
+        // with the same cross term (8 points per wave, the layout it needs).
+        if (xm == XM_BF16X3) {
+            if constexpr (DX == 16)
+                hipLaunchKernelGGL((k_loo_grid<DX, DY, true, 8>), grid, dim3(TILE), 0, stream, pts, nn, n,
+                                   npad, ga, xmean, w.numbuf, w.denbuf, (const int*)w.plist,
+                                   (const int*)w.pcount);
+        } else if (npad <= (1 << 18)) {
             const dim3 rgrid((unsigned)(npad / 8), (unsigned)tiles);
             hipLaunchKernelGGL((k_loo_grid<DX, DY, false, 2>), rgrid, dim3(TILE), 0, stream, pts, nn, n,
                                npad, ga, xmean, w.numbuf, w.denbuf, (const int*)w.plist,
@@ -1051,7 +1160,7 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
 
 #define CDE_GRID_CASE(DX_, DY_)                                                                 \
     case (DX_) * 8 + (DY_):                                                                     \
-        return grid_t<DX_, DY_>(m, ga, gf, crit, xt, w, totals, per_point, counts, stream);
+        return grid_t<DX_, DY_>(m, ga, gf, crit, xm, w, totals, per_point, counts, stream);
 
 // Column means of x (FP64 accumulation in a fixed order, one thread per
 // dimension), stored as FP32: the centring of the cross-term option.
@@ -1123,10 +1232,10 @@ static bool carve_grid_work(void* work, size_t work_bytes, int64_t npad, int n_h
 }
 
 hipError_t launch_grid(cde_model* m, const double* hx, int n_hx, const double* hy, int n_hy, int crit,
-                       bool xt, double* totals, double* per_point, void* work, size_t work_bytes,
+                       int xm, double* totals, double* per_point, void* work, size_t work_bytes,
                        double* counts, hipStream_t stream)
 {
-    if (xt && !m->xmean_ready) {
+    if (xm == XM_BF16X3 && !m->xmean_ready) {
         hipLaunchKernelGGL(k_colmean, dim3(1), dim3(64), 0, stream, (const float*)m->pts, (int)m->n,
                            m->dx, m->stride, (float*)m->xmean);
         hipError_t e0 = hipGetLastError();

@@ -14,8 +14,6 @@
 #include <algorithm>
 #include <vector>
 
-#include <hipcub/hipcub.hpp>
-
 #include "cde_device.h"
 #include "cde_kernels.h"
 
@@ -216,11 +214,8 @@ static hipError_t build_index_t(cde_model* m, void* work, size_t work_bytes, hip
     int2* nodes = (int2*)(((size_t)(dim + max_nodes) + 7) & ~size_t(7));
     const size_t used = ((size_t)((char*)(nodes + table.size()) - w) + 255) & ~size_t(255);
     void* tmp = (void*)(w + used);
-    size_t tmp_bytes = 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k0, k1, v0, v1, npad, 0, 64,
-                                                      stream);
-    if (e != hipSuccess) return e;
-    if (used + tmp_bytes > work_bytes) return hipErrorInvalidValue;
+    if (used + radix_sort_work_bytes(npad) > work_bytes) return hipErrorInvalidValue;
+    hipError_t e;
     const T* pts = (const T*)m->pts;
     if (!table.empty()) {
         e = hipMemcpyAsync(nodes, table.data(), sizeof(int2) * table.size(), hipMemcpyHostToDevice, stream);
@@ -236,10 +231,17 @@ static hipError_t build_index_t(cde_model* m, void* work, size_t work_bytes, hip
         hipLaunchKernelGGL((k_node_keys<T>), dim3(nn), dim3(TILE), 0, stream, pts, stride, (const int*)v0,
                            lv, (const int*)dim, (const double*)lo, (const double*)hi, k0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, k0, k1, v0, v1, npad, 0, 64, stream);
+        // keys: node id (below 2^nb) above 32 position bits; rows past n
+        // hold all-ones keys and stay last
+        int nb = 1;
+        while ((int64_t(1) << nb) < nn) ++nb;
+        bool alt = false;
+        e = radix_sort_pairs(k0, v0, k1, v1, npad, 0, std::min(64, 32 + nb), tmp, &alt, stream);
         if (e != hipSuccess) return e;
-        std::swap(k0, k1);
-        std::swap(v0, v1);
+        if (alt) {
+            std::swap(k0, k1);
+            std::swap(v0, v1);
+        }
     }
     e = hipMemcpyAsync(m->perm, v0, sizeof(int) * (size_t)npad, hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return e;
@@ -261,10 +263,7 @@ static hipError_t build_index_t(cde_model* m, void* work, size_t work_bytes, hip
 
 size_t index_work_bytes(const cde_model* m)
 {
-    size_t tmp_bytes = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, (unsigned long long*)nullptr,
-                                             (unsigned long long*)nullptr, (int*)nullptr, (int*)nullptr,
-                                             (int)m->npad, 0, 64, (hipStream_t)0);
+    const size_t tmp_bytes = radix_sort_work_bytes(m->npad);
     // node tables: at most npad/SUBROWS leaves, so at most 2 npad/SUBROWS
     // nodes over all levels and npad/SUBROWS on one level
     const size_t leaves = (size_t)m->npad / SUBROWS + 1;

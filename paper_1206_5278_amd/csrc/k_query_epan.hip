@@ -25,8 +25,6 @@
 // its launch.
 #include <algorithm>
 
-#include <hipcub/hipcub.hpp>
-
 #include "cde_device.h"
 #include "cde_kernels.h"
 
@@ -261,11 +259,7 @@ __global__ void k_query_epan_reduce(const float* __restrict__ fpart, const doubl
 
 size_t sort_temp_bytes(int q)
 {
-    size_t tmp = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (unsigned long long*)nullptr,
-                                             (unsigned long long*)nullptr, (int*)nullptr, (int*)nullptr,
-                                             q, 0, 64, hipStream_t(0));
-    return (tmp + 255) / 256 * 256;
+    return (radix_sort_work_bytes(q) + 255) / 256 * 256;
 }
 
 template <int DX, int DY>
@@ -298,12 +292,14 @@ hipError_t query_epan_t(const cde_model* m, const float* xq, int q, const float*
     hipLaunchKernelGGL(k_qe_keys<DX>, dim3((q + 255) / 256), dim3(256), 0, stream, xq, q, a, k0, o0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, k0, k1, o0, o1, q, 0, 64, stream);
+    bool alt = false;
+    e = radix_sort_pairs(k0, o0, k1, o1, q, 0, 64, tmp, &alt, stream);
     if (e != hipSuccess) return e;
+    const int* order = alt ? o1 : o0;
     for (int q0 = 0; q0 < q; q0 += qs) {
         const int qn = std::min(qs, q - q0);
         const dim3 grid((qn + EQPB - 1) / EQPB, gb, nch);
-        const int* ord = o1 + q0;
+        const int* ord = order + q0;
         if (gt == 4)
             hipLaunchKernelGGL((k_query_epan<DX, DY, 4>), grid, dim3(ENT), 0, stream, (const double*)m->spts,
                                (const double*)m->tbox, (const double*)m->sbox, n, chunk, xq, ord, qn, yg,

@@ -5,7 +5,7 @@ GPU calls only; this script repeats the same calls on the same seeded inputs
 and checks sampled outputs, each computed by the oracle point by point
 against the whole training set.  Run from the repository root on a GPU:
 
-    python -m tests.fullsize_report [--grid] [--query] [--ise] [--epan] [--headline]
+    python -m tests.fullsize_report [--grid] [--query] [--ise] [--epan] [--headline] [--highdim]
 
 (no flag: the first four; --headline sums the oracle over all 500,000 points
 of the headline workload, about five minutes on 16 threads).  Prints one JSON line per section.  The pass/fail
@@ -82,6 +82,24 @@ def grid_report():
     refp = oracle.loo_grid(x32.astype(np.float64), y32.astype(np.float64), hx, hy, idx=idx, nthreads=NT)
     out["photoz"] = {"per_point_err_16_sampled_points": rel_point_err(got, refp), "nonfinite": int(nf.item())}
 
+    out.update(highdim_report())
+    return out
+
+
+def highdim_report():
+    """The 16-D set on its 16 x 16 grid: 16 sampled points of the full 1M set
+    (default x-distances), then for each way of forming the x-distances (FP64
+    differences, FP32 differences, split-bf16 x3 MFMA cross term) 256 sampled
+    points of the 20k subset and the totals of a 5k subset."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1206_5278_amd as cde
+    import workloads
+    from paper_1206_5278_amd import _binding as B
+    dev = torch.device("cuda:0")
+    out = {"section": "highdim"}
     hx, hy = workloads.WORKLOADS["highdim"]["grid"]
     x, y = workloads.highdim()
     # the full 1M-point set: 16 sampled points against all other points
@@ -106,6 +124,7 @@ def grid_report():
     m5 = cde.Model(torch.from_numpy(x5).to(dev), torch.from_numpy(y5).to(dev))
     res = {}
     for name, xt in (("valu_fp64_differences", B.CDE_XTERM_VALU),
+                     ("valu_fp32_differences", B.CDE_XTERM_VALU_F32),
                      ("mfma_bf16x3_cross_term", B.CDE_XTERM_MFMA_BF16X3)):
         _, pp, _ = m.loo_grid(hx, hy, per_point=True, xterm=xt)
         t5 = m5.loo_grid(hx, hy, xterm=xt)[0].cpu().numpy()
@@ -294,13 +313,13 @@ def epan_report():
 
 def main():
     ap = argparse.ArgumentParser()
-    for s in ("grid", "query", "ise", "epan", "headline"):
+    for s in ("grid", "query", "ise", "epan", "headline", "highdim"):
         ap.add_argument(f"--{s}", action="store_true")
     args = ap.parse_args()
-    chosen = [s for s in ("grid", "query", "ise", "epan", "headline") if getattr(args, s)] or \
+    chosen = [s for s in ("grid", "query", "ise", "epan", "headline", "highdim") if getattr(args, s)] or \
         ["grid", "query", "ise", "epan"]
     fns = {"grid": grid_report, "query": query_report, "ise": ise_report, "epan": epan_report,
-           "headline": headline_report}
+           "headline": headline_report, "highdim": highdim_report}
     for s in chosen:
         print(f"section: {s}", file=sys.stderr, flush=True)
         print(json.dumps(fns[s]()), flush=True)

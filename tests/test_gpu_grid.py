@@ -141,17 +141,21 @@ def test_grid_highdim_subset_16x16():
     assert int(np.argmax(tot)) == int(np.argmax(oracle.totals(ref)))
 
 
-def test_grid_mfma_bf16x3_cross_term_reported():
-    # dx = 16 cross term on the matrix cores (split-bf16 x3): an approximation
-    # whose error is reported; the check here is a sanity bound plus the
-    # exact VALU path on the same model.
-    print("case: highdim subset n=2000 16x16 grid, bf16x3 cross term", flush=True)
+@pytest.mark.parametrize("variant", ["valu_fp32", "mfma_bf16x3"])
+def test_grid_distance_variants_reported(variant):
+    # dx = 16 options that form x-distances approximately (FP32 differences,
+    # or a split-bf16 x3 cross term on the matrix cores) in the same pass
+    # structure as the default: their error against the oracle is reported,
+    # and gated here at the bound measured on this subset; the exact default
+    # path on the same model is checked at the parity tolerance.
+    print(f"case: highdim subset n=2000 16x16 grid, x-distance variant {variant}", flush=True)
     x, y = workloads.highdim(2000, seed=6)
     hx, hy = workloads.WORKLOADS["highdim"]["grid"]
     xo, yo, xd, yd = P.f32_pair(x, y)
     m = cde().Model(xd, yd)
     from paper_1206_5278_amd import _binding as B
-    tot_x, pp_x, nf = m.loo_grid(hx, hy, per_point=True, xterm=B.CDE_XTERM_MFMA_BF16X3)
+    xt = {"valu_fp32": B.CDE_XTERM_VALU_F32, "mfma_bf16x3": B.CDE_XTERM_MFMA_BF16X3}[variant]
+    tot_x, pp_x, nf = m.loo_grid(hx, hy, per_point=True, xterm=xt)
     tot_v, pp_v, _ = m.loo_grid(hx, hy, per_point=True)
     ref = oracle.loo_grid(xo, yo, hx, hy, nthreads=NT)
     P.assert_points(pp_v.cpu().numpy(), ref)  # exact path unchanged
@@ -160,9 +164,10 @@ def test_grid_mfma_bf16x3_cross_term_reported():
     err = np.abs(ex - ref) / np.maximum(1.0, np.abs(ref))
     rt = oracle.totals(ref)
     terr = np.abs(tot_x.cpu().numpy() - rt) / np.abs(rt)
-    print(f"bf16x3 cross term: per-point rel err max {err.max():.3e} median {np.median(err):.3e}; "
-          f"total rel err max {terr.max():.3e} (largest hx: {terr.reshape(16, 16)[-1].max():.3e})",
-          flush=True)
+    print(f"{variant}: per-point rel err max {err.max():.3e} median {np.median(err):.3e}; "
+          f"total rel err max {terr.max():.3e} median {np.median(terr):.3e}", flush=True)
     assert np.all(np.isfinite(ex))
-    # at the widest bandwidth the approximation is tight
-    assert terr.reshape(16, 16)[-1, -1] < 1e-3
+    # measured on this subset: FP32 differences 3.8e-5 per point, 5.5e-8 on
+    # totals; bf16 x3 cross term 7.5e-3 and 3.6e-6; bounds at about 2x
+    bound = {"valu_fp32": (1e-4, 2e-7), "mfma_bf16x3": (2e-2, 1e-5)}[variant]  # (per point, total)
+    assert err.max() <= bound[0] and terr.max() <= bound[1]
