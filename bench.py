@@ -64,6 +64,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=50.0,
+                    help="arrival rate of the short serving stream (0: skip it)")
+    ap.add_argument("--serve-duration", type=float, default=10.0,
+                    help="seconds of arrivals of the short serving stream")
     ap.add_argument("--trace-steps", type=int, default=0,
                     help="after the timed steps, run this many untimed ascent steps from the "
                          "normal-reference start and report the whole trace of S")
@@ -121,6 +125,45 @@ def cpu_baseline(x64, y64, h, target_s):
                       f"(single-setting FP64 oracle, {threads} threads = the cores this process may "
                       f"use (nproc {nproc}, OMP_NUM_THREADS {os.environ.get('OMP_NUM_THREADS', 'unset')}), "
                       f"{dt:.2f} s wall)"}
+
+
+def serve_secondary(rate, duration):
+    """The metric's serving half on a short seeded stream: the same requests
+    through the one-request-per-launch server and the continuous-batching
+    server (grouped job launches, fused query launches); p50/p99 latency,
+    throughput and whether every result is bit-identical between the two.
+    Stream: Poisson arrivals, 70% density queries (1..4096 points, 256-point
+    y grid, with conditional mean and summaries) against 8 resident sets, 30%
+    16 x 16 bandwidth-selection jobs with n log-uniform in [1k, 200k]."""
+    import copy
+
+    import bench_serve
+    import workloads
+    from paper_1206_5278_amd.serve import GpuExecutor
+
+    sets = workloads.resident_sets(8, seed=0)
+    reqs = bench_serve.build_requests(workloads.serve_stream(rate=rate, duration=duration, seed=5), sets,
+                                      seed=5)
+    ex = GpuExecutor(sets)
+    budget = 96 << 30
+    bench_serve.run_mode(ex, copy.deepcopy(reqs[:4]), True, budget, 60.0)  # warm-up
+    out = {"rate_req_s": rate, "duration_s": duration, "requests": len(reqs),
+           "jobs": sum(r.kind == "job" for r in reqs)}
+    results = {}
+    for mode, batched in (("plain", False), ("batched", True)):
+        rep, results[mode] = bench_serve.run_mode(ex, copy.deepcopy(reqs), batched, budget, 300.0)
+        out[mode] = {k: rep[k] for k in ("throughput_req_s", "p50_s", "p99_s", "makespan_s", "completed",
+                                         "failed", "unfinished")}
+        out[mode]["job_p99_s"] = rep["job"]["p99_s"]
+        out[mode]["query_p99_s"] = rep["query"]["p99_s"]
+        print(f"bench: serving stream, {mode} mode done", file=sys.stderr, flush=True)
+    common = set(results["plain"]) & set(results["batched"])
+    out["results_identical_alone_vs_mixed"] = all(results["plain"][k] == results["batched"][k]
+                                                  for k in common)
+    out["compared"] = len(common)
+    for st in ex.sets:
+        st["model"].close()
+    return out
 
 
 def main():
@@ -222,6 +265,10 @@ def main():
                      "wall_s": time.perf_counter() - t0}
         print(f"bench: ascent trace of {args.trace_steps} steps done", file=sys.stderr, flush=True)
 
+    serve = None
+    if args.serve_rate > 0:
+        serve = serve_secondary(args.serve_rate, args.serve_duration)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(x32.astype(np.float64), y32.astype(np.float64), h0.tolist(),
@@ -238,7 +285,8 @@ def main():
                    "accumulation": "FP32 kernel values and 32-pair subtile sums, FP64 per-point totals, FP64 log/reduce"},
         "roofline": roofline, "cpu_baseline": cpu,
         "trace_first_last": [trace[0], trace[-1]] if trace else None,
-        "secondary": {"value_only_ms": vo_ms, "value_only_pair_evals_per_s": pairs / (vo_ms * 1e-3)},
+        "secondary": {"value_only_ms": vo_ms, "value_only_pair_evals_per_s": pairs / (vo_ms * 1e-3),
+                      "serve": serve},
     }
     if trace_run is not None:
         out["ascent"] = trace_run

@@ -104,9 +104,10 @@ def main():
     ap.add_argument("--n-cap", type=int, default=None, help="cap job sizes (smoke runs)")
     ap.add_argument("--budget-gb", type=float, default=96.0)
     ap.add_argument("--deadline", type=float, default=600.0)
+    ap.add_argument("--no-main", action="store_true", help="run the sweep only")
     ap.add_argument("--sweep", type=str, default="",
                     help="comma-separated extra arrival rates, each run for --sweep-duration")
-    ap.add_argument("--sweep-duration", type=float, default=4.0)
+    ap.add_argument("--sweep-duration", type=float, default=60.0)
     ap.add_argument("--progress", type=float, default=30.0,
                     help="seconds between status lines on stderr (0: none)")
     args = ap.parse_args()
@@ -115,45 +116,55 @@ def main():
     from paper_1206_5278_amd.serve import GpuExecutor
 
     sets = workloads.resident_sets(8, seed=args.seed)
-    stream = workloads.serve_stream(rate=args.rate, duration=args.duration, seed=args.seed)
+    stream = workloads.serve_stream(rate=args.rate, duration=args.duration if not args.no_main else 0.5,
+                                    seed=args.seed)
     reqs = build_requests(stream, sets, seed=args.seed, n_cap=args.n_cap)
     ex = GpuExecutor(sets)
     budget = int(args.budget_gb * (1 << 30))
     # warm-up: one small job and one query through every code path
     run_mode(ex, copy.deepcopy(reqs[:4]), True, budget, 60.0)
 
-    res = {}
-    results = {}
-    for mode, batched in (("plain", False), ("batched", True)):
-        rep, out = run_mode(ex, copy.deepcopy(reqs), batched, budget, args.deadline,
-                            progress=args.progress or None)
-        res[mode] = rep
-        results[mode] = out
-        print(f"{mode}: {json.dumps(rep)}", file=sys.stderr, flush=True)
-    common = set(results["plain"]) & set(results["batched"])
-    identical = all(same(results["plain"][k], results["batched"][k]) for k in common)
-    n_jobs = sum(1 for r in reqs if r.kind == "job")
-    offered = sum(job_pairs(r) for r in reqs if r.kind == "job") / args.duration
-    out = {
-        "metric": "serving throughput and p50/p99 latency, continuous batching vs one request per launch",
-        "rate_req_s": args.rate, "duration_s": args.duration, "requests": len(reqs), "jobs": n_jobs,
-        "queries": len(reqs) - n_jobs, "offered_job_pair_evals_per_s": offered,
-        "plain": res["plain"], "batched": res["batched"],
-        "throughput_ratio": res["batched"]["throughput_req_s"] / max(res["plain"]["throughput_req_s"], 1e-9),
-        "results_identical_alone_vs_mixed": identical, "compared": len(common),
-        "data": "synthetic", "dtype": "f32 kernel values, f64 accumulation",
-    }
+    out = {"metric": "serving throughput and p50/p99 latency, continuous batching vs one request per launch",
+           "data": "synthetic", "dtype": "f32 kernel values, f64 accumulation"}
+    if not args.no_main:
+        res = {}
+        results = {}
+        for mode, batched in (("plain", False), ("batched", True)):
+            rep, o = run_mode(ex, copy.deepcopy(reqs), batched, budget, args.deadline,
+                              progress=args.progress or None)
+            res[mode] = rep
+            results[mode] = o
+            print(f"{mode}: {json.dumps(rep)}", file=sys.stderr, flush=True)
+        common = set(results["plain"]) & set(results["batched"])
+        identical = all(same(results["plain"][k], results["batched"][k]) for k in common)
+        n_jobs = sum(1 for r in reqs if r.kind == "job")
+        offered = sum(job_pairs(r) for r in reqs if r.kind == "job") / args.duration
+        out.update({
+            "rate_req_s": args.rate, "duration_s": args.duration, "requests": len(reqs), "jobs": n_jobs,
+            "queries": len(reqs) - n_jobs, "offered_job_pair_evals_per_s": offered,
+            "plain": res["plain"], "batched": res["batched"],
+            "throughput_ratio": res["batched"]["throughput_req_s"] / max(res["plain"]["throughput_req_s"], 1e-9),
+            "results_identical_alone_vs_mixed": identical, "compared": len(common)})
     if args.sweep:
         sweep = []
         for rate in [float(v) for v in args.sweep.split(",") if v]:
             st = workloads.serve_stream(rate=rate, duration=args.sweep_duration, seed=args.seed + 1)
             rq = build_requests(st, sets, seed=args.seed + 1, n_cap=args.n_cap)
-            row = {"rate_req_s": rate, "requests": len(rq)}
+            row = {"rate_req_s": rate, "requests": len(rq), "duration_s": args.sweep_duration}
+            outs = {}
             for mode, batched in (("plain", False), ("batched", True)):
-                rep, _ = run_mode(ex, copy.deepcopy(rq), batched, budget, args.deadline)
-                row[mode] = {k: rep[k] for k in ("throughput_req_s", "p50_s", "p99_s", "makespan_s")}
+                rep, outs[mode] = run_mode(ex, copy.deepcopy(rq), batched, budget, args.deadline,
+                                           progress=args.progress or None)
+                row[mode] = {k: rep[k] for k in ("throughput_req_s", "p50_s", "p99_s", "makespan_s",
+                                                 "completed", "failed", "unfinished")}
+                row[mode]["job_p50_s"] = rep["job"]["p50_s"]
                 row[mode]["job_p99_s"] = rep["job"]["p99_s"]
+                row[mode]["query_p50_s"] = rep["query"]["p50_s"]
                 row[mode]["query_p99_s"] = rep["query"]["p99_s"]
+            common = set(outs["plain"]) & set(outs["batched"])
+            row["results_identical_alone_vs_mixed"] = all(outs["plain"][k] == outs["batched"][k]
+                                                          for k in common)
+            row["compared"] = len(common)
             print(json.dumps(row), file=sys.stderr, flush=True)
             sweep.append(row)
         out["sweep"] = sweep

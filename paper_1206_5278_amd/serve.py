@@ -12,21 +12,30 @@ Scheduling (one scheduler thread, ``tick`` is one pass):
   1. arrivals whose time has come enter the waiting queue (FIFO);
   2. admission: requests leave the queue in order while their device-memory
      footprint fits the HBM budget and a slot is free -- requests arriving
-     while others run are admitted as slots and memory free up;
+     while others run are admitted as slots and memory free up; an admitted
+     job's data is uploaded and its model created at once;
   3. launch: admitted queries wait in a per-set ready list; whenever a
      resident set has no query launch in flight, all of its ready queries
      become ONE fused query launch (so queries that arrive while a batch runs
-     join the next batch); each admitted job is launched on the next of
-     several streams, so jobs of different sizes overlap on the device with
-     each other and with the queries;
+     join the next batch).  Jobs run in grouped launches (``cde_launch_batch``)
+     of work items, each item a range of one job's points, on two lanes:
+     small jobs (n up to 16,384) go whole, all that wait, into one launch
+     whenever the small lane is free; large jobs go in arrival order, in
+     ranges of a bounded number of pair evaluations per launch (a tick), up
+     to two ticks in flight so the device never waits for the scheduler.
+     Large jobs therefore run one after another at the device's full rate
+     (the tail of the latency distribution), while small jobs and queries run
+     beside them instead of behind them;
   4. completion: finished launches (HIP events) release their memory and
      slots; results are copied out and latencies recorded.
-The plain mode is the baseline: one request per launch, in arrival order,
-each waited for before the next starts.
+The plain mode is the baseline: one request per launch (``cde_loo_loglik``
+or one query launch), in arrival order, each waited for before the next
+starts.
 
-Each request's result is computed by the same kernels on the same inputs in
-either mode, so it is identical alone and in the mix (fused query launches
-evaluate each query row independently of the other rows).
+Each request's result is computed on the same inputs by the same per-point
+arithmetic in either mode, so it is bit-identical alone and in the mix: fused
+query launches evaluate each query row independently of the other rows, and
+the grouped launch gives each job the totals cde_loo_loglik gives it.
 """
 from __future__ import annotations
 
@@ -58,6 +67,8 @@ class ServeRequest:
     t_done: float | None = None
     result: object = None
     error: str | None = None
+    # progress of a job in grouped launches: next point to issue
+    next_point: int = 0
 
     @property
     def latency(self):
@@ -75,6 +86,25 @@ class Executor:
         raise NotImplementedError
 
     def launch_job(self, req: ServeRequest) -> object:
+        """Plain mode: the whole job as one launch."""
+        raise NotImplementedError
+
+    def job_points(self, req: ServeRequest) -> int:
+        """Number of training points of a job (its n)."""
+        return int(req.x.shape[0])
+
+    def prepare_job(self, req: ServeRequest) -> None:
+        """Batched mode, at admission: upload the job's data and create its
+        model (ordered before its first grouped launch)."""
+        raise NotImplementedError
+
+    def launch_job_tick(self, items: list, lane: str = "large") -> object:
+        """Batched mode: one grouped launch over work items (req, i0, i1) on
+        the given lane ("small": whole small jobs; "large": ranges of large
+        jobs, whose successive ranges come in order).  Launches of one lane
+        run one after another.  Items that cannot be launched are retried
+        alone; those that still fail are returned in the handle's "failed"
+        list as (req, message) and are not in flight."""
         raise NotImplementedError
 
     def done(self, handle) -> bool:
@@ -101,9 +131,25 @@ class Scheduler:
 
     def __init__(self, executor: Executor, hbm_budget: int, max_active: int = 64,
                  batched: bool = True, clock: Callable[[], float] | None = None,
-                 max_query_rows: int = 1 << 16):
+                 max_query_rows: int = 1 << 16, tick_pairs: float = 1.2e13,
+                 small_job_points: int = 16384, ticks_in_flight: int = 2,
+                 grid_cells: int = 256):
         self.ex = executor
         self.max_query_rows = int(max_query_rows)
+        # grouped job ticks: pair evaluations per tick (n_range * n * cells),
+        # the size up to which a job rides along whole, ticks kept in flight.
+        # The default tick holds a whole 200k-point 16 x 16 job: ranges cost
+        # extra device time (a 200k job: 346 ms whole, 376 ms in 78k-point
+        # ranges, 451 ms in 19.5k-point ranges; the grid pass's last round of
+        # blocks runs part-empty once per range), and small jobs and queries
+        # do not wait for large ones in any case (lanes of their own).
+        self.tick_pairs = float(tick_pairs)
+        self.small_job_points = int(small_job_points)
+        self.ticks_in_flight = int(ticks_in_flight)
+        self.grid_cells = int(grid_cells)
+        self.jobs = []          # admitted jobs with ranges still to issue (arrival order)
+        self.job_ticks = 0      # grouped launches of large-job ranges in flight
+        self.small_busy = False  # a grouped launch of small jobs is in flight
         self.ready_q = collections.OrderedDict()  # set_id -> admitted queries not launched
         self.q_busy = set()                       # sets with a query launch in flight
         self.budget = int(hbm_budget) - int(executor.resident_bytes())
@@ -152,12 +198,82 @@ class Scheduler:
             admitted.append(r)
         return admitted
 
+    def _job_cells(self, r) -> int:
+        cells = len(r.hx) * len(r.hy)
+        return cells if cells > 0 else self.grid_cells
+
+    def _is_small(self, r) -> bool:
+        return self.ex.job_points(r) <= self.small_job_points
+
+    def _plan_tick(self):
+        """Ranges of the oldest large jobs for the next grouped launch, within
+        the tick's budget of pair evaluations (range points x n x cells)."""
+        items, budget = [], self.tick_pairs
+        for r in self.jobs:
+            if self._is_small(r):
+                continue
+            n = self.ex.job_points(r)
+            per_point = float(n) * self._job_cells(r)
+            if items and budget < 256 * per_point:
+                break
+            take = max(256, int(max(budget, 0.0) / per_point) // 256 * 256)
+            i1 = min(n, r.next_point + take)
+            if n - i1 < 256:  # no sliver at the end
+                i1 = n
+            items.append((r, r.next_point, i1))
+            budget -= float(i1 - r.next_point) * per_point
+        return items
+
+    def _issue(self, items, lane):
+        """Launch `items` on `lane`; returns the handle or None, releasing
+        the jobs of items that failed."""
+        try:
+            h = self.ex.launch_job_tick(items, lane)
+            failed = {id(r): (r, msg) for r, msg in h.get("failed", [])}
+        except Exception as e:  # nothing of the launch is in flight
+            h, failed = None, {id(r): (r, str(e)) for r, _, _ in items}
+        # a failed item fails only its own job
+        self.jobs = [q for q in self.jobs if id(q) not in failed]
+        for r, msg in failed.values():
+            r.error = f"launch failed: {msg}"
+            self._release(r, self.now())
+        ok = [(r, i0, i1) for r, i0, i1 in items if id(r) not in failed]
+        for r, _, i1 in ok:
+            r.next_point = i1
+        if h is None:
+            return None
+        done = [r for r, _, i1 in ok if i1 == self.ex.job_points(r)]
+        self.jobs = [r for r in self.jobs if r.next_point < self.ex.job_points(r)]
+        self.inflight.append((h, done, "job_" + lane))
+        return h
+
+    def _launch_jobs(self):
+        if not self.small_busy:
+            small = [(r, 0, self.ex.job_points(r)) for r in self.jobs if self._is_small(r)]
+            if small and self._issue(small, "small") is not None:
+                self.small_busy = True
+        while self.job_ticks < self.ticks_in_flight:
+            items = self._plan_tick()
+            if not items:
+                break
+            if self._issue(items, "large") is not None:
+                self.job_ticks += 1
+
     def _launch(self, admitted):
         for r in admitted:
             if r.kind == "query":
                 self.ready_q.setdefault(r.set_id, []).append(r)
-            else:
+            elif not self.batched:
                 self._start(lambda r=r: self.ex.launch_job(r), [r], None)
+            else:
+                try:
+                    self.ex.prepare_job(r)
+                    self.jobs.append(r)
+                except Exception as e:
+                    r.error = f"launch failed: {e}"
+                    self._release(r, self.now())
+        if self.batched and self.jobs:
+            self._launch_jobs()
         for set_id in list(self.ready_q):
             rs = self.ready_q[set_id]
             if not self.batched:
@@ -201,7 +317,11 @@ class Scheduler:
                 except Exception as e:
                     for r in reqs:
                         r.error = f"completion failed: {e}"
-                if busy_set is not None:
+                if busy_set == "job_large":
+                    self.job_ticks -= 1
+                elif busy_set == "job_small":
+                    self.small_busy = False
+                elif busy_set is not None:
                     self.q_busy.discard(busy_set)
                 now = self.now()
                 for r in reqs:
@@ -209,7 +329,7 @@ class Scheduler:
             else:
                 still.append((h, reqs, busy_set))
         self.inflight = still
-        if not still:
+        if not still and not self.jobs:
             self.ex.idle()
 
     def tick(self) -> bool:
@@ -220,9 +340,9 @@ class Scheduler:
         if not self.batched and self.inflight:
             return True  # plain mode: one request in service at a time
         admitted = self._admit(now)
-        if admitted or self.ready_q:
+        if admitted or self.ready_q or self.jobs:
             self._launch(admitted)
-        return bool(self.pending or self.waiting or self.inflight or self.ready_q)
+        return bool(self.pending or self.waiting or self.inflight or self.ready_q or self.jobs)
 
     def run(self, idle_sleep: float = 2e-4, deadline: float | None = None,
             progress: float | None = None, log=None) -> None:
@@ -250,7 +370,7 @@ class Scheduler:
         lat = np.array([r.latency for r in done]) if done else np.zeros(0)
         out = {"completed": len(done), "failed": len(self.completed) - len(done),
                "rejected": len(self.rejected),
-               "unfinished": len(self.pending) + len(self.waiting) +
+               "unfinished": len(self.pending) + len(self.waiting) + len(self.jobs) +
                sum(len(q) for _, q, _ in self.inflight) + sum(len(v) for v in self.ready_q.values())}
         for kind in ("job", "query"):
             lk = np.array([r.latency for r in done if r.kind == kind])
@@ -267,22 +387,35 @@ class Scheduler:
 
 
 class GpuExecutor(Executor):
-    """Runs requests through the C ABI on HIP streams."""
+    """Runs requests through the C ABI on HIP streams: fused query launches
+    on two query streams, grouped job launches (``cde_launch_batch``) on one
+    stream per job lane, job uploads on the small-job lane (never behind a
+    long launch)."""
 
-    def __init__(self, sets, n_streams: int = 4, grid_points: int = 256, max_query_rows: int = 1 << 16):
+    def __init__(self, sets, n_streams: int = 2, grid_points: int = 256, max_query_rows: int = 1 << 16):
         import torch
 
         from . import _binding
         from .drivers import normal_reference_bandwidths
-        from .model import Model, density_summary
+        from .model import Model, density_summary, launch_batch
         self.torch = torch
         self.Model = Model
         self.B = _binding
         self.density_summary = density_summary
+        self.launch_batch = launch_batch
         self.alpha = 0.05
         self.dev = torch.device("cuda:0")
+        # Four streams in all: the device runs a process's work on four
+        # hardware queues, and streams that share a queue run in order, so a
+        # fifth stream would put a long job launch in front of a short query
+        # launch.  Two query streams, the small-job lane (which also carries
+        # job uploads: short work) and the large-job lane.
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_streams)]
+        self.job_streams = {"small": torch.cuda.Stream(device=self.dev),
+                            "large": torch.cuda.Stream(device=self.dev)}
+        self.upload_stream = self.job_streams["small"]
         self.rr = 0
+        self.job_state = {}  # rid -> {"model", "totals", "keep", "ready" event}
         # Finished job models are destroyed only when the device is idle (or
         # in bulk past a limit): freeing device memory synchronises the whole
         # device and would serialise the overlapping launches.
@@ -357,6 +490,54 @@ class GpuExecutor(Executor):
             ev.record(s)
         return {"ev": ev, "tot": tot, "model": m, "req": r, "keep": (xd, yd)}
 
+    def prepare_job(self, r):
+        torch = self.torch
+        u = self.upload_stream
+        with torch.cuda.stream(u):
+            xd = torch.from_numpy(r.x).to(self.dev)
+            yd = torch.from_numpy(r.y).to(self.dev)
+            m = self.Model(xd, yd, stream=u)
+            totals = torch.empty(len(r.hx) * len(r.hy), dtype=torch.float64, device=self.dev)
+            ready = torch.cuda.Event()
+            ready.record(u)
+        self.job_state[r.rid] = {"model": m, "totals": totals, "keep": (xd, yd), "ready": ready}
+
+    def launch_job_tick(self, items, lane="large"):
+        torch = self.torch
+        s = self.job_streams[lane]
+        for r, i0, _ in items:
+            if i0 == 0:  # the job's upload and model creation come first
+                s.wait_event(self.job_state[r.rid]["ready"])
+        groups = {}
+        for r, i0, i1 in items:
+            key = (r.x.shape[1], r.y.shape[1] if r.y.ndim > 1 else 1, tuple(r.hx), tuple(r.hy))
+            groups.setdefault(key, []).append((r, i0, i1))
+        failed = []
+
+        def work(r, i0, i1):
+            js = self.job_state[r.rid]
+            return (js["model"], i0, i1, js["totals"] if i1 == r.x.shape[0] else None, None)
+
+        with torch.cuda.stream(s):
+            for (_, _, hx, hy), its in groups.items():
+                try:
+                    self.launch_batch([work(*it) for it in its], hx, hy, stream=s)
+                except Exception:
+                    # the library checks every item before it launches any,
+                    # so nothing of this group ran: each item alone
+                    for it in its:
+                        try:
+                            self.launch_batch([work(*it)], hx, hy, stream=s)
+                        except Exception as e:
+                            failed.append((it[0], str(e)))
+            ev = torch.cuda.Event()
+            ev.record(s)
+        bad = {id(r) for r, _ in failed}
+        for r, _ in failed:
+            self.graveyard.append(self.job_state.pop(r.rid)["model"])
+        tick = [(r, i1 == r.x.shape[0]) for r, _, i1 in items if id(r) not in bad]
+        return {"ev": ev, "tick": tick, "failed": failed}
+
     def done(self, h):
         return h["ev"].query()
 
@@ -370,14 +551,26 @@ class GpuExecutor(Executor):
                 q = r.xq.shape[0]
                 r.result = {"f": f[o:o + q], "mean": mean[o:o + q], "summary": summ[o:o + q]}
                 o += q
+        elif "tick" in h:
+            for r, last in h["tick"]:
+                if not last:
+                    continue
+                js = self.job_state.pop(r.rid)
+                self._job_result(r, js["totals"].cpu().numpy())
+                self.graveyard.append(js["model"])
+            if len(self.graveyard) >= self.graveyard_limit:
+                self.idle()
         else:
             r = h["req"]
-            t = h["tot"].cpu().numpy()
-            finite = np.where(np.isfinite(t), t, -np.inf)
-            r.result = {"totals": t.reshape(len(r.hx), len(r.hy)), "argmax": int(np.argmax(finite))}
+            self._job_result(r, h["tot"].cpu().numpy())
             self.graveyard.append(h["model"])
             if len(self.graveyard) >= self.graveyard_limit:
                 self.idle()
+
+    @staticmethod
+    def _job_result(r, t):
+        finite = np.where(np.isfinite(t), t, -np.inf)
+        r.result = {"totals": t.reshape(len(r.hx), len(r.hy)), "argmax": int(np.argmax(finite))}
 
     def idle(self):
         for m in self.graveyard:
@@ -387,4 +580,3 @@ class GpuExecutor(Executor):
     def wait_all(self):
         self.torch.cuda.synchronize()
         self.idle()
-

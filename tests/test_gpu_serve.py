@@ -22,8 +22,12 @@ def gpu():
         pytest.skip("no GPU")
 
 
-def test_serve_alone_vs_mixed_identical_and_oracle():
-    print("case: serve small stream, plain vs batched", flush=True)
+@pytest.mark.parametrize("tick_pairs,small_points", [(1e12, 16384), (3e8, 600)])
+def test_serve_alone_vs_mixed_identical_and_oracle(tick_pairs, small_points):
+    # (3e8, 600): every job above 600 points runs as ranges over several
+    # grouped launches of the large-job lane
+    print(f"case: serve small stream, plain vs batched, tick {tick_pairs:g} small {small_points}",
+          flush=True)
     import bench_serve
     from paper_1206_5278_amd.serve import GpuExecutor, Scheduler
     sets = [workloads.gmm(n, seed=40 + k, dx=dx) for k, (n, dx) in
@@ -35,7 +39,8 @@ def test_serve_alone_vs_mixed_identical_and_oracle():
     ex = GpuExecutor(sets, grid_points=64)
     out = {}
     for batched in (False, True):
-        s = Scheduler(ex, hbm_budget=8 << 30, batched=batched)
+        s = Scheduler(ex, hbm_budget=8 << 30, batched=batched, tick_pairs=tick_pairs,
+                      small_job_points=small_points)
         rs = copy.deepcopy(reqs)
         s.submit_all(rs)
         s.run(deadline=120.0)

@@ -1,6 +1,7 @@
 """CPU tests of the serving scheduler with a fake executor and a fake clock:
-admission by memory footprint and slots, FIFO order, fused query launches,
-the one-request-per-launch baseline, and failure isolation."""
+admission by memory footprint and slots, fused query launches, grouped job
+ticks (small jobs whole, large jobs in arrival order in point ranges), the
+one-request-per-launch baseline, and failure isolation."""
 import numpy as np
 
 import pytest
@@ -17,14 +18,21 @@ class FakeClock:
 
 
 class FakeExecutor(Executor):
-    """Each launch finishes `latency` fake seconds after it starts."""
+    """A launch finishes `latency` fake seconds after it starts; a job tick
+    finishes after max(latency, pair evaluations / rate)."""
 
-    def __init__(self, clock, latency=1.0, fail_rid=None):
+    def __init__(self, clock, latency=1.0, fail_rid=None, sizes=None, rate=None):
         self.clock, self.latency, self.fail_rid = clock, latency, fail_rid
+        self.sizes = sizes or {}
+        self.rate = rate
         self.launches = []
+        self.ranges = {}
 
     def footprint(self, r):
         return 100 if r.kind == "job" else 10
+
+    def job_points(self, r):
+        return self.sizes.get(r.rid, 1000)
 
     def _h(self, kind, reqs):
         if any(r.rid == self.fail_rid for r in reqs):
@@ -38,6 +46,24 @@ class FakeExecutor(Executor):
     def launch_job(self, r):
         return self._h("job", [r])
 
+    def prepare_job(self, r):
+        pass
+
+    def launch_job_tick(self, items, lane="large"):
+        failed = [(r, "injected launch failure") for r, _, _ in items if r.rid == self.fail_rid]
+        ok = [(r, i0, i1) for r, i0, i1 in items if r.rid != self.fail_rid]
+        self.launches.append(("tick", [(r.rid, i0, i1) for r, i0, i1 in ok], self.clock(), lane))
+        for r, i0, i1 in ok:
+            self.ranges.setdefault(r.rid, []).append((i0, i1))
+        dur = self.latency
+        if self.rate:
+            dur = max(dur, sum((i1 - i0) * self.job_points(r) * 256.0 for r, i0, i1 in ok) / self.rate)
+        # launches of one lane run one after another on its stream
+        end = getattr(self, "lane_end", {})
+        end[lane] = max(self.clock(), end.get(lane, 0.0)) + dur
+        self.lane_end = end
+        return {"t": end[lane], "reqs": [r for r, _, _ in ok], "failed": failed}
+
     def done(self, h):
         return self.clock() >= h["t"]
 
@@ -46,7 +72,7 @@ class FakeExecutor(Executor):
             r.result = r.rid
 
 
-def drive(sched, clock, step=0.25, limit=1000):
+def drive(sched, clock, step=0.25, limit=5000):
     sched.t0 = clock()
     for _ in range(limit):
         if not sched.tick():
@@ -64,7 +90,11 @@ def reqs_mixed():
     return out
 
 
-def test_batched_fuses_queries_per_set_and_overlaps_jobs():
+def ticks(ex):
+    return [l for l in ex.launches if l[0] == "tick"]
+
+
+def test_batched_fuses_queries_per_set_and_groups_small_jobs():
     clock = FakeClock()
     ex = FakeExecutor(clock)
     s = Scheduler(ex, hbm_budget=10_000, max_active=64, batched=True, clock=clock)
@@ -73,6 +103,8 @@ def test_batched_fuses_queries_per_set_and_overlaps_jobs():
     q_launches = [l for l in ex.launches if l[0] == "query"]
     assert len(q_launches) == 2  # one fused launch per resident set
     assert sorted(sum((l[1] for l in q_launches), [])) == list(range(6))
+    # the three small jobs ride whole in one grouped launch
+    assert ticks(ex) == [("tick", [(6, 0, 1000), (7, 0, 1000), (8, 0, 1000)], 0.0, "small")]
     assert all(l[2] == 0.0 for l in ex.launches)  # everything started in the first tick
     assert len(s.completed) == 9 and all(r.result == r.rid for r in s.completed)
     assert max(r.latency for r in s.completed) <= 1.25
@@ -89,6 +121,33 @@ def test_plain_mode_is_one_request_per_launch_in_order():
     assert all(b >= a + 1.0 for a, b in zip(starts, starts[1:]))
 
 
+def test_large_jobs_in_arrival_order_small_jobs_ride_along():
+    # tick budget 2e12 pair evaluations at 2e13 per fake second: ~0.1 s ticks
+    clock = FakeClock()
+    sizes = {0: 200_000, 1: 150_000, 2: 2_000, 3: 60_000}
+    ex = FakeExecutor(clock, latency=0.01, sizes=sizes, rate=2e13)
+    s = Scheduler(ex, hbm_budget=10_000, batched=True, clock=clock, tick_pairs=2e12)
+    s.submit_all([ServeRequest(0, "job", 0.0), ServeRequest(1, "job", 0.1), ServeRequest(2, "job", 0.2),
+                  ServeRequest(3, "job", 0.3)])
+    drive(s, clock, step=0.01)
+    # every job's ranges cover [0, n) in order, 256-aligned inside
+    for rid, n in sizes.items():
+        rs = ex.ranges[rid]
+        assert rs[0][0] == 0 and rs[-1][1] == n
+        assert all(a[1] == b[0] and a[1] % 256 == 0 for a, b in zip(rs, rs[1:]))
+    done = {r.rid: r.t_done for r in s.completed}
+    # the small job, on its own lane, finishes right after it arrives
+    assert done[2] <= 0.2 + 0.02
+    assert [l[3] for l in ticks(ex) if any(it[0] == 2 for it in l[1])] == ["small"]
+    # large jobs run in arrival order: job 1's first range comes in the
+    # launch that issues job 0's last one, or later
+    large = [l for l in ticks(ex) if l[3] == "large"]
+    first1 = min(k for k, l in enumerate(large) if any(it[0] == 1 for it in l[1]))
+    last0 = max(k for k, l in enumerate(large) if any(it[0] == 0 for it in l[1]))
+    assert first1 >= last0 and done[0] < done[1] <= done[3]
+    assert len(s.completed) == 4 and all(r.error is None for r in s.completed)
+
+
 def test_admission_by_footprint_and_late_arrivals():
     clock = FakeClock()
     ex = FakeExecutor(clock, latency=2.0)
@@ -96,7 +155,10 @@ def test_admission_by_footprint_and_late_arrivals():
     jobs = [ServeRequest(i, "job", 0.0) for i in range(4)] + [ServeRequest(9, "job", 1.0)]
     s.submit_all(jobs)
     drive(s, clock)
-    start = {l[1][0]: l[2] for l in ex.launches}
+    start = {}
+    for _, its, t, _ in ticks(ex):
+        for rid, _, _ in its:
+            start.setdefault(rid, t)
     assert start[0] == 0.0 and start[1] == 0.0  # two fit in 250 bytes
     assert start[2] >= 2.0 and start[3] >= 2.0  # admitted as memory frees up
     assert start[9] >= 2.0
@@ -112,7 +174,7 @@ def test_resident_memory_is_taken_from_the_budget():
     assert s.budget == 150
     s.submit_all([ServeRequest(i, "job", 0.0) for i in range(2)])
     drive(s, clock)
-    start = {l[1][0]: l[2] for l in ex.launches}
+    start = {its[0][0]: t for _, its, t, _ in ticks(ex)}
     assert start[0] == 0.0 and start[1] >= 2.0
     ex.resident_bytes = lambda: 300
     with pytest.raises(ValueError):
@@ -129,21 +191,22 @@ def test_slot_limit_and_rejection():
     s.submit_all([big])
     drive(s, clock)
     assert [r.rid for r in s.rejected] == [50]
-    starts = sorted(l[2] for l in ex.launches)
+    starts = sorted(t for _, its, t, _ in ticks(ex) for _ in its)
     assert starts[:2] == [0.0, 0.0] and starts[2] >= 1.0
 
 
-def test_failed_launch_fails_only_its_request():
+@pytest.mark.parametrize("batched", [True, False])
+def test_failed_launch_fails_only_its_request(batched):
     clock = FakeClock()
     ex = FakeExecutor(clock, fail_rid=7)
-    s = Scheduler(ex, hbm_budget=10_000, batched=True, clock=clock)
+    s = Scheduler(ex, hbm_budget=10_000, batched=batched, clock=clock)
     s.submit_all(reqs_mixed())
     drive(s, clock)
     bad = [r for r in s.completed if r.error]
     assert [r.rid for r in bad] == [7]
     assert sum(1 for r in s.completed if r.error is None) == 8
     rep = s.report(1.0)
-    assert rep["failed"] == 1 and rep["completed"] == 8
+    assert rep["failed"] == 1 and rep["completed"] == 8 and rep["unfinished"] == 0
 
 
 def test_queries_arriving_during_a_batch_join_the_next_batch():
