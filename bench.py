@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=50.0,
                     help="arrival rate of the short serving stream (0: skip it)")
-    ap.add_argument("--serve-duration", type=float, default=10.0,
+    ap.add_argument("--serve-duration", type=float, default=20.0,
                     help="seconds of arrivals of the short serving stream")
     ap.add_argument("--trace-steps", type=int, default=0,
                     help="after the timed steps, run this many untimed ascent steps from the "

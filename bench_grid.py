@@ -42,6 +42,9 @@ def main():
                     help="skip the two large sets (photoz 500k and highdim 1M)")
     ap.add_argument("--highdim-only", action="store_true",
                     help="only the 1M-point 16-D set, with its three x-distance variants")
+    ap.add_argument("--variant", choices=("valu_fp64_differences", "valu_fp32_differences",
+                                          "mfma_bf16x3_cross_term"), default=None,
+                    help="with --highdim-only: run this x-distance variant alone (profiling)")
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -53,7 +56,7 @@ def main():
     out = {"metric": "grid LOO-loglik pair-kernel evals/s"}
 
     if args.highdim_only:
-        highdim(out, cde, workloads, B, np, torch, dev)
+        highdim(out, cde, workloads, B, np, torch, dev, only=args.variant)
         print(json.dumps(out))
         return
 
@@ -92,10 +95,10 @@ def main():
     print(json.dumps(out))
 
 
-def highdim(out, cde, workloads, B, np, torch, dev):
+def highdim(out, cde, workloads, B, np, torch, dev, only=None):
     """The 1M-point 16-D set on its 16 x 16 grid, with each way of forming
     the x-distances (FP64 differences, FP32 differences, split-bf16 x3 MFMA
-    cross term) in the same pass structure."""
+    cross term) in the same pass structure (or the variant `only`)."""
     hx, hy = workloads.WORKLOADS["highdim"]["grid"]
     x, y = workloads.highdim()
     x32, y32 = x.astype(np.float32), y.astype(np.float32)
@@ -104,6 +107,8 @@ def highdim(out, cde, workloads, B, np, torch, dev):
     for name, xt in (("valu_fp64_differences", B.CDE_XTERM_VALU),
                      ("valu_fp32_differences", B.CDE_XTERM_VALU_F32),
                      ("mfma_bf16x3_cross_term", B.CDE_XTERM_MFMA_BF16X3)):
+        if only is not None and name != only:
+            continue
         dt, tot, nf = timed_grid(m, hx, hy, 1, xt)
         res[name] = {"s": dt, "evals_per_s": 1e6 * (1e6 - 1) * 256 / dt, "nonfinite": int(nf.item())}
         print(json.dumps({name: res[name]}), file=sys.stderr, flush=True)

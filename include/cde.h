@@ -220,6 +220,14 @@ typedef struct cde_work_item {
 cde_status cde_launch_batch(const cde_work_item* items, int32_t n_items, const double* hx, int32_t n_hx,
                             const double* hy, int32_t n_hy, cde_criterion criterion, void* stream);
 
+/* Scheduling hint for cde_launch_batch: the number of points whose ranges
+ * fill one full round of the grouped grid pass on the current device
+ * (compute units x resident blocks per unit x points per block) for models
+ * of this shape.  Ranges that are whole multiples of it keep the pass's last
+ * round of blocks full; a range of 2.4 rounds costs as much as 3.  Returns 0
+ * for unsupported shapes or when no device is visible.  No work is launched. */
+int64_t cde_batch_round_points(int32_t dx, int32_t dy);
+
 /* Exact LOO log-likelihood for a list of g diagonal bandwidth settings.
  *   h: host [g][dx+dy] (hx_1..hx_dx, hy_1..hy_dy per setting).
  *   kernel: CDE_GAUSSIAN, or CDE_EPANECHNIKOV (FP64 pair arithmetic over

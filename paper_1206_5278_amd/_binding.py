@@ -43,6 +43,7 @@ SIGNATURES = {
     "cde_check_bandwidths": (ctypes.c_int, [_dp, _i32, _i32, _dp, ctypes.c_int, _i32]),
     "cde_loo_grad_noalloc": (ctypes.c_int, [_vp, _dp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "cde_launch_batch": (ctypes.c_int, [_vp, _i32, _dp, _i32, _dp, _i32, ctypes.c_int, _vp]),
+    "cde_batch_round_points": (ctypes.c_int64, [_i32, _i32]),
 }
 
 

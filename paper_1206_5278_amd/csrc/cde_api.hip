@@ -861,6 +861,20 @@ cde_status cde_launch_batch(const cde_work_item* items, int32_t n_items, const d
     }
 }
 
+int64_t cde_batch_round_points(int32_t dx, int32_t dy)
+{
+    try {
+        if (!supported_dims(dx, dy)) return 0;
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        return grid_round_points(dx, dy, ncu);
+    } catch (...) {
+        return 0;
+    }
+}
+
 cde_status cde_loo_grad_noalloc(cde_model* m, const double* h, cde_criterion criterion,
                                 double* total_dev, double* grad_dev, double* per_point_dev,
                                 void* stream)

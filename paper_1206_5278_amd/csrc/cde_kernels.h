@@ -122,6 +122,10 @@ struct GridRange {
     double* counts;
     bool do_nn;
 };
+// Points per full round of the grouped launch's FP32 grid pass on the
+// current device: compute units x resident blocks per CU x points per
+// block (0 for an unsupported shape).
+int64_t grid_round_points(int dx, int dy, int ncu);
 // The grid pipeline over a work list of ranges of models sharing dx and dy,
 // for a grid of at most 16 x 16 cells: one launch per stage per 8 items.
 hipError_t launch_grid_batch(const GridRange* r, int count, const double* hx, int n_hx, const double* hy,

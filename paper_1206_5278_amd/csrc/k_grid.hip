@@ -450,6 +450,125 @@ __global__ __launch_bounds__(TILE) void k_loo_grid(const float* __restrict__ pts
                                  plist, pcount);
 }
 
+// Packed FP64 rerun of flagged points whose flagged cells all lie in the
+// first 4 x 4 cells of their grid tile (local a < 4 and b < 4), which is
+// where small shifted sums concentrate when the bandwidths grow with the
+// index.  Rows of the 16 x 16 f64 product are (point p, a) = 4 p + a and its
+// columns (point p, b) = 4 p + b, so its four diagonal 4 x 4 blocks are four
+// points' cells; the off-diagonal blocks pair one point's x-kernel values
+// with another's y-kernel values and are discarded.  One product step thus
+// covers four points where grid64_body covers one.  The per-pair arithmetic
+// is grid64_body's: FP64 distances, shifted distances rounded to FP32 after
+// the FP64 subtraction, exp2_neg_wide kernel values, FP64 products summed
+// over j in order.  The lists come from k_compact_points: packed entries
+// fill a tile's list from its end, counted in pcount[32 + tile].
+//
+// A wave holds 4 points; a distance group is 16 tile rows.  Lane (k, c),
+// k = lane / 16, c = lane % 16, forms the distance of point c % 4 to row
+// 4 (c / 4) + k of the group; product step s then needs, in lane (k, c),
+// the pair of point c / 4 and row 4 s + k, held by lane 16 k + 4 s + c / 4
+// (a gather through ds_bpermute).
+template <int DX, int DY>
+__device__ __forceinline__ void grid64p_body(int bx, int by, const float* __restrict__ pts,
+                                             const double* __restrict__ nn, int n, int npad,
+                                             const GridArgs& ga, double* __restrict__ numbuf,
+                                             double* __restrict__ denbuf, const int* __restrict__ plist,
+                                             const int* __restrict__ pcount)
+{
+    constexpr int S = row_stride(DX, DY);
+    constexpr int PPB = 16;  // points per block: 4 waves of 4
+    __shared__ float tile[TILE * S];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    plist += (size_t)by * npad;
+    const int cnt_list = pcount[32 + by];
+    if (bx * PPB >= cnt_list) return;  // whole block past the list (uniform)
+    const int e0 = bx * PPB + wave * 4;  // list entries of this wave's points
+    // entry e sits at npad - 1 - e; a ragged tail repeats the last entry
+    auto point = [&](int q) -> int { return plist[npad - 1 - min(e0 + q, cnt_list - 1)]; };
+    auto point_valid = [&](int q) -> bool { return e0 + q < cnt_list; };
+    const int tb = ga.gyp / 16;
+    const int ab = by / tb, bb = by % tb;
+    const bool do_den = (bb == 0);
+
+    const int c = lane & 15, kr = lane >> 4;
+    const int di = point(c & 3);
+    const int jo = 4 * (c >> 2) + kr;
+    double own[S];
+    own_f64<S>(own, pts + (size_t)di * S);
+    const double m_i = nn[di], my_i = nn[npad + di];
+    // product role: row / column 4 (c / 4) + (c % 4): cell a = c % 4 of A, b = c % 4 of B
+    const float ca = ga.cx[ab * 16 + (c & 3)];
+    const float cb = ga.cy[bb * 16 + (c & 3)];
+
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    double dsum = 0.0;
+    const int ntiles = (n + TILE - 1) / TILE;
+    float pre[S];
+    load_row<S>(pre, pts + (size_t)tid * S);
+    for (int t = 0; t < ntiles; ++t) {
+        __syncthreads();
+        store_row<S>(tile + tid * S, pre);
+        __syncthreads();
+        if (t + 1 < ntiles) load_row<S>(pre, pts + ((size_t)(t + 1) * TILE + tid) * S);
+        const int base = t * TILE;
+        const int cnt = min(TILE, n - base);
+        const int ngroups = (cnt + 15) / 16;
+        for (int g = 0; g < ngroups; ++g) {
+            const int jj = g * 16 + jo;
+            float pj[S];
+            load_row<S>(pj, tile + jj * S);  // rows >= cnt hold packed padding (in bounds)
+            double d2x, d2y;
+            dist2<DX, DY>(own, pj, d2x, d2y);
+            float xa = (float)(d2x - m_i), ya = (float)(d2y - my_i);
+            if (jj >= cnt || base + jj == di) {
+                xa = EXCLUDED;
+                ya = EXCLUDED;
+            }
+            const int xai = __float_as_int(xa), yai = __float_as_int(ya);
+            Unroll<4>::run([&](auto cc) {
+                constexpr int st = decltype(cc)::value;
+                const int src = 4 * (16 * kr + 4 * st + (c >> 2));  // byte address of the source lane
+                const float xb = __int_as_float(__builtin_amdgcn_ds_bpermute(src, xai));
+                const float yb = __int_as_float(__builtin_amdgcn_ds_bpermute(src, yai));
+                const double ex = exp2_neg_wide(xb * ca);
+                const double ey = exp2_neg_wide(yb * cb);
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, ey, acc, 0, 0, 0);
+                dsum += ex;  // used by the b-tile-0 blocks only
+            });
+        }
+    }
+
+    // register r holds row kr + 4 r = (point r, a = kr) of column c =
+    // (point c / 4, b = c % 4): the diagonal block is r = c / 4
+    const int p = c >> 2;
+    const double v = p == 0 ? acc[0] : p == 1 ? acc[1] : p == 2 ? acc[2] : acc[3];
+    {
+        const int a = ab * 16 + kr, b = bb * 16 + (c & 3);
+        if (point_valid(p) && a < ga.gx && b < ga.gy) numbuf[((size_t)a * ga.gy + b) * npad + point(p)] = v;
+    }
+    if (do_den) {
+        // den' of (point c / 4, a = c % 4): the four k-rows in a fixed order
+        double d = dsum;
+        d += __shfl_xor(d, 16, 64);
+        d += __shfl_xor(d, 32, 64);
+        const int a = ab * 16 + (c & 3);
+        if (lane < 16 && a < ga.gx && point_valid(p)) denbuf[(size_t)a * npad + point(p)] = d;
+    }
+}
+
+template <int DX, int DY>
+__global__ __launch_bounds__(TILE) void k_loo_grid_packed(const float* __restrict__ pts,
+                                                          const double* __restrict__ nn, int n, int npad,
+                                                          GridArgs ga, double* __restrict__ numbuf,
+                                                          double* __restrict__ denbuf,
+                                                          const int* __restrict__ plist,
+                                                          const int* __restrict__ pcount)
+{
+    grid64p_body<DX, DY>(blockIdx.x, blockIdx.y, pts, nn, n, npad, ga, numbuf, denbuf, plist, pcount);
+}
+
 // FP32 fast pass: the same decomposition with FP32 kernel values (plain
 // v_exp_f32), v_mfma_f32_16x16x4f32 products and sums, partial sums over a
 // 256-point j-tile folded into Kahan-compensated FP32 totals.  FP32 cannot
@@ -841,8 +960,8 @@ struct GridFin {
 // too small for FP32 to have carried it are queued for the exact fixup.
 // flag_points != NULL (after the FP32 pass): mark (tile, point) pairs with a
 // cell below the tile's threshold (2^-130 biased, 2^-80 otherwise), in
-// flag_points[tile][npad]; otherwise queue entries below 2^-1000 for the
-// per-entry fixup.
+// flag_points[tile][npad] (bits: where in the tile the cells lie);
+// otherwise queue entries below 2^-1000 for the per-entry fixup.
 template <class Fin>
 __device__ __forceinline__ void finalize_body(int i, int g, const double* __restrict__ numbuf,
                                               const double* __restrict__ denbuf,
@@ -866,7 +985,10 @@ __device__ __forceinline__ void finalize_body(int i, int g, const double* __rest
     if (flag_points) {
         const int t = (a / 16) * gf.tb + b / 16;
         const double lim = (gf.biased >> t) & 1u ? 0x1p-130 : 0x1p-80;
-        if (!(num >= lim)) flag_points[(size_t)t * npad + i] = 1;
+        // bit 0: a flagged cell in the tile's first 4 x 4 cells, bit 1: one
+        // outside them (the point then takes the full rerun)
+        if (!(num >= lim))
+            atomicOr(flag_points + (size_t)t * npad + i, ((a & 15) < 4 && (b & 15) < 4) ? 1 : 2);
     } else if (!(num >= 0x1p-1000)) {
         const int slot = atomicAdd(fix_count, 1);
         if (slot < fix_cap) fix_list[slot] = make_int2(g, i);
@@ -883,18 +1005,27 @@ __global__ void k_grid_finalize(const double* __restrict__ numbuf, const double*
                   crit, ell, fix_count, fix_list, fix_cap, flag_points);
 }
 
-// List of flagged points (order of the list does not affect any result).
+// Lists of flagged points (order of a list does not affect any result).
+// One list area per grid tile t, list[tile][npad]: points for the full rerun
+// from its start (count[t] of them), points whose flagged cells all lie in
+// the tile's first 4 x 4 cells from its end (count[32 + t]), when `pack`;
+// the two never meet, since a tile flags at most n <= npad points.
 __device__ __forceinline__ void compact_body(int i, int t, const int* __restrict__ flag, int n, int npad,
-                                             int* __restrict__ count, int* __restrict__ list)
+                                             int* __restrict__ count, int* __restrict__ list, bool pack)
 {
-    // one list per grid tile t: flag[tile][npad] -> list[tile][npad]
-    if (i < n && flag[(size_t)t * npad + i]) list[(size_t)t * npad + atomicAdd(count + t, 1)] = i;
+    if (i >= n) return;
+    const int f = flag[(size_t)t * npad + i];
+    if (f == 0) return;
+    if ((f & 2) || !pack)
+        list[(size_t)t * npad + atomicAdd(count + t, 1)] = i;
+    else
+        list[(size_t)t * npad + npad - 1 - atomicAdd(count + 32 + t, 1)] = i;
 }
 
 __global__ void k_compact_points(const int* __restrict__ flag, int n, int npad, int* __restrict__ count,
-                                 int* __restrict__ list)
+                                 int* __restrict__ list, int pack)
 {
-    compact_body(blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y, flag, n, npad, count, list);
+    compact_body(blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y, flag, n, npad, count, list, pack != 0);
 }
 
 // Exact recomputation of queued (setting, point) entries: one wave per entry,
@@ -1070,7 +1201,7 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
         // path (the FP32 denominators stand where b-tile 0 is not recomputed).
         hipLaunchKernelGGL(k_zero_int, dim3((unsigned)(((size_t)tiles * npad + 255) / 256)), dim3(256), 0, stream,
                            w.flags, tiles * npad);
-        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, w.pcount, tiles);
+        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, w.pcount, 64);
         constexpr int PW = CDE_GRID32_POINTS_PER_WAVE;
         if (xm == XM_F64 && ga.gxp % 32 == 0 && ga.gyp % 32 == 0) {
             constexpr int PWQ = 2;
@@ -1122,7 +1253,13 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
                            (const double*)w.denbuf, nn, n, npad, gf, crit, w.ell, w.fix_count,
                            w.fix_list, w.fix_cap, w.flags);
         hipLaunchKernelGGL(k_compact_points, dim3((n + 255) / 256, (unsigned)tiles), dim3(256), 0, stream,
-                           (const int*)w.flags, n, npad, w.pcount, w.plist);
+                           (const int*)w.flags, n, npad, w.pcount, w.plist, xm == XM_BF16X3 ? 0 : 1);
+        if (xm != XM_BF16X3) {
+            hipLaunchKernelGGL((k_loo_grid_packed<DX, DY>), dim3((unsigned)(npad / 16), (unsigned)tiles),
+                               dim3(TILE), 0, stream, pts, nn, n, npad, ga, w.numbuf, w.denbuf,
+                               (const int*)w.plist, (const int*)w.pcount);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         // Points per wave of the rerun.  Each block streams all n points, so
         // 8 per wave keeps that traffic low; up to 2^18 points the flagged
         // lists are short (a few thousand points: ~100 blocks of 32) and 2
@@ -1365,7 +1502,16 @@ __global__ void k_compact_batch(GridBatch b)
     const int k = batch_item(b, blockIdx.x);
     const GridBatchItem& t = b.it[k];
     const int i = t.p0 + (blockIdx.x - b.pre[k]) * blockDim.x + threadIdx.x;
-    compact_body(i, 0, t.w.flags, t.n, t.npad, t.w.pcount, t.w.plist);
+    compact_body(i, 0, t.w.flags, t.n, t.npad, t.w.pcount, t.w.plist, true);
+}
+
+template <int DX, int DY>
+__global__ __launch_bounds__(TILE) void k_rerun_packed_batch(GridBatch b, GridArgs ga)
+{
+    const int k = batch_item(b, blockIdx.x);
+    const GridBatchItem& t = b.it[k];
+    grid64p_body<DX, DY>(blockIdx.x - b.pre[k], 0, t.pts, t.nn, t.n, t.npad, ga, t.w.numbuf, t.w.denbuf,
+                         t.w.plist, t.w.pcount);
 }
 
 template <int DX, int DY, int PWF>
@@ -1444,8 +1590,16 @@ static hipError_t grid_batch_t(const GridBatch& all, const bool* do_nn, const Gr
                        crit);
     hipLaunchKernelGGL(k_compact_batch, dim3((unsigned)blocks), dim3(256), 0, stream, b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // FP64 rerun of flagged points, with the points-per-wave rule of the
-    // one-model launch (2 up to 2^18 rows, else 8), one launch per rule
+    // FP64 rerun of flagged points: the packed rerun (16 points per block),
+    // then the full rerun with the points-per-wave rule of the one-model
+    // launch (2 up to 2^18 rows, else 8), one launch per rule
+    {
+        GridBatch pb = all;
+        const int pblocks = batch_prefix(pb, 16);
+        hipLaunchKernelGGL((k_rerun_packed_batch<DX, DY>), dim3((unsigned)pblocks), dim3(TILE), 0, stream, pb,
+                           ga);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     for (int pwf : {2, 8}) {
         GridBatch rb = all;
         rb.count = 0;
@@ -1474,6 +1628,34 @@ static hipError_t grid_batch_t(const GridBatch& all, const bool* do_nn, const Gr
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <int DX, int DY>
+static int batch_round_blocks()
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, (const void*)k_loo_grid32_batch<DX, DY, CDE_GRID32_POINTS_PER_WAVE>, TILE, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu;
+}
+
+#define CDE_ROUND_CASE(DX_, DY_) \
+    case (DX_) * 8 + (DY_): per_cu = batch_round_blocks<DX_, DY_>(); break;
+
+int64_t grid_round_points(int dx, int dy, int ncu)
+{
+    int per_cu = 0;
+    switch (dx * 8 + dy) {
+        CDE_ROUND_CASE(1, 1) CDE_ROUND_CASE(1, 2) CDE_ROUND_CASE(2, 1) CDE_ROUND_CASE(2, 2)
+        CDE_ROUND_CASE(3, 1) CDE_ROUND_CASE(3, 2) CDE_ROUND_CASE(4, 1) CDE_ROUND_CASE(4, 2)
+        CDE_ROUND_CASE(5, 1) CDE_ROUND_CASE(5, 2) CDE_ROUND_CASE(6, 1) CDE_ROUND_CASE(6, 2)
+        CDE_ROUND_CASE(7, 1) CDE_ROUND_CASE(7, 2) CDE_ROUND_CASE(8, 1) CDE_ROUND_CASE(8, 2)
+        CDE_ROUND_CASE(16, 1) CDE_ROUND_CASE(16, 2)
+        default: return 0;
+    }
+    return (int64_t)per_cu * (ncu > 0 ? ncu : 1) * 4 * CDE_GRID32_POINTS_PER_WAVE;
 }
 
 #define CDE_GRID_BATCH_CASE(DX_, DY_) \

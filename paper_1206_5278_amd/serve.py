@@ -10,10 +10,13 @@ Two request kinds:
 
 Scheduling (one scheduler thread, ``tick`` is one pass):
   1. arrivals whose time has come enter the waiting queue (FIFO);
-  2. admission: requests leave the queue in order while their device-memory
-     footprint fits the HBM budget and a slot is free -- requests arriving
-     while others run are admitted as slots and memory free up; an admitted
-     job's data is uploaded and its model created at once;
+  2. admission: each request kind (job, query) has its own FIFO queue and
+     its own slots, so queries never wait for a slot behind queued jobs;
+     device memory is granted in arrival order across both queues (the
+     oldest request that is free to go and does not fit the HBM budget stops
+     all admission until memory frees up, so no request starves).  Requests
+     arriving while others run are admitted as slots and memory free up; an
+     admitted job's data is uploaded and its model created at once;
   3. launch: admitted queries wait in a per-set ready list; whenever a
      resident set has no query launch in flight, all of its ready queries
      become ONE fused query launch (so queries that arrive while a batch runs
@@ -21,11 +24,12 @@ Scheduling (one scheduler thread, ``tick`` is one pass):
      of work items, each item a range of one job's points, on two lanes:
      small jobs (n up to 16,384) go whole, all that wait, into one launch
      whenever the small lane is free; large jobs go in arrival order, in
-     ranges of a bounded number of pair evaluations per launch (a tick), up
-     to two ticks in flight so the device never waits for the scheduler.
-     Large jobs therefore run one after another at the device's full rate
-     (the tail of the latency distribution), while small jobs and queries run
-     beside them instead of behind them;
+     ranges of a bounded number of pair evaluations per launch (a tick), one
+     tick in flight: the next range is issued when the previous one ends, so
+     queries issued meanwhile find the device free of job blocks instead of
+     behind a queued range.  Large jobs therefore run one after another at
+     the device's full rate (the tail of the latency distribution), while
+     small jobs and queries run beside them instead of behind them;
   4. completion: finished launches (HIP events) release their memory and
      slots; results are copied out and latencies recorded.
 The plain mode is the baseline: one request per launch (``cde_loo_loglik``
@@ -93,6 +97,11 @@ class Executor:
         """Number of training points of a job (its n)."""
         return int(req.x.shape[0])
 
+    def round_points(self, req: ServeRequest) -> int:
+        """Points per full round of the device for this job's shape: ranges
+        of a job are whole multiples of it."""
+        return 256
+
     def prepare_job(self, req: ServeRequest) -> None:
         """Batched mode, at admission: upload the job's data and create its
         model (ordered before its first grouped launch)."""
@@ -131,18 +140,21 @@ class Scheduler:
 
     def __init__(self, executor: Executor, hbm_budget: int, max_active: int = 64,
                  batched: bool = True, clock: Callable[[], float] | None = None,
-                 max_query_rows: int = 1 << 16, tick_pairs: float = 1.2e13,
-                 small_job_points: int = 16384, ticks_in_flight: int = 2,
+                 max_query_rows: int = 1 << 16, tick_pairs: float = 3e12,
+                 small_job_points: int = 16384, ticks_in_flight: int = 1,
                  grid_cells: int = 256):
         self.ex = executor
         self.max_query_rows = int(max_query_rows)
         # grouped job ticks: pair evaluations per tick (n_range * n * cells),
         # the size up to which a job rides along whole, ticks kept in flight.
-        # The default tick holds a whole 200k-point 16 x 16 job: ranges cost
-        # extra device time (a 200k job: 346 ms whole, 376 ms in 78k-point
-        # ranges, 451 ms in 19.5k-point ranges; the grid pass's last round of
-        # blocks runs part-empty once per range), and small jobs and queries
-        # do not wait for large ones in any case (lanes of their own).
+        # Ranges are whole rounds of the device (executor.round_points) and
+        # about tick_pairs each: every range costs a fixed ~7 ms besides its
+        # work (a 200k-point job: 346 ms whole; in ranges of 1, 2, 4 and 7
+        # rounds of 16,384 points 445, 395, 370 and 354 ms), while a shorter
+        # launch lets queries reach the device sooner.  The default splits a
+        # 200k-point 16 x 16 job into three or four ranges.  A second tick in
+        # flight keeps the device busy with job blocks back to back; at
+        # 50 req/s that raised the query p99 from 0.6 s to 1.4 s.
         self.tick_pairs = float(tick_pairs)
         self.small_job_points = int(small_job_points)
         self.ticks_in_flight = int(ticks_in_flight)
@@ -155,17 +167,21 @@ class Scheduler:
         self.budget = int(hbm_budget) - int(executor.resident_bytes())
         if self.budget <= 0:
             raise ValueError("the resident sets alone exceed the HBM budget")
-        self.max_active = int(max_active)
+        self.max_active = int(max_active)  # slots per request kind (batched mode)
         self.batched = batched
         self.clock = clock or time.perf_counter
         self.pending = collections.deque()   # not yet arrived (sorted by t_arrive)
-        self.waiting = collections.deque()   # arrived, not admitted
+        # arrived, not admitted: one FIFO queue per request kind
+        self.waiting = {"job": collections.deque(), "query": collections.deque()}
         self.inflight = []                   # (handle, [requests])
         self.used = 0
-        self.active = 0
+        self.active = 0                      # admitted, not finished (all kinds)
+        self.active_kind = {"job": 0, "query": 0}
         self.completed = []
         self.rejected = []
         self.t0 = None
+        self._admitted_any = False
+        self._seq = 0
 
     # -------------------------------------------------------------- intake
     def submit_all(self, reqs) -> None:
@@ -184,17 +200,31 @@ class Scheduler:
                 r.t_done = now
                 self.rejected.append(r)
             else:
-                self.waiting.append(r)
+                self._seq += 1
+                self.waiting[r.kind].append((self._seq, r))  # seq: global arrival order
+
+    def n_waiting(self) -> int:
+        return sum(len(q) for q in self.waiting.values())
+
+    def _slot_free(self, kind) -> bool:
+        if not self.batched:  # plain mode: one request in service at a time
+            return self.active == 0
+        return self.active_kind[kind] < self.max_active
 
     def _admit(self, now):
         admitted = []
-        limit = self.max_active if self.batched else 1
-        while self.waiting and self.active < limit and \
-                self.used + self.waiting[0].footprint <= self.budget:
-            r = self.waiting.popleft()
+        while True:
+            heads = [q for kind, q in self.waiting.items() if q and self._slot_free(kind)]
+            if not heads:
+                break
+            q = min(heads, key=lambda q: q[0][0])
+            if self.used + q[0][1].footprint > self.budget:
+                break  # memory in arrival order
+            r = q.popleft()[1]
             r.t_admit = now
             self.used += r.footprint
             self.active += 1
+            self.active_kind[r.kind] += 1
             admitted.append(r)
         return admitted
 
@@ -214,11 +244,12 @@ class Scheduler:
                 continue
             n = self.ex.job_points(r)
             per_point = float(n) * self._job_cells(r)
-            if items and budget < 256 * per_point:
+            rnd = max(256, int(self.ex.round_points(r)) // 256 * 256)
+            if items and budget < rnd * per_point:
                 break
-            take = max(256, int(max(budget, 0.0) / per_point) // 256 * 256)
+            take = max(1, int(round(max(budget, 0.0) / (per_point * rnd)))) * rnd
             i1 = min(n, r.next_point + take)
-            if n - i1 < 256:  # no sliver at the end
+            if n - i1 < rnd // 2:  # no sliver at the end
                 i1 = n
             items.append((r, r.next_point, i1))
             budget -= float(i1 - r.next_point) * per_point
@@ -306,6 +337,7 @@ class Scheduler:
         r.t_done = now
         self.used -= r.footprint
         self.active -= 1
+        self.active_kind[r.kind] -= 1
         self.completed.append(r)
 
     def _complete(self):
@@ -335,14 +367,16 @@ class Scheduler:
     def tick(self) -> bool:
         """One scheduling pass; returns False once everything has finished."""
         now = self.now()
+        self._admitted_any = False
         self._arrivals(now)
         self._complete()
         if not self.batched and self.inflight:
             return True  # plain mode: one request in service at a time
         admitted = self._admit(now)
+        self._admitted_any = bool(admitted)
         if admitted or self.ready_q or self.jobs:
             self._launch(admitted)
-        return bool(self.pending or self.waiting or self.inflight or self.ready_q or self.jobs)
+        return bool(self.pending or self.n_waiting() or self.inflight or self.ready_q or self.jobs)
 
     def run(self, idle_sleep: float = 2e-4, deadline: float | None = None,
             progress: float | None = None, log=None) -> None:
@@ -357,10 +391,10 @@ class Scheduler:
                 break
             if progress is not None and now >= next_log:
                 line = (f"serve: t={now:.0f} s completed={len(self.completed)} "
-                        f"waiting={len(self.waiting)} in_flight={sum(len(q) for _, q, _ in self.inflight)}")
+                        f"waiting={self.n_waiting()} in_flight={sum(len(q) for _, q, _ in self.inflight)}")
                 (log or (lambda m: print(m, file=sys.stderr, flush=True)))(line)
                 next_log += progress
-            if not self.waiting or self.active >= self.max_active:
+            if not self._admitted_any:
                 time.sleep(idle_sleep)
         self.ex.wait_all()
 
@@ -370,7 +404,7 @@ class Scheduler:
         lat = np.array([r.latency for r in done]) if done else np.zeros(0)
         out = {"completed": len(done), "failed": len(self.completed) - len(done),
                "rejected": len(self.rejected),
-               "unfinished": len(self.pending) + len(self.waiting) + len(self.jobs) +
+               "unfinished": len(self.pending) + self.n_waiting() + len(self.jobs) +
                sum(len(q) for _, q, _ in self.inflight) + sum(len(v) for v in self.ready_q.values())}
         for kind in ("job", "query"):
             lk = np.array([r.latency for r in done if r.kind == kind])
@@ -415,6 +449,7 @@ class GpuExecutor(Executor):
                             "large": torch.cuda.Stream(device=self.dev)}
         self.upload_stream = self.job_streams["small"]
         self.rr = 0
+        self._round = {}     # (dx, dy) -> points per full round of the grouped grid pass
         self.job_state = {}  # rid -> {"model", "totals", "keep", "ready" event}
         # Finished job models are destroyed only when the device is idle (or
         # in bulk past a limit): freeing device memory synchronises the whole
@@ -489,6 +524,12 @@ class GpuExecutor(Executor):
             ev = torch.cuda.Event()
             ev.record(s)
         return {"ev": ev, "tot": tot, "model": m, "req": r, "keep": (xd, yd)}
+
+    def round_points(self, r):
+        key = (r.x.shape[1], r.y.shape[1] if r.y.ndim > 1 else 1)
+        if key not in self._round:
+            self._round[key] = int(self.B.load().cde_batch_round_points(*key)) or 256
+        return self._round[key]
 
     def prepare_job(self, r):
         torch = self.torch

@@ -102,6 +102,12 @@ def test_workspace_bytes_host_arithmetic(lib):
         assert B.workspace_bytes(*args) == 0, args
 
 
+def test_batch_round_points_unsupported_shapes(lib):
+    # shapes the kernels are not built for answer 0 before any device query
+    for dx, dy in [(0, 1), (3, 3), (9, 1), (17, 1), (5, 0)]:
+        assert lib.cde_batch_round_points(dx, dy) == 0, (dx, dy)
+
+
 def test_bandwidth_range_check_host(lib):
     """The representable-range rule of the model calls, on the host: each
     c_k = log2(e)/(2 h_k^2) <= 2^59 and X, Y = sum_k range_k^2 c_k <= 2^100

@@ -125,3 +125,27 @@ def test_batch_argument_errors():
     ref, _ = single_totals(a[2], a[3])
     assert torch.equal(t, ref)
     assert status(lambda: ma.loo_grad([0.5, 0.5, 0.5])) == 0  # the evaluation is complete
+
+
+def test_round_points_and_whole_round_ranges():
+    """cde_batch_round_points: a positive multiple of 256 points (ranges are
+    multiples of 256) and of the device's compute-unit count; a job split at
+    one round gives the totals of the whole-job call, bit for bit."""
+    print("case: batch round points, n = round + 700, dx 5", flush=True)
+    from paper_1206_5278_amd import _binding as B
+    lib = B.load()
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    for dx, dy in [(1, 1), (5, 1), (8, 2), (16, 1), (16, 2)]:
+        r = lib.cde_batch_round_points(dx, dy)
+        assert r > 0 and r % 256 == 0 and r % ncu == 0, (dx, dy, r)
+    rnd = lib.cde_batch_round_points(5, 1)
+    n = rnd + 700
+    x, y, xd, yd = job(n, 5, 90)
+    m = cde().Model(xd, yd)
+    t = torch.empty(256, dtype=torch.float64, device="cuda")
+    cde().launch_batch([(m, 0, rnd, None, None)], HX, HY)
+    cde().launch_batch([(m, rnd, n, t, None)], HX, HY)
+    torch.cuda.synchronize()
+    ref, _ = single_totals(xd, yd)
+    assert torch.equal(t, ref)
+    m.close()

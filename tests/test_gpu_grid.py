@@ -141,6 +141,59 @@ def test_grid_highdim_subset_16x16():
     assert int(np.argmax(tot)) == int(np.argmax(oracle.totals(ref)))
 
 
+def rerun_classes(x, y, hx, hy, lim=-130.0, margin=8.0):
+    """CPU count (FP64, all pairs) of the points the FP32 pass flags for the
+    FP64 rerun, by where their flagged cells lie, for ascending grids of one
+    16 x 16 tile: the shifted sum of a cell falls as either bandwidth falls,
+    so a point has flagged cells iff cell (0, 0) is below 2^lim, and one
+    outside the first 4 x 4 cells iff cell (4, 0) or (0, 4) is.  Points
+    within 2^margin of the threshold are left out of both counts."""
+    x = np.asarray(x, np.float32).astype(np.float64)
+    y = np.asarray(y, np.float32).astype(np.float64)
+    d2x = ((x[:, None, :] - x[None, :, :]) ** 2).sum(-1)
+    d2y = ((y[:, None, :] - y[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(d2x, np.inf)
+    np.fill_diagonal(d2y, np.inf)
+    u = d2x - d2x.min(1, keepdims=True)
+    v = d2y - d2y.min(1, keepdims=True)
+
+    def log2_sum(a, b):
+        t = u * (np.log2(np.e) / (2 * hx[a] ** 2)) + v * (np.log2(np.e) / (2 * hy[b] ** 2))
+        mn = t.min(1)
+        return -mn + np.log2(np.exp2(-(t - mn[:, None])).sum(1))
+
+    c00, c40, c04 = log2_sum(0, 0), log2_sum(4, 0), log2_sum(0, 4)
+    below, above = (lambda z: z < lim - margin), (lambda z: z > lim + margin)
+    packed = below(c00) & above(c40) & above(c04)
+    full = below(c40) | below(c04)
+    return int(packed.sum()), int(full.sum())
+
+
+def test_grid_packed_and_full_fp64_reruns():
+    # Points whose cells the FP32 pass cannot carry are recomputed in FP64:
+    # those whose flagged cells all lie in the tile's first 4 x 4 cells four
+    # to a product step, the others one per step.  Both kinds are present
+    # here (counted on the CPU); every point matches the oracle, and the
+    # grouped launch over two ranges gives the one-call totals bit for bit.
+    print("case: highdim subset n=2000 16x16, packed and full FP64 reruns", flush=True)
+    x, y = workloads.highdim(2000, seed=7)
+    hx, hy = workloads.WORKLOADS["highdim"]["grid"]
+    packed, full = rerun_classes(x, y, hx, hy)
+    print(f"CPU count: {packed} points for the packed rerun, {full} for the full rerun", flush=True)
+    assert packed >= 50 and full >= 50
+    _, tot, pp, nonfin, ref = run_grid(x, y, hx, hy)
+    assert nonfin == 0
+    check(tot, pp, ref)
+    _, _, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    t = torch.empty(256, dtype=torch.float64, device="cuda")
+    cde().launch_batch([(m, 0, 1024, None, None)], hx, hy)
+    cde().launch_batch([(m, 1024, 2000, t, None)], hx, hy)
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy(), tot)
+    m.close()
+
+
 @pytest.mark.parametrize("variant", ["valu_fp32", "mfma_bf16x3"])
 def test_grid_distance_variants_reported(variant):
     # dx = 16 options that form x-distances approximately (FP32 differences,

@@ -34,6 +34,11 @@ class FakeExecutor(Executor):
     def job_points(self, r):
         return self.sizes.get(r.rid, 1000)
 
+    def round_points(self, r):
+        return self.round
+
+    round = 256
+
     def _h(self, kind, reqs):
         if any(r.rid == self.fail_rid for r in reqs):
             raise RuntimeError("injected launch failure")
@@ -126,15 +131,18 @@ def test_large_jobs_in_arrival_order_small_jobs_ride_along():
     clock = FakeClock()
     sizes = {0: 200_000, 1: 150_000, 2: 2_000, 3: 60_000}
     ex = FakeExecutor(clock, latency=0.01, sizes=sizes, rate=2e13)
+    ex.round = 4096
     s = Scheduler(ex, hbm_budget=10_000, batched=True, clock=clock, tick_pairs=2e12)
     s.submit_all([ServeRequest(0, "job", 0.0), ServeRequest(1, "job", 0.1), ServeRequest(2, "job", 0.2),
                   ServeRequest(3, "job", 0.3)])
     drive(s, clock, step=0.01)
-    # every job's ranges cover [0, n) in order, 256-aligned inside
+    # every job's ranges cover [0, n) in order, inner boundaries at whole
+    # rounds of the device (4096 points here)
     for rid, n in sizes.items():
         rs = ex.ranges[rid]
         assert rs[0][0] == 0 and rs[-1][1] == n
-        assert all(a[1] == b[0] and a[1] % 256 == 0 for a, b in zip(rs, rs[1:]))
+        assert all(a[1] == b[0] and a[1] % 4096 == 0 for a, b in zip(rs, rs[1:]))
+    assert len(ex.ranges[0]) > 2  # the first large job was split
     done = {r.rid: r.t_done for r in s.completed}
     # the small job, on its own lane, finishes right after it arrives
     assert done[2] <= 0.2 + 0.02
@@ -193,6 +201,40 @@ def test_slot_limit_and_rejection():
     assert [r.rid for r in s.rejected] == [50]
     starts = sorted(t for _, its, t, _ in ticks(ex) for _ in its)
     assert starts[:2] == [0.0, 0.0] and starts[2] >= 1.0
+
+
+def test_queries_do_not_wait_for_job_slots():
+    # two job slots, both taken by long jobs with two more queued: a query
+    # that arrives meanwhile is admitted and launched at once
+    clock = FakeClock()
+    ex = FakeExecutor(clock, latency=2.0)
+    s = Scheduler(ex, hbm_budget=10_000, max_active=2, batched=True, clock=clock)
+    s.submit_all([ServeRequest(i, "job", 0.0) for i in range(4)] +
+                 [ServeRequest(9, "query", 0.5, set_id=0, xq=np.zeros((2, 1), np.float32))])
+    drive(s, clock)
+    qstart = [t for kind, rids, t, *_ in ex.launches if kind == "query" and 9 in rids]
+    assert qstart == [0.5]
+    starts = {}
+    for _, its, t, _ in ticks(ex):
+        for rid, _, _ in its:
+            starts.setdefault(rid, t)
+    assert starts[0] == 0.0 and starts[1] == 0.0 and starts[2] >= 2.0 and starts[3] >= 2.0
+    assert s.active == 0 and s.active_kind == {"job": 0, "query": 0}
+
+
+def test_memory_is_granted_in_arrival_order():
+    # job 1 waits for memory: the younger query does not take memory before
+    # it (no starvation of large requests by a stream of small ones)
+    clock = FakeClock()
+    ex = FakeExecutor(clock, latency=2.0)
+    s = Scheduler(ex, hbm_budget=150, max_active=64, batched=True, clock=clock)
+    s.submit_all([ServeRequest(0, "job", 0.0), ServeRequest(1, "job", 0.0),
+                  ServeRequest(9, "query", 0.25, set_id=0, xq=np.zeros((2, 1), np.float32))])
+    drive(s, clock)
+    start1 = min(t for _, its, t, _ in ticks(ex) if any(it[0] == 1 for it in its))
+    qstart = [t for kind, rids, t, *_ in ex.launches if kind == "query"][0]
+    assert start1 >= 2.0 and qstart >= start1
+    assert len(s.completed) == 3 and all(r.error is None for r in s.completed)
 
 
 @pytest.mark.parametrize("batched", [True, False])
