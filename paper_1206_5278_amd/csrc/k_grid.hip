@@ -10,39 +10,47 @@
 // distances d2x_ij, d2y_ij times per-bandwidth coefficients, so
 //     num_i[a][b] = sum_j ex_a(i,j) * ey_b(i,j)
 // is, for each i, a dense contraction over j of an [Gx x J] matrix with a
-// [J x Gy] matrix: it runs on the matrix cores (v_mfma_f64_16x16x4f64),
-// while the VALU forms the distances and only Gx + Gy kernel values per pair
-// (not Gx * Gy).
+// [J x Gy] matrix: the products and sums run on the matrix cores, while the
+// VALU forms the distances and only Gx + Gy kernel values per pair (not
+// Gx * Gy).
 //
-// Range and precision: every exponent is taken relative to the point's
-// nearest x-neighbour distance m_i and nearest y-neighbour distance my_i
-// (over j != i, computed once per model by k_nn with the same FP32 formula):
+// Range: every exponent is taken relative to the point's nearest x-neighbour
+// distance m_i and nearest y-neighbour distance my_i (over j != i, computed
+// once per model by k_nn with the FP64 formula):
 //     ex_a = 2^-((d2x - m_i) c_a),  ey_b = 2^-((d2y - my_i) c'_b),
-// so ex <= 1 with ex = 1 at the x-neighbour (den' >= 1) and ey <= 1.  Over a
-// whole grid the largest term of a cell can still be hundreds of binary
-// orders below 1 (small hx with small hy), which FP32 cannot hold; so each
-// kernel value is formed as v_exp_f32 of the fractional part of its exponent
-// (FP32 accuracy) scaled exactly by a power of two in FP64, and the products
-// and sums over j run in FP64 on the matrix cores.  The shifts cancel in the
-// ratio and are restored in FP64 by the finalisation.  An entry whose
-// shifted num' is below 2^-1000 is recomputed exactly by k_grid_fixup with a
-// per-entry shift.
+// so ex <= 1 with ex = 1 at the x-neighbour (den' >= 1) and ey <= 1.  The
+// shifts cancel in the ratio and are restored in FP64 by the finalisation.
 //
-// Cross-term option (dx = 16, CDE_XTERM_MFMA_BF16X3): the x-distances are
-// formed as |u_i|^2 + |u_j|^2 - 2 u_i.u_j on coordinates centred by the data
-// mean, with the cross term u_i.u_j of each wave's 8 points against a whole
-// 256-point j-tile computed on the matrix cores as a split-bf16 product
-// (u = hi + lo in bf16; hi.hi + hi.lo + lo.hi accumulated in FP32 by
-// v_mfma_f32_16x16x16_bf16) and staged in LDS.  This trades the 16 FP64
-// differences per pair for an approximation whose error grows with |u|^2 /
-// h^2; it is reported against the oracle, not gated.
+// Passes (see the kernels for details):
+//   1. the FP32 pass over all points (k_loo_grid32: one 16 x 16 grid tile per
+//      block on v_mfma_f32_16x16x4f32; k_loo_grid32q: 32 x 32 quads on
+//      v_mfma_f32_32x32x2f32), the tile of the smallest bandwidths with
+//      biased exponents, FP32 tile sums folded into Kahan-compensated totals;
+//   2. k_grid_finalize flags the (tile, point) pairs with a cell whose
+//      shifted num' is too small for FP32 to have carried it, and
+//      k_compact_points lists them; those are recomputed with FP64 kernel
+//      values (v_exp_f32 of the fractional exponent scaled exactly by a power
+//      of two) on v_mfma_f64_16x16x4f64: four points per product step when
+//      their flagged cells lie in the tile's first 4 x 4 cells
+//      (k_loo_grid_packed), one per step otherwise (k_loo_grid);
+//   3. entries still below 2^-1000 are recomputed exactly with a per-entry
+//      shift (k_grid_fixup), and k_grid_rows sums each setting in a fixed
+//      order.
 //
-// Work decomposition: a 256-lane block owns 32 points (8 per wave) and one
-// 16 x 16 tile of the (padded) grid (blockIdx.y); j streams through LDS in
-// 256-point tiles.  Lane l of a wave forms the distance of point i0 + l%8 to
-// tile row 4*((l%16)/8) + l/16 of the current 8-row group; a DPP row
-// broadcast (row_newbcast) then hands each MFMA operand lane the pair it
-// needs, so every distance is computed once per tile of the grid.
+// x-distance options (dx = 16): FP32 differences (CDE_XTERM_VALU_F32), or
+// |u_i|^2 + |u_j|^2 - 2 u_i.u_j on coordinates centred by the data mean with
+// the cross term of each block's points against a whole 256-point j-tile
+// computed on the matrix cores as a split-bf16 product (u = hi + lo;
+// hi.hi + hi.lo + lo.hi accumulated in FP32 by v_mfma_f32_16x16x16_bf16) and
+// staged in LDS (CDE_XTERM_MFMA_BF16X3).  Both trade exact FP64 differences
+// for approximations whose errors the tests report and bound.
+//
+// Work decomposition: a 256-lane block owns a group of points and one grid
+// tile (blockIdx.y); j streams through LDS in 256-point tiles.  Each lane
+// forms the FP64 distance of one (point, row) pair of the current row group,
+// and a cross-lane move (ds_bpermute, or a DPP row broadcast folded into the
+// multiply at dx = 16) hands each MFMA operand lane the pair it needs, so
+// every distance is computed once per tile of the grid.
 #include <type_traits>
 
 #include "cde_device.h"
