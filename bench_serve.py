@@ -54,9 +54,11 @@ def job_pairs(r):
     return float(n) * (n - 1) * len(r.hx) * len(r.hy)
 
 
-def run_mode(executor, reqs, batched, budget, deadline, progress=None):
+def run_mode(executor, reqs, batched, budget, deadline, progress=None, **sched):
+    """One run of `reqs` through a Scheduler; `sched` overrides its settings
+    (tick_pairs, ticks_in_flight, small_job_points)."""
     from paper_1206_5278_amd.serve import Scheduler
-    s = Scheduler(executor, hbm_budget=budget, max_active=64, batched=batched)
+    s = Scheduler(executor, hbm_budget=budget, max_active=64, batched=batched, **sched)
     s.submit_all(reqs)
     t0 = time.perf_counter()
     s.run(deadline=deadline, progress=progress)
@@ -108,6 +110,10 @@ def main():
     ap.add_argument("--sweep", type=str, default="",
                     help="comma-separated extra arrival rates, each run for --sweep-duration")
     ap.add_argument("--sweep-duration", type=float, default=60.0)
+    ap.add_argument("--tick-pairs", type=float, default=None,
+                    help="batched mode: pair evaluations per large-job range (scheduler default if unset)")
+    ap.add_argument("--ticks-in-flight", type=int, default=None,
+                    help="batched mode: large-job ranges in flight (scheduler default if unset)")
     ap.add_argument("--progress", type=float, default=30.0,
                     help="seconds between status lines on stderr (0: none)")
     args = ap.parse_args()
@@ -121,17 +127,19 @@ def main():
     reqs = build_requests(stream, sets, seed=args.seed, n_cap=args.n_cap)
     ex = GpuExecutor(sets)
     budget = int(args.budget_gb * (1 << 30))
+    sched = {k: v for k, v in (("tick_pairs", args.tick_pairs), ("ticks_in_flight", args.ticks_in_flight))
+             if v is not None}
     # warm-up: one small job and one query through every code path
     run_mode(ex, copy.deepcopy(reqs[:4]), True, budget, 60.0)
 
     out = {"metric": "serving throughput and p50/p99 latency, continuous batching vs one request per launch",
-           "data": "synthetic", "dtype": "f32 kernel values, f64 accumulation"}
+           "data": "synthetic", "dtype": "f32 kernel values, f64 accumulation", "scheduler": sched}
     if not args.no_main:
         res = {}
         results = {}
         for mode, batched in (("plain", False), ("batched", True)):
             rep, o = run_mode(ex, copy.deepcopy(reqs), batched, budget, args.deadline,
-                              progress=args.progress or None)
+                              progress=args.progress or None, **(sched if batched else {}))
             res[mode] = rep
             results[mode] = o
             print(f"{mode}: {json.dumps(rep)}", file=sys.stderr, flush=True)
@@ -154,7 +162,7 @@ def main():
             outs = {}
             for mode, batched in (("plain", False), ("batched", True)):
                 rep, outs[mode] = run_mode(ex, copy.deepcopy(rq), batched, budget, args.deadline,
-                                           progress=args.progress or None)
+                                           progress=args.progress or None, **(sched if batched else {}))
                 row[mode] = {k: rep[k] for k in ("throughput_req_s", "p50_s", "p99_s", "makespan_s",
                                                  "completed", "failed", "unfinished")}
                 row[mode]["job_p50_s"] = rep["job"]["p50_s"]
