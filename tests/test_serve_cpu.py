@@ -249,6 +249,7 @@ def test_failed_launch_fails_only_its_request(batched):
     assert sum(1 for r in s.completed if r.error is None) == 8
     rep = s.report(1.0)
     assert rep["failed"] == 1 and rep["completed"] == 8 and rep["unfinished"] == 0
+    assert s.active == 0 and s.active_kind == {"job": 0, "query": 0} and s.used == 0
 
 
 def test_queries_arriving_during_a_batch_join_the_next_batch():
