@@ -204,6 +204,10 @@ typedef struct cde_work_item {
  * models: every stage of the grid pass runs as one launch over all items
  * (per 8 items), so many small bandwidth-selection jobs, and the slices of
  * large ones, share the device in one kernel instead of one launch each.
+ * A range runs the FP32 pass over its points and lists the ones that need
+ * FP64 recomputation; the recomputation, the finalisation and the sums run
+ * once per model, in the call whose range ends at n, over the whole model
+ * (so a model's last range costs more than its others).
  *   items [n_items], 1 <= n_items <= 512: all models FP32, with the same dx
  *     and dy and on the same device, each model at most once per call.
  *   hx [n_hx], hy [n_hy]: one grid for all items, 1 <= n_hx, n_hy <= 16.

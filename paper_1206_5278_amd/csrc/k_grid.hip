@@ -1510,14 +1510,16 @@ __device__ __forceinline__ int batch_item(const GridBatch& b, int bx)
     return k;
 }
 
-// per item (blockIdx.y): clear the flags of its range and its list and queue counters
+// per item (blockIdx.y): clear the flags of its range and the fixup queue
+// counter; the lists of flagged points are cleared by a model's first range
+// only, since every range of the model appends to them
 __global__ void k_batch_zero(GridBatch b)
 {
     const GridBatchItem& t = b.it[blockIdx.y];
     const int i = t.p0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (i < t.p1) t.w.flags[i] = 0;
     if (blockIdx.x == 0 && threadIdx.x < 64) {
-        t.w.pcount[threadIdx.x] = 0;
+        if (t.p0 == 0) t.w.pcount[threadIdx.x] = 0;
         if (threadIdx.x == 0) *t.w.fix_count = 0;
     }
 }
@@ -1642,21 +1644,35 @@ static hipError_t grid_batch_t(const GridBatch& all, const bool* do_nn, const Gr
                        crit);
     hipLaunchKernelGGL(k_compact_batch, dim3((unsigned)blocks), dim3(256), 0, stream, b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // The rest runs once per model, with the range that ends it, over the
+    // whole model: every range has appended its flagged points to the
+    // model's lists, so the FP64 reruns run once, well filled, instead of
+    // once per range; then the finalisation of all points (FP64 values where
+    // rerun), the fixup queue and the row sums.  Each point's arithmetic is
+    // the one-model launch's, so the totals stay bit-identical.
+    GridBatch lb = all;
+    lb.count = 0;
+    for (int k = 0; k < all.count; ++k)
+        if (all.it[k].p1 == all.it[k].npad) {
+            lb.it[lb.count] = all.it[k];
+            lb.it[lb.count++].p0 = 0;
+        }
+    if (lb.count == 0) return hipSuccess;
     // FP64 rerun of flagged points: the packed rerun (16 points per block),
     // then the full rerun with the points-per-wave rule of the one-model
     // launch (2 up to 2^18 rows, else 8), one launch per rule
     {
-        GridBatch pb = all;
+        GridBatch pb = lb;
         const int pblocks = batch_prefix(pb, 16);
         hipLaunchKernelGGL((k_rerun_packed_batch<DX, DY>), dim3((unsigned)pblocks), dim3(TILE), 0, stream, pb,
                            ga);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     for (int pwf : {2, 8}) {
-        GridBatch rb = all;
+        GridBatch rb = lb;
         rb.count = 0;
-        for (int k = 0; k < all.count; ++k)
-            if ((all.it[k].npad <= (1 << 18)) == (pwf == 2)) rb.it[rb.count++] = all.it[k];
+        for (int k = 0; k < lb.count; ++k)
+            if ((lb.it[k].npad <= (1 << 18)) == (pwf == 2)) rb.it[rb.count++] = lb.it[k];
         if (rb.count == 0) continue;
         const int rblocks = batch_prefix(rb, 4 * pwf);
         if (pwf == 2)
@@ -1665,21 +1681,15 @@ static hipError_t grid_batch_t(const GridBatch& all, const bool* do_nn, const Gr
             hipLaunchKernelGGL((k_rerun_batch<DX, DY, 8>), dim3((unsigned)rblocks), dim3(TILE), 0, stream, rb, ga);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_finalize_batch<false>, dim3((unsigned)blocks, (unsigned)G), dim3(256), 0, stream, b, gf,
+    const int lblocks = batch_prefix(lb, 256);
+    hipLaunchKernelGGL(k_finalize_batch<false>, dim3((unsigned)lblocks, (unsigned)G), dim3(256), 0, stream, lb, gf,
                        crit);
-    hipLaunchKernelGGL((k_fixup_batch<DX, DY>), dim3(BATCH_FIX_BLOCKS, (unsigned)all.count), dim3(TILE), 0,
-                       stream, all, ga, gf, crit);
+    hipLaunchKernelGGL((k_fixup_batch<DX, DY>), dim3(BATCH_FIX_BLOCKS, (unsigned)lb.count), dim3(TILE), 0,
+                       stream, lb, ga, gf, crit);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    GridBatch lb = all;
-    lb.count = 0;
-    for (int k = 0; k < all.count; ++k)
-        if (all.it[k].p1 == all.it[k].npad) lb.it[lb.count++] = all.it[k];
-    if (lb.count > 0) {
-        hipLaunchKernelGGL(k_rows_batch, dim3((unsigned)G, (unsigned)lb.count), dim3(256), 0, stream, lb);
-        hipLaunchKernelGGL(k_counts_batch, dim3(1), dim3(64), 0, stream, lb, G);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    hipLaunchKernelGGL(k_rows_batch, dim3((unsigned)G, (unsigned)lb.count), dim3(256), 0, stream, lb);
+    hipLaunchKernelGGL(k_counts_batch, dim3(1), dim3(64), 0, stream, lb, G);
+    return hipGetLastError();
 }
 
 template <int DX, int DY>
