@@ -148,9 +148,9 @@ class Scheduler:
         # grouped job ticks: pair evaluations per tick (n_range * n * cells),
         # the size up to which a job rides along whole, ticks kept in flight.
         # Ranges are whole rounds of the device (executor.round_points) and
-        # about tick_pairs each: every range costs a fixed ~7 ms besides its
-        # work (a 200k-point job: 346 ms whole; in ranges of 1, 2, 4 and 7
-        # rounds of 16,384 points 445, 395, 370 and 354 ms), while a shorter
+        # about tick_pairs each: every range costs 2-3 ms besides its work
+        # (a 200k-point dx = 3 job: 307 ms whole; in ranges of 1, 2, 4 and 7
+        # rounds of 16,384 points 341, 326, 317 and 310 ms), while a shorter
         # launch lets queries reach the device sooner.  The default splits a
         # 200k-point 16 x 16 job into three or four ranges.  A second tick in
         # flight keeps the device busy with job blocks back to back; at
