@@ -1470,8 +1470,11 @@ size_t grid_work_bytes(const cde_model* m, int n_hx, int n_hy)
 // GridBatch::pre and runs the same device function, on the same per-point
 // arithmetic, as the one-model launch: each point's values are therefore
 // bit-identical to cde_loo_loglik's, whatever the list holds.  A model's
-// ranges run in order (their work buffers carry over between launches); the
-// item that ends a model also sums its rows into the totals.
+// ranges run in order (their work buffers carry over between launches): each
+// range runs the FP32 pass over its points and appends its flagged points
+// to the model's lists, and the item that ends a model runs the FP64 reruns,
+// the finalisation and the fixup over the whole model and sums its rows
+// into the totals.
 
 constexpr int GRID_BATCH_MAX = 8;  // items per launch
 
