@@ -103,6 +103,9 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--duration", type=float, default=10.0)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--stream-seed", type=int, default=None,
+                    help="seed of the main stream (default --seed; bench.py's short stream is --seed 0 "
+                         "--stream-seed 5 --rate 50 --duration 20)")
     ap.add_argument("--n-cap", type=int, default=None, help="cap job sizes (smoke runs)")
     ap.add_argument("--budget-gb", type=float, default=96.0)
     ap.add_argument("--deadline", type=float, default=600.0)
@@ -122,9 +125,10 @@ def main():
     from paper_1206_5278_amd.serve import GpuExecutor
 
     sets = workloads.resident_sets(8, seed=args.seed)
+    sseed = args.seed if args.stream_seed is None else args.stream_seed
     stream = workloads.serve_stream(rate=args.rate, duration=args.duration if not args.no_main else 0.5,
-                                    seed=args.seed)
-    reqs = build_requests(stream, sets, seed=args.seed, n_cap=args.n_cap)
+                                    seed=sseed)
+    reqs = build_requests(stream, sets, seed=sseed, n_cap=args.n_cap)
     ex = GpuExecutor(sets)
     budget = int(args.budget_gb * (1 << 30))
     sched = {k: v for k, v in (("tick_pairs", args.tick_pairs), ("ticks_in_flight", args.ticks_in_flight))
