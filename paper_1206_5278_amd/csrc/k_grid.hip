@@ -158,8 +158,8 @@ __device__ __forceinline__ void own_f64(double (&dst)[S], const float* src)
 // and branch cost more than the FP64 formula it saves.)
 
 template <int DX, int DY>
-__device__ __forceinline__ void nn_body(int bx, const float* __restrict__ pts, int n,
-                                        double* __restrict__ nn, int npad)
+__device__ __forceinline__ void nn_body(int bx, int chunk, int nchunks, const float* __restrict__ pts,
+                                        int n, double* __restrict__ nn, int npad)
 {
     constexpr int S = row_stride(DX, DY);
     __shared__ float tile[TILE * S];
@@ -173,7 +173,9 @@ __device__ __forceinline__ void nn_body(int bx, const float* __restrict__ pts, i
     ScreenedMin sx, sy;
     double mx = inf_<double>(), my = inf_<double>();
     const int ntiles = (n + TILE - 1) / TILE;
-    for (int t = 0; t < ntiles; ++t) {
+    const int tpc = (ntiles + nchunks - 1) / nchunks;
+    const int t0 = chunk * tpc, t1 = min(ntiles, t0 + tpc);
+    for (int t = t0; t < t1; ++t) {
         __syncthreads();
         float pre[S];
         load_row<S>(pre, pts + ((size_t)t * TILE + tid) * S);
@@ -218,15 +220,39 @@ __device__ __forceinline__ void nn_body(int bx, const float* __restrict__ pts, i
             }
         }
     }
-    nn[i] = mx;
-    nn[npad + i] = my;
+    // the minima of the chunks combine through an integer atomic min on the
+    // bit patterns (non-negative doubles order like their bits): exact and
+    // independent of the order; nn starts at +inf (k_nn_init)
+    atomicMin((unsigned long long*)(nn + i), (unsigned long long)__double_as_longlong(mx));
+    atomicMin((unsigned long long*)(nn + npad + i), (unsigned long long)__double_as_longlong(my));
+}
+
+// j-tile chunks of the neighbour-shift pass: a point block streams every j
+// tile, so small sets would leave most of the device idle (a 16k-point job
+// has 64 point blocks); chunks bring the launch to about 2048 blocks.  A
+// function of n only.
+static int nn_chunks(int64_t n)
+{
+    const int64_t ntiles = (n + TILE - 1) / TILE;
+    const int64_t c = (2048 + ntiles - 1) / ntiles;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(c, ntiles));
+}
+
+// nn[p0 .. p1) and nn[npad + p0 .. npad + p1) = +inf
+__global__ void k_nn_init(double* __restrict__ nn, int npad, int p0, int p1)
+{
+    const int i = p0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p1) {
+        nn[i] = inf_<double>();
+        nn[npad + i] = inf_<double>();
+    }
 }
 
 template <int DX, int DY>
 __global__ __launch_bounds__(TILE) void k_nn(const float* __restrict__ pts, int n,
                                              double* __restrict__ nn, int npad)
 {
-    nn_body<DX, DY>(blockIdx.x, pts, n, nn, npad);
+    nn_body<DX, DY>(blockIdx.x, blockIdx.y, gridDim.y, pts, n, nn, npad);
 }
 
 // Grid coefficients (base 2), padded to a multiple of 16 with copies of the
@@ -1237,8 +1263,10 @@ static hipError_t grid_t(const cde_model* m, const GridArgs& ga, const GridFin& 
     const double* nn = (const double*)m->nn;
     hipError_t e;
     if (!m->nn_ready) {
-        hipLaunchKernelGGL((k_nn<DX, DY>), dim3(nb), dim3(TILE), 0, stream, pts, n, (double*)m->nn,
-                           npad);
+        hipLaunchKernelGGL(k_nn_init, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, stream, (double*)m->nn,
+                           npad, 0, npad);
+        hipLaunchKernelGGL((k_nn<DX, DY>), dim3(nb, (unsigned)nn_chunks(n)), dim3(TILE), 0, stream, pts, n,
+                           (double*)m->nn, npad);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const int tiles = (ga.gxp / 16) * (ga.gyp / 16);
@@ -1494,6 +1522,7 @@ struct GridBatchItem {
     double* nn;        // [2][npad] neighbour shifts of the model
     int n, npad;
     int p0, p1;        // points [p0, p1); p1 = npad for the model's last range
+    int nn_chunks;     // j chunks of the neighbour-shift pass (nn_chunks(n))
     GridWork w;        // the model's grid work buffers
     double* totals;    // [G], written by the model's last range
     double* counts;    // [G] non-finite counts (model scratch)
@@ -1527,12 +1556,26 @@ __global__ void k_batch_zero(GridBatch b)
     }
 }
 
+// per item (blockIdx.y): the neighbour shifts of its range start at +inf
+__global__ void k_nn_init_batch(GridBatch b)
+{
+    const GridBatchItem& t = b.it[blockIdx.y];
+    const int i = t.p0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < t.p1) {
+        t.nn[i] = inf_<double>();
+        t.nn[t.npad + i] = inf_<double>();
+    }
+}
+
+// blocks of an item: (point block of its range) x (j chunk), chunk fastest
 template <int DX, int DY>
 __global__ __launch_bounds__(TILE) void k_nn_batch(GridBatch b)
 {
     const int k = batch_item(b, blockIdx.x);
     const GridBatchItem& t = b.it[k];
-    nn_body<DX, DY>(t.p0 / TILE + (blockIdx.x - b.pre[k]), t.pts, t.n, t.nn, t.npad);
+    const int local = blockIdx.x - b.pre[k];
+    nn_body<DX, DY>(t.p0 / TILE + local / t.nn_chunks, local % t.nn_chunks, t.nn_chunks, t.pts, t.n, t.nn,
+                    t.npad);
 }
 
 template <int DX, int DY, int PW>
@@ -1634,8 +1677,16 @@ static hipError_t grid_batch_t(const GridBatch& all, const bool* do_nn, const Gr
     for (int k = 0; k < all.count; ++k)
         if (do_nn[k]) nb.it[nb.count++] = all.it[k];
     if (nb.count > 0) {
-        const int blocks = batch_prefix(nb, TILE);
-        hipLaunchKernelGGL((k_nn_batch<DX, DY>), dim3((unsigned)blocks), dim3(TILE), 0, stream, nb);
+        int nmax = 0;
+        nb.pre[0] = 0;
+        for (int k = 0; k < nb.count; ++k) {
+            const int pts_k = nb.it[k].p1 - nb.it[k].p0;
+            nmax = std::max(nmax, pts_k);
+            nb.pre[k + 1] = nb.pre[k] + (pts_k + TILE - 1) / TILE * nb.it[k].nn_chunks;
+        }
+        hipLaunchKernelGGL(k_nn_init_batch, dim3((unsigned)((nmax + 255) / 256), (unsigned)nb.count), dim3(256), 0,
+                           stream, nb);
+        hipLaunchKernelGGL((k_nn_batch<DX, DY>), dim3((unsigned)nb.pre[nb.count]), dim3(TILE), 0, stream, nb);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     GridBatch b = all;
@@ -1760,6 +1811,7 @@ hipError_t launch_grid_batch(const GridRange* r, int count, const double* hx, in
             t.npad = (int)q.m->npad;
             t.p0 = (int)q.i0;
             t.p1 = q.i1 == q.m->n ? (int)q.m->npad : (int)q.i1;
+            t.nn_chunks = nn_chunks(q.m->n);
             if (!carve_grid_work(q.work, q.work_bytes, q.m->npad, n_hx, n_hy, t.w)) return hipErrorInvalidValue;
             t.totals = q.totals;
             t.counts = q.counts;
