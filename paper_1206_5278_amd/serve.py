@@ -9,7 +9,7 @@ Two request kinds:
              resident training sets (``cde_density_query``).
 
 Scheduling (one scheduler thread, ``tick`` is one pass):
-  1. arrivals whose time has come enter the waiting queue (FIFO);
+  1. arrivals whose time has come enter the waiting queue of their kind;
   2. admission: each request kind (job, query) has its own FIFO queue and
      its own slots, so queries never wait for a slot behind queued jobs;
      device memory is granted in arrival order across both queues (the
