@@ -108,10 +108,14 @@ typedef enum {
                                  differences, FP64 squares and sums); the parity path */
     CDE_XTERM_MFMA_BF16X3 = 2,/* dx = 16: |u_i|^2 + |u_j|^2 - 2 u_i.u_j on mean-centred
                                  coordinates u, the cross term from a split-bf16 x3 MFMA
-                                 product (hi.hi + hi.lo + lo.hi, FP32 accumulate); an
-                                 approximation whose error is reported, not gated */
+                                 product (hi.hi + hi.lo + lo.hi, FP32 accumulate), in the
+                                 FP32 pass and in the FP64 rerun of flagged points; an
+                                 approximation whose error the tests bound at its measured
+                                 size, above the parity tolerance */
     CDE_XTERM_VALU_F32 = 3    /* dx = 16: the differences, squares, sums and neighbour shift in
-                                 FP32 on the VALU; an approximation, reported, not gated */
+                                 FP32 on the VALU, in the FP32 pass (flagged points are rerun
+                                 with FP64 differences); an approximation, bounded like the
+                                 above */
 } cde_xterm;
 
 /* ABI version of the loaded library (CDE_ABI_VERSION at build time). */
@@ -179,8 +183,8 @@ size_t cde_workspace_bytes(int64_t n, int32_t dx, int32_t dy, cde_precision prec
  *   per-point outputs stay in the caller's point order).
  *   xterm: CDE_XTERM_MFMA_BF16X3 and CDE_XTERM_VALU_F32 are accepted for
  *   dx = 16, FP32 data and the Gaussian kernel only (CDE_EUNSUPPORTED
- *   otherwise); both change only how the FP32 pass and the FP64 rerun of
- *   flagged points form x-distances.
+ *   otherwise); they change only how x-distances are formed (see
+ *   cde_xterm).
  *   Limits: n_hx, n_hy in [1, 64]. */
 cde_status cde_loo_loglik(cde_model* m, const double* hx, int32_t n_hx, const double* hy,
                           int32_t n_hy, cde_criterion criterion, cde_kernel kernel,
