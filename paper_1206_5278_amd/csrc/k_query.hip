@@ -6,7 +6,7 @@
 //     F[q][g] = sum_i w(q, i) k(i, g),
 // a dense contraction over the training points of a [Q x n] matrix of
 // x-kernels with an [n x k] matrix of y-kernels.  It runs on
-// v_mfma_f32_16x16x4f32: per training point, one x-kernel value per query and
+// v_mfma_f32_32x32x2f32: per training point, one x-kernel value per query and
 // one y-kernel value per grid point are formed on the VALU (not one product
 // kernel per (q, g)).
 //
@@ -20,16 +20,17 @@
 // query's peak is not carried to full relative precision (FP32 range); such
 // tail values are far below the accuracy floor of a density estimate.
 //
-// Work decomposition: a 512-lane block owns 128 queries (16 per wave), a chunk
-// of 64, 128 or 256 grid points (blockIdx.y) and a chunk of training points
-// (blockIdx.z).  The y-kernel values of a panel of 32 training points and
-// the block's grid points are formed once per block in LDS and read by all
-// eight waves as MFMA B operands; the x-kernel values are formed per wave.
-// Chunk partial sums (FP32 numerators, FP64 denominators) are combined in
-// FP64 in a fixed order by k_query_reduce.  The training-point chunks depend
-// on n alone and every query row is accumulated on its own, so a query's
-// result does not depend on which other queries share its launch; large
-// batches run in slices of queries that bound the partial storage.
+// Work decomposition: a 512-lane block owns 128 queries, a chunk of 64, 128
+// or 256 grid points (blockIdx.y) and a chunk of training points
+// (blockIdx.z).  For each panel of 32 training points, the x-kernel values of
+// the block's queries and the y-kernel values of its grid points are formed
+// once per block in LDS and read by the eight waves as MFMA operands (wave w:
+// 32 queries by half of the grid points).  Chunk partial sums (FP32
+// numerators, FP64 denominators) are combined in FP64 in a fixed order by
+// k_query_reduce.  The training-point chunks depend on n alone and every
+// query row is accumulated on its own, so a query's result does not depend on
+// which other queries share its launch; large batches run in slices of
+// queries that bound the partial storage.
 #include <type_traits>
 
 #include "cde_device.h"
@@ -39,7 +40,7 @@ namespace cde {
 
 namespace {
 
-typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr float QEXCLUDED = 1e20f;
 
@@ -227,19 +228,49 @@ __global__ __launch_bounds__(TILE) void k_qshift_y(const float* __restrict__ pts
 }
 
 // Numerator and denominator partials of one chunk of training points for
-// 128 queries (8 waves of 16) and GW = 16 GT grid points.  The training tile
-// is staged in LDS as doubles; for each panel of 32 of its points the block
-// first writes the y-kernel values k'(i, g) of all GW grid points to LDS
-// (computed once per block, shared by the eight waves), then each wave runs
-// 4-point MFMA steps: A = the x-kernel values w'(q, i) of its 16 queries
-// (lane % 16 = query, lane / 16 = point), B = the y-kernel values read from
-// LDS (lane / 16 = point, lane % 16 = grid column).  Each panel's MFMA sums
-// (8 roundings) are added into FP32 chunk sums (at most 64 panels), so a
-// chunk partial carries a relative error of at most about 72 x 2^-24 of its
-// all-positive terms; chunks are combined in FP64.
-constexpr int QWAVES = 8;            // waves per query block
-constexpr int QNT = 64 * QWAVES;     // threads per query block
-constexpr int QPB = 16 * QWAVES;     // queries per query block
+// 128 queries and GW = 64 GT grid points.  The training tile is staged in LDS
+// as doubles.  For each panel of 32 of its points the block writes to LDS the
+// x-kernel values w'(q, i) of its 128 queries and the y-kernel values k'(i, g)
+// of its GW grid points, each formed once per block.  Wave w then owns the 32
+// queries 32 (w % 4) .. and the GT column tiles of half w / 4 of the grid
+// points, and runs 2-point v_mfma_f32_32x32x2f32 steps: A = w' (lane % 32 =
+// query, lane / 32 = point), B = k' (lane / 32 = point, lane % 32 = column).
+// Each panel's MFMA sums (16 steps) are added into FP32 chunk sums (at most 64
+// panels), so a chunk partial carries a relative error of at most about
+// 96 x 2^-24 of its all-positive terms; chunks are combined in FP64.
+constexpr int QWAVES = 8;         // waves per query block
+constexpr int QNT = 64 * QWAVES;  // threads per query block
+constexpr int QPB = 128;          // queries per query block
+
+template <int GT>
+struct QPanelB;  // a lane's GT consecutive y-kernel values (one per column tile)
+template <>
+struct QPanelB<1> {
+    float v[1];
+    __device__ __forceinline__ void load(const float* p) { v[0] = p[0]; }
+};
+template <>
+struct QPanelB<2> {
+    float v[2];
+    __device__ __forceinline__ void load(const float* p)
+    {
+        const float2 t = *(const float2*)p;
+        v[0] = t.x;
+        v[1] = t.y;
+    }
+};
+template <>
+struct QPanelB<4> {
+    float v[4];
+    __device__ __forceinline__ void load(const float* p)
+    {
+        const float4 t = *(const float4*)p;
+        v[0] = t.x;
+        v[1] = t.y;
+        v[2] = t.z;
+        v[3] = t.w;
+    }
+};
 
 template <int DX, int DY, int GT>
 __global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pts, int n, int chunk,
@@ -251,44 +282,55 @@ __global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pt
                                                      double* __restrict__ dpart)
 {
     constexpr int S = row_stride(DX, DY), SD = DX + DY;
-    constexpr int GW = 16 * GT;
-    // LDS row of y-kernel values, padded to 16 (mod 32 and mod 64 in {16, 48}):
-    // the four 16-lane groups of a B read then fall in disjoint banks.
-    constexpr int YS = (GW % 32 == 16) ? GW : GW + 16;
-    constexpr int SUB = 32;
-    constexpr int PSTEP = QNT / GW;   // panel rows filled per pass of the block
-    constexpr int YPT = SUB / PSTEP;  // y-kernel values per thread per panel
-    static_assert(QNT % GW == 0 && SUB % PSTEP == 0, "grid width must divide the block");
+    constexpr int GWW = 32 * GT;  // grid columns per wave
+    constexpr int GW = 2 * GWW;   // grid columns per block
+    constexpr int SUB = 32;       // training points per panel
+    // LDS rows padded by 32 floats: the two 32-lane halves of a wave, which
+    // read consecutive rows, start 128 bytes apart in the banks.
+    constexpr int YS = GW + 32, XS = QPB + 32;
+    constexpr int YSTEP = QNT / GW, YPT = SUB / YSTEP;   // y panel rows: per pass, per thread
+    constexpr int XSTEP = QNT / QPB, XPT = SUB / XSTEP;  // x panel rows: per pass, per thread
+    static_assert(QNT % GW == 0 && SUB % YSTEP == 0 && SUB % XSTEP == 0, "panel shape");
+    static_assert(YS % 4 == 0 && GWW % 4 == 0, "B vector reads stay aligned");
+    static_assert(TILE * SD >= QNT, "the tile area holds the denominator reduction");
     __shared__ double tile[TILE * SD];
-    __shared__ float ykv[SUB * YS];
+    __shared__ __align__(16) float ykv[SUB * YS];  // [point][position]; position = half, then GT n + t
+    __shared__ float xkv[SUB * XS];  // [point][query]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int q0 = blockIdx.x * QPB + wave * 16;
+    const int q0 = blockIdx.x * QPB;
     const int g0 = blockIdx.y * GW;
     const int c = blockIdx.z;
-    const int kr = lane >> 4;
 
-    // A role: query q0 + lane % 16
-    const int qi = min(q0 + (lane & 15), q - 1);
+    // x-kernel role: query q0 + tid % QPB, panel rows tid / QPB + XSTEP r
+    const int xcol = tid % QPB, xrow = tid / QPB;
+    const int qi = min(q0 + xcol, q - 1);
     double xo[DX];
 #pragma unroll
     for (int kk = 0; kk < DX; ++kk) xo[kk] = (double)xq[(size_t)qi * DX + kk] * qa.sx[kk];
     const double m_q = mq[qi];
-    // y-kernel role: grid column tid % GW, panel rows tid / GW + PSTEP r
-    const int gcol = tid % GW;
-    const int gy = min(g0 + gcol, k - 1);
+    // y-kernel role: LDS position tid % GW, panel rows tid / GW + YSTEP r.
+    // Position h GWW + GT n + t holds grid column h GWW + 32 t + n, so a lane
+    // of half h reads its GT column tiles' values as one vector.
+    const int ypos = tid % GW, yrow = tid / GW;
+    const int yh = ypos / GWW, yr = ypos % GWW;
+    const int gy = min(g0 + yh * GWW + 32 * (yr % GT) + yr / GT, k - 1);
     double yo[DY];
 #pragma unroll
     for (int l = 0; l < DY; ++l) yo[l] = (double)yg[(size_t)gy * DY + l] * qa.sy[l];
     const double mu_g = mu[gy];
-    const int prow = tid / GW;
+    // MFMA role
+    const int qg = wave & 3, half = wave >> 2;
+    const int kr = lane >> 5, m32 = lane & 31;
+    const float* arow = xkv + kr * XS + 32 * qg + m32;
+    const float* brow = ykv + kr * YS + half * GWW + GT * m32;
 
     // Panel sums (MFMA, 32 points) are added into FP32 chunk sums; a chunk
     // holds at most 8 tiles (64 panels).
-    float tot[GT][4];
+    float tot[GT][16];
 #pragma unroll
     for (int t = 0; t < GT; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) tot[t][r] = 0.f;
+        for (int r = 0; r < 16; ++r) tot[t][r] = 0.f;
     double dtot = 0.0;
 
     const int j0 = c * chunk, j1 = min(n, j0 + chunk);
@@ -309,51 +351,54 @@ __global__ __launch_bounds__(QNT) void k_query_mfma(const float* __restrict__ pt
             // values <= 1 from the clamp; their x-kernel values are 0.
 #pragma unroll
             for (int r = 0; r < YPT; ++r) {
-                const int p = prow + PSTEP * r;
+                const int p = yrow + YSTEP * r;
                 const float a = (float)sdist2_shifted<DY>(yo, tile + (s0 + p) * SD + DX, mu_g);
-                ykv[p * YS + gcol] = exp2_<float>(-fmaxf(a, 0.f));
+                ykv[p * YS + ypos] = exp2_<float>(-fmaxf(a, 0.f));
+            }
+#pragma unroll
+            for (int r = 0; r < XPT; ++r) {
+                const int p = xrow + XSTEP * r;
+                const double d2 = sdist2_shifted<DX>(xo, tile + (s0 + p) * SD, m_q);
+                const float w = exp2_<float>(-(s0 + p < cnt ? (float)d2 : QEXCLUDED));
+                dp += w;
+                xkv[p * XS + xcol] = w;
             }
             __syncthreads();
-            v4f acc[GT];
-            // x-kernel value of a 4-point step; the next step's is formed
-            // before the current step's MFMAs are issued
-            auto weight = [&](int ii) {
-                const double d2 = sdist2_shifted<DX>(xo, tile + ii * SD, m_q);
-                const float xa = ii < cnt ? (float)d2 : QEXCLUDED;
-                return exp2_<float>(-xa);
-            };
-            float w = weight(s0 + kr);
+            v16f acc[GT];
 #pragma unroll
-            for (int s = 0; s < SUB; s += 4) {
-                const float wn = s + 4 < SUB ? weight(s0 + s + 4 + kr) : 0.f;
-                dp += w;
-                const float* brow = ykv + (s + kr) * YS + (lane & 15);
+            for (int s = 0; s < SUB; s += 2) {
+                const float a = arow[s * XS];
+                QPanelB<GT> b;
+                b.load(brow + s * YS);
 #pragma unroll
                 for (int t = 0; t < GT; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                        w, brow[16 * t], s == 0 ? v4f{0.f, 0.f, 0.f, 0.f} : acc[t], 0, 0, 0);
-                w = wn;
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b.v[t], s == 0 ? v16f{} : acc[t], 0, 0, 0);
             }
 #pragma unroll
             for (int t = 0; t < GT; ++t)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) tot[t][r] += acc[t][r];
+                for (int r = 0; r < 16; ++r) tot[t][r] += acc[t][r];
         }
         dtot += (double)dp;
     }
-    // den' partial of query q0 + lane%16: the four k-rows in a fixed order
-    double dsum = dtot;
-    dsum += __shfl_xor(dsum, 16, 64);
-    dsum += __shfl_xor(dsum, 32, 64);
-    if (blockIdx.y == 0 && lane < 16 && q0 + lane < q) dpart[(size_t)c * q + q0 + lane] = dsum;
-    // f32 16x16x4 result layout: register r holds query 4*(lane/16) + r,
-    // grid column lane%16
+    // den' partial of query q0 + xcol: the XSTEP row groups in a fixed order
+    __syncthreads();
+    tile[xrow * QPB + xcol] = dtot;
+    __syncthreads();
+    if (tid < QPB && blockIdx.y == 0 && q0 + tid < q) {
+        double dsum = tile[tid];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int qq = q0 + 4 * (lane >> 4) + r;
+        for (int r = 1; r < XSTEP; ++r) dsum += tile[r * QPB + tid];
+        dpart[(size_t)c * q + q0 + tid] = dsum;
+    }
+    // f32 32x32x2 result layout: register r of lane l holds row (query)
+    // 8 (r / 4) + 4 (l / 32) + r % 4 and column (grid point) l % 32
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int qq = q0 + 32 * qg + 8 * (r >> 2) + 4 * kr + (r & 3);
 #pragma unroll
         for (int t = 0; t < GT; ++t) {
-            const int g = g0 + 16 * t + (lane & 15);
+            const int g = g0 + half * GWW + 32 * t + m32;
             if (qq < q && g < k) fpart[((size_t)c * q + qq) * k + g] = tot[t][r];
         }
     }
@@ -384,11 +429,19 @@ int64_t query_chunk_points(int64_t n)
     return std::min<int64_t>(8, (ntiles + 255) / 256) * TILE;
 }
 
-// Grid tiles of 16 points per block: 4, 8 or 16 (a function of k only).
+// Grid tiles of 16 points per block of the Epanechnikov query: 4, 8 or 16
+// (a function of k only).
 int query_grid_tiles(int64_t k)
 {
     const int64_t nt = (k + 15) / 16;
     return nt <= 4 ? 4 : nt <= 8 ? 8 : 16;
+}
+
+// Column tiles of 32 grid points per wave of k_query_mfma: 1, 2 or 4, so a
+// block covers 64, 128 or 256 grid points (a function of k only).
+static int query_col_tiles(int64_t k)
+{
+    return k <= 64 ? 1 : k <= 128 ? 2 : 4;
 }
 
 // Queries per slice: chunk partials of one slice (k FP32 numerators and one
@@ -425,8 +478,8 @@ static hipError_t query_t(const cde_model* m, const float* xq, int q, const floa
     qa.log_cy = lcy;
     const int n = (int)m->n;
     const float* pts = (const float*)m->pts;
-    const int gt = query_grid_tiles(k);
-    const int gb = (k + 16 * gt - 1) / (16 * gt);
+    const int gt = query_col_tiles(k);
+    const int gb = (k + 64 * gt - 1) / (64 * gt);
     const int chunk = (int)query_chunk_points(n);
     const int nch = (n + chunk - 1) / chunk;
     const int qs = (int)query_slice(nch, q, k);
@@ -451,14 +504,14 @@ static hipError_t query_t(const cde_model* m, const float* xq, int q, const floa
         const dim3 grid(qb, gb, nch);
         const float* xs = xq + (size_t)q0 * DX;
         const double* mqs = mq + q0;
-        if (gt == 4)
-            hipLaunchKernelGGL((k_query_mfma<DX, DY, 4>), grid, dim3(QNT), 0, stream, pts, n, chunk, xs,
+        if (gt == 1)
+            hipLaunchKernelGGL((k_query_mfma<DX, DY, 1>), grid, dim3(QNT), 0, stream, pts, n, chunk, xs,
                                qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
-        else if (gt == 8)
-            hipLaunchKernelGGL((k_query_mfma<DX, DY, 8>), grid, dim3(QNT), 0, stream, pts, n, chunk, xs,
+        else if (gt == 2)
+            hipLaunchKernelGGL((k_query_mfma<DX, DY, 2>), grid, dim3(QNT), 0, stream, pts, n, chunk, xs,
                                qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
         else
-            hipLaunchKernelGGL((k_query_mfma<DX, DY, 16>), grid, dim3(QNT), 0, stream, pts, n, chunk, xs,
+            hipLaunchKernelGGL((k_query_mfma<DX, DY, 4>), grid, dim3(QNT), 0, stream, pts, n, chunk, xs,
                                qn, yg, k, qa, mqs, (const double*)mu, fpart, dpart);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int64_t total = (int64_t)qn * k;

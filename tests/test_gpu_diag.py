@@ -252,8 +252,8 @@ def test_query_parity_and_normalisation():
 
 @pytest.mark.parametrize("dx,dy", DIMS)
 def test_query_all_shapes(dx, dy):
-    # FP32 models: matrix-core query kernel; k = 150 spans two 128-point chunks
-    # and q = 70 two 64-query blocks with ragged tails.
+    # FP32 models: matrix-core query kernel; k = 150 fills part of one
+    # 256-point grid block and q = 70 part of one 128-query block.
     say(f"case: query shape dx={dx} dy={dy}")
     v = workloads.gmm_general(400, dx + dy, seed=200 + dx * 10 + dy)
     x, y = v[:, :dx], v[:, dx:]
