@@ -15,14 +15,16 @@
 // dense contraction:  Q_i = sum_l w_il M_il  with  M = W G  (W the x-kernel
 // matrix with a zero diagonal, G the symmetric y-convolution matrix).
 //
-// k_ise_mfma: a 512-lane block owns 128 rows i (16 per wave) and 256 columns
-// l, and runs over all training points j.  For each panel of 32 j the block
-// writes G'(j, l) for its 256 columns to LDS (once for all eight waves); each
-// wave then runs 4-point v_mfma_f32_16x16x4f32 steps with A = its own
-// x-kernel values w'(i, j) (lane % 16 = row, lane / 16 = j; zero for j = i)
-// and B = the panel.  Every 8 tiles of j (64 panels, FP32 sums) the block
-// folds sum_l w'(i, l) M_il into FP64 row sums (w'(i, i) = 0 leaves l = i
-// out).  Row sums of the column blocks are combined in a fixed order.
+// k_ise_mfma: a 512-lane block owns 128 rows i and 256 columns l, and runs
+// over all training points j.  For each panel of 32 j the block writes to LDS
+// the x-kernel values w'(i, j) of its 128 rows (zero for j = i) and G'(j, l)
+// of its 256 columns, each formed once per block; wave w then takes rows
+// 32 (w % 4) .. and the columns of half w / 4, and runs 2-point
+// v_mfma_f32_32x32x2f32 steps (A = w', lane % 32 = row, lane / 32 = j;
+// B = G', lane / 32 = j, lane % 32 = column).  Every 8 tiles of j (64
+// panels, FP32 sums) the block folds sum_l w'(i, l) M_il into FP64 row sums
+// (w'(i, i) = 0 leaves l = i out).  Row sums of the column halves and of the
+// column blocks are combined in a fixed order.
 //
 // Shifts: w'(i, j) = 2^-(d2x(i, j) - m_i) with m_i the exact FP64 minimum
 // over j != i (prepass k_ise_shift), so the nearest point has w' = 1 up to
@@ -39,13 +41,13 @@ namespace cde {
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr float IEXCL = 1e20f;     // exponent of an excluded pair (2^-1e20 = 0)
 constexpr int IWAVES = 8;          // waves per block
 constexpr int INT = 64 * IWAVES;   // threads per block
-constexpr int IPB = 16 * IWAVES;   // rows i per block
-constexpr int IGT = 16;            // column tiles of 16 per block
-constexpr int IGW = 16 * IGT;      // columns l per block
+constexpr int IPB = 128;           // rows i per block
+constexpr int IGW = 256;           // columns l per block
 constexpr int ISEG = 8;            // tiles of j per FP64 fold
 
 struct IseArgs {
@@ -152,24 +154,33 @@ __global__ __launch_bounds__(INT) void k_ise_mfma(const float* __restrict__ pts,
                                                   double* __restrict__ qpart, double* __restrict__ den)
 {
     constexpr int S = row_stride(DX, DY), SD = DX + DY;
-    constexpr int YS = IGW + 16;       // padded panel row (conflict-free B reads)
-    constexpr int SUB = 32;            // j per panel
-    constexpr int PSTEP = INT / IGW;   // panel rows filled per pass of the block
-    constexpr int YPT = SUB / PSTEP;   // panel values per thread
+    constexpr int GWW = IGW / 2;                          // columns per wave
+    constexpr int GT = GWW / 32;                          // column tiles of 32 per wave
+    constexpr int SUB = 32;                               // j per panel
+    // LDS rows padded by 32 floats: the two 32-lane halves of a wave, which
+    // read consecutive rows, start 128 bytes apart in the banks.
+    constexpr int YS = IGW + 32, XS = IPB + 32;
+    constexpr int YSTEP = INT / IGW, YPT = SUB / YSTEP;  // G panel rows: per pass, per thread
+    constexpr int XSTEP = INT / IPB, XPT = SUB / XSTEP;  // w panel rows: per pass, per thread
+    static_assert(GT == 4 && SUB % YSTEP == 0 && SUB % XSTEP == 0, "panel shape");
+    static_assert(SUB * XS >= 2 * INT, "the w panel holds the denominator reduction");
     __shared__ double tile[TILE * SD];
-    __shared__ float ykv[SUB * YS];
+    __shared__ __align__(16) float ykv[SUB * YS];  // [j][position]; position = half, then 4 n + t
+    __shared__ __align__(16) float xkv[SUB * XS];  // [j][row]
     __shared__ double xrow[IPB * DX];
     __shared__ double mrow[IPB];
     __shared__ double xcol[IGW * DX];
+    __shared__ double qrow[2 * IPB];  // [column half][row]: folded row sums
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i0 = blockIdx.x * IPB, l0 = blockIdx.y * IGW;
-    const int kr = lane >> 4;
 
     for (int v = tid; v < IPB; v += INT) {
         const int i = min(i0 + v, n - 1);
 #pragma unroll
         for (int k = 0; k < DX; ++k) xrow[v * DX + k] = (double)pts[(size_t)i * S + k] * a.sx[k];
         mrow[v] = mi[i];
+        qrow[v] = 0.0;
+        qrow[IPB + v] = 0.0;
     }
     for (int v = tid; v < IGW; v += INT) {
         const int l = min(l0 + v, n - 1);
@@ -177,27 +188,34 @@ __global__ __launch_bounds__(INT) void k_ise_mfma(const float* __restrict__ pts,
         for (int k = 0; k < DX; ++k) xcol[v * DX + k] = (double)pts[(size_t)l * S + k] * a.sx[k];
     }
 
-    // A role: row qi = i0 + 16 wave + lane % 16
-    const int qi = i0 + wave * 16 + (lane & 15);
-    const int qc = min(qi, n - 1);
+    // w panel role: row i0 + tid % IPB, panel rows tid / IPB + XSTEP r
+    const int wcol = tid % IPB, wrow = tid / IPB;
+    const int wi = i0 + wcol;
+    const int wc = min(wi, n - 1);
     double xo[DX];
 #pragma unroll
-    for (int k = 0; k < DX; ++k) xo[k] = (double)pts[(size_t)qc * S + k] * a.sx[k];
-    const double m_q = mi[qc];
-    // panel role: column tid % IGW, panel rows tid / IGW + PSTEP r
-    const int gcol = tid % IGW;
-    const int gl = min(l0 + gcol, n - 1);
+    for (int k = 0; k < DX; ++k) xo[k] = (double)pts[(size_t)wc * S + k] * a.sx[k];
+    const double m_q = mi[wc];
+    // G panel role: LDS position tid % IGW, panel rows tid / IGW + YSTEP r.
+    // Position h GWW + 4 n + t holds column h GWW + 32 t + n, so a lane of
+    // half h reads its four column tiles' values as one vector.
+    const int ypos = tid % IGW, yrow = tid / IGW;
+    const int yh = ypos / GWW, yr = ypos % GWW;
+    const int gl = min(l0 + yh * GWW + 32 * (yr % GT) + yr / GT, n - 1);
     double yo[DY];
 #pragma unroll
     for (int l = 0; l < DY; ++l) yo[l] = (double)pts[(size_t)gl * S + DX + l] * a.sg[l];
-    const int prow = tid / IGW;
+    // MFMA role: rows 32 (wave % 4) .., columns of half wave / 4
+    const int qg = wave & 3, half = wave >> 2;
+    const int kr = lane >> 5, m32 = lane & 31;
+    const float* arow = xkv + kr * XS + 32 * qg + m32;
+    const float* brow = ykv + kr * YS + half * GWW + GT * m32;
 
-    float tot[IGT][4];
+    float tot[GT][16];
 #pragma unroll
-    for (int t = 0; t < IGT; ++t)
+    for (int t = 0; t < GT; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) tot[t][r] = 0.f;
-    double qacc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int r = 0; r < 16; ++r) tot[t][r] = 0.f;
     double dtot = 0.0;
 
     const bool stager = tid < TILE;
@@ -217,84 +235,81 @@ __global__ __launch_bounds__(INT) void k_ise_mfma(const float* __restrict__ pts,
             __syncthreads();  // tile staged / previous panel read by every wave
 #pragma unroll
             for (int r = 0; r < YPT; ++r) {
-                const int p = prow + PSTEP * r;
+                const int p = yrow + YSTEP * r;
                 const float e = (float)sdist2_shifted<DY>(yo, tile + (s0 + p) * SD + DX, 0.0);
-                ykv[p * YS + gcol] = exp2_<float>(-e);
+                ykv[p * YS + ypos] = exp2_<float>(-e);
+            }
+            // w'(i, j), zero for j = i and for rows past cnt
+#pragma unroll
+            for (int r = 0; r < XPT; ++r) {
+                const int p = wrow + XSTEP * r;
+                const double d2 = sdist2_shifted<DX>(xo, tile + (s0 + p) * SD, m_q);
+                const float w = exp2_<float>(-((s0 + p < cnt && t0 + s0 + p != wi) ? (float)d2 : IEXCL));
+                dp += w;
+                xkv[p * XS + wcol] = w;
             }
             __syncthreads();
-            v4f acc[IGT];
-            // x-kernel value of a 4-point step; the next step's is formed
-            // before the current step's MFMAs are issued
-            auto weight = [&](int jj) {
-                const int j = t0 + jj;
-                const double d2 = sdist2_shifted<DX>(xo, tile + jj * SD, m_q);
-                const float xa = (jj < cnt && j != qi) ? (float)d2 : IEXCL;
-                return exp2_<float>(-xa);
-            };
-            float w = weight(s0 + kr);
+            v16f acc[GT];
 #pragma unroll
-            for (int s = 0; s < SUB; s += 4) {
-                const float wn = s + 4 < SUB ? weight(s0 + s + 4 + kr) : 0.f;
-                dp += w;
-                const float* brow = ykv + (s + kr) * YS + (lane & 15);
+            for (int s = 0; s < SUB; s += 2) {
+                const float av = arow[s * XS];
+                const v4f b = *(const v4f*)(brow + s * YS);
 #pragma unroll
-                for (int t = 0; t < IGT; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                        w, brow[16 * t], s == 0 ? v4f{0.f, 0.f, 0.f, 0.f} : acc[t], 0, 0, 0);
-                w = wn;
+                for (int t = 0; t < GT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b[t], s == 0 ? v16f{} : acc[t], 0, 0, 0);
             }
 #pragma unroll
-            for (int t = 0; t < IGT; ++t)
+            for (int t = 0; t < GT; ++t)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) tot[t][r] += acc[t][r];
+                for (int r = 0; r < 16; ++r) tot[t][r] += acc[t][r];
         }
         dtot += (double)dp;
         if (tt % ISEG == ISEG - 1 || tt + 1 == ntiles) {
-            // fold: qacc[r] += sum_t M(i_r, l_t) w'(i_r, l_t); result layout of
-            // the 16x16x4 MFMA: register r = row 4 (lane / 16) + r, column lane % 16
+            // fold: qrow[half][i] += sum over the wave's columns l of
+            // M(i, l) w'(i, l).  f32 32x32x2 result layout: register r of lane
+            // l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int ir = wave * 16 + 4 * kr + r;
+            for (int r = 0; r < 16; ++r) {
+                const int ir = 32 * qg + 8 * (r >> 2) + 4 * kr + (r & 3);
                 const int gi = i0 + ir;
                 double s = 0.0;
 #pragma unroll
-                for (int t = 0; t < IGT; ++t) {
-                    const int lc = 16 * t + (lane & 15);
+                for (int t = 0; t < GT; ++t) {
+                    const int lc = half * GWW + 32 * t + m32;
                     const int l = l0 + lc;
                     const double e = sdist2_shifted<DX>(xrow + ir * DX, xcol + lc * DX, mrow[ir]);
                     const float wil = (l < n && l != gi) ? exp2_<float>(-(float)e) : 0.f;
                     s = fma_((double)tot[t][r], (double)wil, s);
                     tot[t][r] = 0.f;
-                    // keep the 64 weight evaluations from being hoisted
-                    // together (register pressure)
-                    __builtin_amdgcn_sched_barrier(0);
                 }
-                qacc[r] += s;
+                // the row's 32 lanes of this half, in a fixed butterfly
+                s += __shfl_xor(s, 1, 64);
+                s += __shfl_xor(s, 2, 64);
+                s += __shfl_xor(s, 4, 64);
+                s += __shfl_xor(s, 8, 64);
+                s += __shfl_xor(s, 16, 64);
+                if (m32 == 0) qrow[half * IPB + ir] += s;  // one writer per entry
+                // keep the weight evaluations of different rows from being
+                // hoisted together (register pressure)
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
-    // row sums over the 16 lanes of a row group, in a fixed butterfly
+    // W'_i of row wi: the XSTEP row groups in a fixed order; Q'_i: the two
+    // column halves in order
+    double* red = (double*)xkv;
+    __syncthreads();
+    red[wrow * IPB + wcol] = dtot;
+    __syncthreads();
+    if (tid < IPB && i0 + tid < n) {
+        qpart[(size_t)blockIdx.y * n + i0 + tid] = qrow[tid] + qrow[IPB + tid];
+        if (blockIdx.y == 0) {
+            double dsum = red[tid];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        double v = qacc[r];
-        v += __shfl_xor(v, 1, 64);
-        v += __shfl_xor(v, 2, 64);
-        v += __shfl_xor(v, 4, 64);
-        v += __shfl_xor(v, 8, 64);
-        qacc[r] = v;
-    }
-    if ((lane & 15) == 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int gi = i0 + wave * 16 + 4 * kr + r;
-            if (gi < n) qpart[(size_t)blockIdx.y * n + gi] = qacc[r];
+            for (int r = 1; r < XSTEP; ++r) dsum += red[r * IPB + tid];
+            den[i0 + tid] = dsum;
         }
     }
-    // W'_i of row qi: the four j-groups of the A operand, in a fixed order
-    double dsum = dtot;
-    dsum += __shfl_xor(dsum, 16, 64);
-    dsum += __shfl_xor(dsum, 32, 64);
-    if (blockIdx.y == 0 && lane < 16 && qi < n) den[qi] = dsum;
 }
 
 // T1_i = c_G Q'_i / W'_i^2 (column blocks summed in order), T2_i = exp(l_i)
