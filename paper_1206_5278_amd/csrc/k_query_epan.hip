@@ -8,9 +8,11 @@
 // and f = 0 where no training x lies inside the query's window (eq. (1) is
 // 0/0 there).  Window values are formed in FP64 (the edge 1 - |u|^2 cancels)
 // on rows, queries and grid points scaled by 1/h when staged (one rounding
-// each, relative 2^-53), and rounded once to FP32; products run on v_mfma_f32_16x16x4f32 exactly as
-// in the Gaussian query kernel (k_query.hip): 8 waves x 16 queries per
-// block, y-kernel panels of 32 training points shared through LDS.
+// each, relative 2^-53), and rounded once to FP32; products run on
+// v_mfma_f32_16x16x4f32 with 8 waves x 16 queries per block, each wave
+// forming its own queries' window values, and y-kernel panels of 32 training
+// points shared through LDS (16 queries per wave keep the per-wave skip test
+// below fine-grained).
 //
 // Exact skipping: the training points are read in the model's spatial
 // (kd-leaf) order with their 256-row tile and 32-row panel boxes, and the
