@@ -252,8 +252,9 @@ def test_query_parity_and_normalisation():
 
 @pytest.mark.parametrize("dx,dy", DIMS)
 def test_query_all_shapes(dx, dy):
-    # FP32 models: matrix-core query kernel; k = 150 fills part of one
-    # 256-point grid block and q = 70 part of one 128-query block.
+    # FP32 models: matrix-core query kernel; k = 40, 100 and 150 use grid
+    # blocks of 64, 128 and 256 points (one, two and four 32-column tiles per
+    # wave), each part-filled, and q = 70 fills part of one 128-query block.
     say(f"case: query shape dx={dx} dy={dy}")
     v = workloads.gmm_general(400, dx + dy, seed=200 + dx * 10 + dy)
     x, y = v[:, :dx], v[:, dx:]
@@ -262,12 +263,13 @@ def test_query_all_shapes(dx, dy):
     h = list(np.linspace(0.7, 1.2, dx)) + list(np.linspace(0.3, 0.5, dy))
     rng = np.random.default_rng(dx * 7 + dy)
     xq = (xo[rng.choice(400, 70)] + 0.1 * rng.normal(size=(70, dx))).astype(np.float32).astype(np.float64)
-    yg = (yo[rng.choice(400, 150)] + 0.2 * rng.normal(size=(150, dy))).astype(np.float32).astype(np.float64)
-    f = m.query(P.to_dev(xq), P.to_dev(yg), h).cpu().numpy()
-    ref = oracle.density(xo, yo, h, xq, yg, nthreads=NT)
-    peak = ref.max(axis=1, keepdims=True)
-    err = np.abs(f - ref)
-    assert np.all(err <= 1e-5 * ref + 1e-7 * peak), float(np.max(err / (1e-5 * ref + 1e-7 * peak)))
+    for k in (40, 100, 150):
+        yg = (yo[rng.choice(400, k)] + 0.2 * rng.normal(size=(k, dy))).astype(np.float32).astype(np.float64)
+        f = m.query(P.to_dev(xq), P.to_dev(yg), h).cpu().numpy()
+        ref = oracle.density(xo, yo, h, xq, yg, nthreads=NT)
+        peak = ref.max(axis=1, keepdims=True)
+        err = np.abs(f - ref)
+        assert np.all(err <= 1e-5 * ref + 1e-7 * peak), (k, float(np.max(err / (1e-5 * ref + 1e-7 * peak))))
 
 
 def test_query_rows_independent_of_batch():
