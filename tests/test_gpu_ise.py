@@ -77,6 +77,23 @@ def test_cv_ise_parity_all_points(dx, dy, n):
     check_total(out, t1, t2)
 
 
+@pytest.mark.parametrize("dx,dy", [(dx, dy) for dx in (1, 2, 3, 4, 5, 6, 7, 8, 16) for dy in (1, 2)])
+def test_cv_ise_all_shapes(dx, dy):
+    # every compiled (dx, dy) instance: n = 290 gives 3 row blocks and 2
+    # column blocks (both ragged) and 2 tiles of j
+    say(f"case: cv_ise shape dx={dx} dy={dy} n=290")
+    v = workloads.gmm_general(290, dx + dy, seed=900 + 10 * dx + dy)
+    x, y = v[:, :dx], v[:, dx:]
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    h = list(np.linspace(0.6, 1.0, dx)) + list(np.linspace(0.3, 0.45, dy))
+    out, terms = m.cv_ise(h, terms=True)
+    out, terms = out.cpu().numpy(), terms.cpu().numpy()
+    t1, t2 = oracle.cv_ise(xo, yo, h, nthreads=NT)
+    check_terms(terms, t1, t2)
+    check_total(out, t1, t2)
+
+
 def test_cv_ise_several_fold_segments_sampled():
     # n = 4,700: 19 tiles of j, three FP64 folds (8 + 8 + 3 tiles); sampled
     # points against the oracle, the total against the returned terms
