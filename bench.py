@@ -9,7 +9,11 @@ step: N (N - 1).
 
 Prints one JSON line with the throughput, the roofline of the dominant
 kernel (timed live with HIP events on the stream it runs on) and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+CPU oracle timed on a bounded sample of the same workload.  Secondary
+figures, measured after the timed steps: the value-only pass, one density
+query batch on the same resident set (16,384 queries x 256 grid points,
+fraction of the FP32 matrix-core peak) and a short serving stream in both
+modes.
 """
 from __future__ import annotations
 
@@ -68,6 +72,7 @@ def parse():
                     help="arrival rate of the short serving stream (0: skip it)")
     ap.add_argument("--serve-duration", type=float, default=20.0,
                     help="seconds of arrivals of the short serving stream")
+    ap.add_argument("--no-query", action="store_true", help="skip the density-query secondary")
     ap.add_argument("--trace-steps", type=int, default=0,
                     help="after the timed steps, run this many untimed ascent steps from the "
                          "normal-reference start and report the whole trace of S")
@@ -125,6 +130,48 @@ def cpu_baseline(x64, y64, h, target_s):
                       f"(single-setting FP64 oracle, {threads} threads = the cores this process may "
                       f"use (nproc {nproc}, OMP_NUM_THREADS {os.environ.get('OMP_NUM_THREADS', 'unset')}), "
                       f"{dt:.2f} s wall)"}
+
+
+# Dense FP32 matrix-core peak of MI355X (FLOP/s, an FMA counted as two).
+MFMA_F32_PEAK = 157.3e12
+
+
+def query_secondary(model, x32, y32, h, q=16384, k=256, reps=3):
+    """Density queries (eq. 1) on the same resident training set: q query
+    points (training points plus N(0, 0.05^2) noise, seed 7) on a k-point y
+    grid, the batch of bench_query.py.  Mean HIP-event time of one call on
+    the stream it runs on, and its fraction of the FP32 matrix-core peak for
+    the 2 q n k FLOP of the contraction."""
+    import numpy as np
+    import torch
+
+    n, dx = x32.shape
+    rng = np.random.default_rng(7)
+    xq = (x32[rng.choice(n, q)] + 0.05 * rng.standard_normal((q, dx))).astype(np.float32)
+    ys = y32[:, 0].astype(np.float64)
+    yg = np.linspace(ys.min() - 3 * ys.std(), ys.max() + 3 * ys.std(), k).astype(np.float32)
+    dev = torch.device("cuda:0")
+    xqd = torch.from_numpy(xq).to(dev)
+    ygd = torch.from_numpy(yg.reshape(-1, 1)).to(dev)
+    stream = torch.cuda.current_stream()
+    model.query(xqd, ygd, h, stream=stream)  # warm-up (grows the model's scratch)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        model.query(xqd, ygd, h, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    t = float(np.mean(ms))
+    flops = 2.0 * q * n * k
+    return {"workload": f"{q} queries x {k}-point y grid against the same {n} points", "ms": t,
+            "queries_per_s": q / (t * 1e-3),
+            "roofline": {"bound": "mfma", "achieved": flops / (t * 1e-3) / 1e12, "peak": MFMA_F32_PEAK / 1e12,
+                         "unit": "TFLOP/s", "frac": flops / (t * 1e-3) / MFMA_F32_PEAK,
+                         "work": "2 q n k FLOP of the contraction; whole call timed"}}
 
 
 def serve_secondary(rate, duration):
@@ -265,6 +312,13 @@ def main():
                      "wall_s": time.perf_counter() - t0}
         print(f"bench: ascent trace of {args.trace_steps} steps done", file=sys.stderr, flush=True)
 
+    query = None
+    if not args.no_query:
+        try:
+            query = query_secondary(model, x32, y32, h0.tolist())
+        except Exception as e:  # the headline line is printed regardless
+            query = {"error": str(e)}
+
     serve = None
     if args.serve_rate > 0:
         serve = serve_secondary(args.serve_rate, args.serve_duration)
@@ -286,7 +340,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
         "trace_first_last": [trace[0], trace[-1]] if trace else None,
         "secondary": {"value_only_ms": vo_ms, "value_only_pair_evals_per_s": pairs / (vo_ms * 1e-3),
-                      "serve": serve},
+                      "query": query, "serve": serve},
     }
     if trace_run is not None:
         out["ascent"] = trace_run
