@@ -53,6 +53,54 @@ def test_photoz_500k_sampled_points_value_and_grad_call(photoz_full):
         assert np.all(np.isfinite(grad.cpu().numpy()))
 
 
+def test_photoz_500k_query_batch_sampled_rows(photoz_full):
+    # The density-query batch the benchmarks time (bench_query.py and
+    # bench.py's secondary figure): 16,384 queries on a 256-point y grid
+    # against all 500,000 points, in one call (8 slices of 2,048 queries).
+    # 8 sampled rows against the oracle (each over all points), and rows
+    # alone equal to the same rows in the batch.
+    print("case: photoz n=500000 query batch q=16384 k=256, 8 sampled rows", flush=True)
+    xo, yo, m = photoz_full
+    n, dx = xo.shape
+    h = cde().normal_reference_bandwidths(xo, yo).tolist()
+    rng = np.random.default_rng(7)
+    xq = (xo[rng.choice(n, 16384)].astype(np.float32)
+          + 0.05 * rng.standard_normal((16384, dx))).astype(np.float32)
+    ys = yo[:, 0]
+    yg = np.linspace(ys.min() - 3 * ys.std(), ys.max() + 3 * ys.std(), 256).astype(np.float32)
+    xqd, ygd = P.to_dev(xq, torch.float32), P.to_dev(yg.reshape(-1, 1), torch.float32)
+    f = m.query(xqd, ygd, h).cpu().numpy()
+    assert np.all(np.isfinite(f)) and np.all(f >= 0)
+    rows = np.sort(np.random.default_rng(5).choice(16384, 8, replace=False))
+    ref = oracle.density(xo, yo, h, xq[rows].astype(np.float64), yg.astype(np.float64), nthreads=NT)
+    peak = ref.max(axis=1, keepdims=True)
+    err = np.abs(f[rows] - ref)
+    assert np.all(err <= 1e-5 * ref + 1e-7 * peak), float(np.max(err / (1e-5 * ref + 1e-7 * peak)))
+    part = m.query(xqd[rows[:2].tolist()].contiguous(), ygd, h).cpu().numpy()
+    assert np.array_equal(part, f[rows[:2]])
+
+
+def test_photoz_20k_cv_ise_sampled_points():
+    # The cross-validated ISE in the configuration bench_ise.py times
+    # (photoz N = 20,000, normal-reference bandwidths): T1 and T2 of 8
+    # sampled points against the oracle, each a double sum over all points,
+    # and the means against the returned terms.
+    print("case: photoz n=20000 cv_ise, 8 sampled points", flush=True)
+    x, y = workloads.photoz(20_000, seed=0)
+    xo, yo, xd, yd = P.f32_pair(x, y)
+    m = cde().Model(xd, yd)
+    h = cde().normal_reference_bandwidths(xo, yo).tolist()
+    out, terms = m.cv_ise(h, terms=True)
+    out, terms = out.cpu().numpy(), terms.cpu().numpy()
+    idx = np.sort(np.random.default_rng(1).choice(20_000, 8, replace=False))
+    t1, t2 = oracle.cv_ise(xo, yo, h, idx=idx, nthreads=NT)
+    assert np.all(np.abs(terms[idx, 0] - t1) <= 1e-5 * t1)
+    assert np.all(np.abs(terms[idx, 1] - t2) <= 1e-5 * np.maximum(1.0, np.abs(np.log(t2))) * t2)
+    np.testing.assert_allclose(out[1], terms[:, 0].mean(), rtol=1e-12)
+    np.testing.assert_allclose(out[2], terms[:, 1].mean(), rtol=1e-12)
+    m.close()
+
+
 def test_photoz_5k_subsample_gradient_vs_oracle_and_fd():
     print("case: photoz 5k subsample gradient", flush=True)
     x, y = workloads.photoz(500_000, seed=0)
