@@ -80,6 +80,33 @@ def test_photoz_500k_query_batch_sampled_rows(photoz_full):
     assert np.array_equal(part, f[rows[:2]])
 
 
+def test_photoz_500k_epanechnikov_sampled_points(photoz_full):
+    # The Epanechnikov LOO pass in the configuration bench_epan.py times
+    # (photoz N = 500,000, h = f sd per dimension, exact tile skipping over
+    # the model's spatial order): 32 sampled points per bandwidth against the
+    # oracle over all other points, at 0.2 sd, where some points have no
+    # neighbour in their window (l_i = -inf, so the total is -inf), and at
+    # 32 sd, the smallest multiple with a finite total.
+    print("case: photoz n=500000 Epanechnikov LOO, 32 sampled points at 0.2 and 32 sd", flush=True)
+    xo, yo, m = photoz_full
+    sd = np.std(np.concatenate([xo, yo], axis=1), axis=0)
+    idx = np.sort(np.random.default_rng(2).choice(len(xo), 32, replace=False))
+    for f in (0.2, 32.0):
+        h = list(f * sd)
+        tot, pp = m.loo_list([h], per_point=True, kernel="epanechnikov")
+        got = pp.cpu().numpy()[0]
+        ref = oracle.loo_epan(xo, yo, h, "cond", idx=idx, nthreads=NT)
+        fin = np.isfinite(ref)
+        assert np.array_equal(np.isfinite(got[idx]), fin), f
+        assert np.all(got[idx][~fin] == ref[~fin])
+        if fin.any():
+            P.assert_points(got[idx][fin], ref[fin])
+        if np.isfinite(got).all():
+            assert abs(float(tot[0]) - float(np.sum(got))) <= 1e-9 * float(np.sum(np.abs(got)))
+        else:
+            assert float(tot[0]) == -np.inf
+
+
 def test_photoz_20k_cv_ise_sampled_points():
     # The cross-validated ISE in the configuration bench_ise.py times
     # (photoz N = 20,000, normal-reference bandwidths): T1 and T2 of 8
