@@ -1,7 +1,9 @@
 """CPU tests of the serving scheduler with a fake executor and a fake clock:
 admission by memory footprint and slots, fused query launches, grouped job
 ticks (small jobs whole, large jobs in arrival order in point ranges), the
-one-request-per-launch baseline, and failure isolation."""
+one-request-per-launch baseline, failure isolation, and the scheduler's
+invariants checked at every tick over seeded random streams (a scheduler
+that skips the memory test or overfills a slot fails them)."""
 import numpy as np
 
 import pytest
@@ -266,3 +268,70 @@ def test_queries_arriving_during_a_batch_join_the_next_batch():
     assert batches[0] == [0]
     assert batches[1] == [1, 2, 3, 4]
     assert batches[2] == [5]
+
+
+def _random_stream(seed):
+    """Seeded mixed stream: jobs of log-uniform size (small and large, some
+    with a failing launch), queries of 1..40 rows on 3 sets, arrivals over
+    5 fake seconds."""
+    rng = np.random.default_rng(seed)
+    reqs, sizes = [], {}
+    for rid in range(int(rng.integers(20, 60))):
+        t = float(rng.uniform(0.0, 5.0))
+        if rng.random() < 0.4:
+            reqs.append(ServeRequest(rid, "job", t))
+            sizes[rid] = int(np.exp(rng.uniform(np.log(300), np.log(300_000))))
+        else:
+            reqs.append(ServeRequest(rid, "query", t, set_id=int(rng.integers(0, 3)),
+                                     xq=np.zeros((int(rng.integers(1, 41)), 1), np.float32)))
+    return reqs, sizes
+
+
+@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("batched", [True, False])
+def test_random_streams_keep_the_scheduler_invariants(seed, batched):
+    # At every tick: memory in use within the budget, slots within the limit
+    # (batched) or one request in service (plain).  At the end: every request
+    # finished exactly once, failures only for the failing job, nothing held,
+    # each kind admitted in arrival order, and every job's ranges covering
+    # [0, n) in order.
+    reqs, sizes = _random_stream(seed)
+    jobs = [r.rid for r in reqs if r.kind == "job"]
+    fail = jobs[len(jobs) // 2] if jobs else None
+    clock = FakeClock()
+    ex = FakeExecutor(clock, latency=0.05, fail_rid=fail, sizes=sizes, rate=2e12)
+    ex.round = 1024
+    s = Scheduler(ex, hbm_budget=230, max_active=3, batched=batched, clock=clock, tick_pairs=5e10,
+                  small_job_points=4096)
+    s.submit_all(reqs)
+    s.t0 = clock()
+    for _ in range(200_000):
+        more = s.tick()
+        assert 0 <= s.used <= s.budget
+        if batched:
+            assert all(0 <= v <= 3 for v in s.active_kind.values())
+        else:
+            assert s.active <= 1 and len(s.inflight) <= 1
+        if not more:
+            break
+        clock.t += 0.01
+    else:
+        raise AssertionError("scheduler did not finish")
+    assert sorted(r.rid for r in s.completed) == sorted(r.rid for r in reqs)
+    assert not s.rejected
+    assert {r.rid for r in s.completed if r.error} == ({fail} if fail is not None else set())
+    assert all(r.result == r.rid for r in s.completed if r.error is None)
+    assert s.used == 0 and s.active == 0 and s.active_kind == {"job": 0, "query": 0}
+    rep = s.report(1.0)
+    assert rep["unfinished"] == 0 and rep["completed"] + rep["failed"] == len(reqs)
+    for kind in ("job", "query"):
+        ks = sorted((r for r in reqs if r.kind == kind), key=lambda r: (r.t_arrive, r.rid))
+        admits = [r.t_admit for r in ks]
+        assert admits == sorted(admits), kind
+    if batched:
+        for rid, n in sizes.items():
+            if rid == fail:
+                continue
+            rs = ex.ranges[rid]
+            assert rs[0][0] == 0 and rs[-1][1] == n
+            assert all(a[1] == b[0] for a, b in zip(rs, rs[1:]))
