@@ -85,7 +85,7 @@ def parse():
 def host_cpu():
     """(threads the oracle may use, nproc, CPU model): every core this
     process may run on, capped by OMP_NUM_THREADS when the host sets it (a
-    GPU machine gives each GPU a share of its cores that way)."""
+    multi-GPU host can give each GPU a share of its cores that way)."""
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
