@@ -216,7 +216,7 @@ def serve_secondary(rate, duration):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+        print("bench.py: the library runs on one GPU only; multi-GPU runs are not supported "
               "(the path shards by point ranges with one all-reduce of the totals; not built)",
               file=sys.stderr)
         sys.exit(2)

@@ -87,7 +87,7 @@ typedef enum {
     CDE_EINVAL = 1,       /* bad argument: null pointer, n < 2, h <= 0 or non-finite, ... */
     CDE_ENOMEM = 2,       /* device allocation failed */
     CDE_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed */
-    CDE_EUNSUPPORTED = 4  /* valid but outside this build: dx > 64, dy > 4, ... */
+    CDE_EUNSUPPORTED = 4  /* valid but outside what the library supports: dx > 64, dy > 4, ... */
 } cde_status;
 
 typedef enum {
